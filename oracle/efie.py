@@ -111,7 +111,7 @@ def pair_blocks(k, geo: Geometry, To, Ts, deriv=False):
         n = geo.normal[Ts[idx]]
         d = np.einsum("qpx,qx->qp", ro[idx] - tvs[:, None, 0, :], n)
         # int (r' - v'_b)/R = int (r' - r)/R + (r - v'_b) int 1/R, and r' - r = (rho' - rho) - d n
-        rel = Iv - d[:, :, None] * n[:, None, :]              # (Q, 7, 3)
+        rel = Iv - (d * I1)[:, :, None] * n[:, None, :]       # (Q, 7, 3)
         inner = rel[:, :, None, :] + (ro[idx][:, :, None, :] - tvs[:, None, :, :]) * I1[:, :, None, None]
         wq = wo[idx]
         S0[idx] += np.einsum("qp,qp->q", wq, I1)
