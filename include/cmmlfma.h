@@ -1,0 +1,149 @@
+/*
+ * cmmlfma.h -- C ABI of the MI355X (gfx950) MLFMA library for characteristic-mode
+ * analysis of PEC surfaces (Dai, Wu, Meng, Chew, Sha, "Multilevel Fast Multipole
+ * Algorithm for Characteristic Mode Analysis").
+ *
+ * The library builds, from a triangle mesh and a wavenumber k, the RWG
+ * discretisation (eq. (4)), an octree with near and far interaction lists
+ * (section III-C), and applies to one or more complex vectors
+ *   Z = R + iX  (eqs. (5), (7), (11)),   R  (eqs. (19)-(22)),   X (eqs. (15)-(18)),
+ *   Z^H,  and dZ/dk,
+ * plus the sparse approximate inverse (SAI) preconditioner of the near-field
+ * matrix (section IV).  These are the products an implicitly restarted Arnoldi
+ * solve of  Z^-1 R J = J / (1 + i lambda)  (eq. (24)) needs at every step.
+ *
+ * Conventions (all entry points):
+ *  - Sign convention.  The public matrix is
+ *        Z_mn = ik eta <f_m, [I - grad grad'/k^2] exp(-ikR)/R, f_n>,
+ *    i.e. -conj of eq. (5) written with eq. (3), so that R = Re Z is positive
+ *    semidefinite and X J = lambda R J has the characteristic values of Table II.
+ *  - Unknown order.  RWG n is the n-th interior edge in increasing
+ *    (smaller vertex, larger vertex) order; T+ is the lower-numbered triangle
+ *    (cm_rwg_table).  f = l/(2A+) (r - p+) on T+, l/(2A-) (p- - r) on T-.
+ *  - Vectors.  x and y are DEVICE pointers to interleaved complex numbers,
+ *    row-major N x ncols with row stride ld >= ncols (elements): entry (i, c)
+ *    at x[i*ld + c].  CM_C64 = complex float (far field in FP32, near field
+ *    stored and applied in FP64), CM_C128 = complex double (all FP64).
+ *    The caller owns x and y; they must not alias.  y is overwritten.
+ *  - Streams.  cm_apply / cm_sai_apply enqueue work on the given HIP stream
+ *    (NULL = default stream) and return without synchronising.  cm_create and
+ *    cm_sai_build block until their device work is done.
+ *  - Errors.  Every call returns a cm_status; no exception crosses the ABI.
+ *    cm_last_error() returns a thread-local message for the last failure.
+ *  - Threads.  One handle must not be used by two host threads at once, and
+ *    applies that overlap on different streams with the same handle race on
+ *    its workspace.
+ */
+#ifndef CMMLFMA_H
+#define CMMLFMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cm_handle cm_handle;          /* opaque, library-owned */
+
+typedef enum {
+  CM_OK = 0,
+  CM_E_BADARG = -1,       /* null pointer, size out of range, bad enum          */
+  CM_E_MESH = -2,         /* non-manifold edge, zero-area triangle, NaN vertex,
+                             or mesh too coarse for the leaf boxes               */
+  CM_E_OOM = -3,          /* host or device allocation failed / size overflow   */
+  CM_E_HIP = -4,          /* a HIP runtime call failed                          */
+  CM_E_NOT_BUILT = -5,    /* handle has no device data (host-only plan) or the
+                             SAI has not been built                             */
+  CM_E_NUMERIC = -6,      /* non-finite translator or table entry               */
+  CM_E_UNSUPPORTED = -7   /* option combination not implemented                 */
+} cm_status;
+
+typedef enum {
+  CM_OP_Z = 0,      /* y = Z x                                                 */
+  CM_OP_R = 1,      /* y = R x   (sin kernel; near field = own leaf box only,
+                                  neighbouring leaf boxes translated, eq. (22)) */
+  CM_OP_X = 2,      /* y = X x   (cos kernel, eq. (18))                        */
+  CM_OP_ZH = 3,     /* y = Z^H x = conj(Z conj(x))  (Z = Z^T)                  */
+  CM_OP_DZDK = 4    /* y = (dZ/dk) x, tree and sampling frozen (needs
+                       CM_FLAG_DERIV at create)                                */
+} cm_op;
+
+typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
+
+/* option flags */
+#define CM_FLAG_HOST_ONLY 1u   /* build the host plan only (no device work);
+                                  cm_apply returns CM_E_NOT_BUILT            */
+#define CM_FLAG_DERIV     2u   /* also build dZ_near/dk and derivative tables */
+#define CM_FLAG_CHECK     4u   /* brute-force check that every leaf-box pair is
+                                  covered exactly once (O(boxes^2))          */
+
+typedef struct {
+  int32_t nlv;       /* number of octree levels including level 0 (>= 3)        */
+  double d0;         /* digits of accuracy in the truncation rule, eq. (30)     */
+  int32_t interp_p;  /* local Lagrange interpolation points per direction (even,
+                        2..12)                                                  */
+  double eta;        /* wave impedance; <= 0 selects 376.730313668 ohm          */
+  uint32_t flags;    /* CM_FLAG_*                                               */
+  int32_t max_cols;  /* largest ncols any apply will use (1..64)                */
+} cm_opts;
+
+/* Fill opts with defaults: nlv = 0 (must be set), d0 = 3, interp_p = 6,
+   eta = 376.730313668, flags = 0, max_cols = 32. */
+void cm_default_opts(cm_opts* o);
+
+/* Build a handle.  xyz: host, n_vert x 3 float64 (wavelength units are the
+   caller's; k is in the same units).  tri: host, n_tri x 3 int32 vertex
+   indices.  k: host array of n_k wavenumbers (n_k = 1 in this version).
+   Blocks until all device set-up (near-field fill with singularity
+   extraction, leaf radiation patterns, translators) is complete.  The caller
+   keeps ownership of xyz/tri/k (copied).  On failure *out is NULL. */
+cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                    const double* k, int32_t n_k, const cm_opts* o, void* hip_stream,
+                    cm_handle** out);
+
+/* Release all host and device memory of the handle (NULL is a no-op). */
+void cm_destroy(cm_handle* h);
+
+/* Number of RWG unknowns N. */
+cm_status cm_num_unknowns(const cm_handle* h, int64_t* n);
+
+/* RWG table in the library's unknown order: edge_v (N x 2: smaller, larger
+   vertex), tri_pm (N x 2: T+, T-).  Host arrays, caller-allocated. */
+cm_status cm_rwg_table(const cm_handle* h, int32_t* edge_v, int32_t* tri_pm);
+
+/* y = op(x) on ncols columns (1 <= ncols <= max_cols).  k_index must be NULL
+   (all columns at k[0]).  Asynchronous on hip_stream. */
+cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols,
+                   const int32_t* k_index, cm_dtype dt, void* hip_stream);
+
+/* Build the SAI preconditioner P minimising ||I - Z_near P||_F column by
+   column over a prescribed pattern (section IV): entries of Z_near with
+   |z_ij| < eps1 |z_jj| are dropped, column j's pattern is
+   {i : |z_ij| >= eps2 |z_jj|}, and entries of the solution with
+   |p_ij| < eps3 max_i |p_ij| are dropped afterwards.  Blocks. */
+cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3);
+
+/* y = P x (same vector conventions as cm_apply).  Asynchronous. */
+cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols,
+                       cm_dtype dt, void* hip_stream);
+
+/* Copy the near-field matrix to host (public unknown order, CSR by row):
+   row_ptr (N+1, int64), col (nnz, int32), val (nnz complex128 interleaved).
+   Pass NULLs to query *nnz only.  which = 0: Z_near, 1: dZ_near/dk,
+   2: the SAI matrix P. */
+cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_t* row_ptr,
+                         int32_t* col, double* val);
+
+/* JSON description of the plan (levels, boxes, L, K, list sizes, nnz) and the
+   algorithmic bytes / flops per apply stage, NUL-terminated into buf.
+   Returns CM_E_BADARG if buf_len is too small (needed size in *needed). */
+cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* needed);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* cm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMMLFMA_H */

@@ -1,0 +1,427 @@
+// C ABI (include/cmmlfma.h): handle life cycle, device set-up, argument checks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "../../include/cmmlfma.h"
+#include "cm_device.h"
+
+namespace cm {
+void set_quadrature_constants();
+void launch_near_fill(double k, double eta, const Dev& d, int nbox, hipStream_t s);
+void launch_leaf_patterns(double k, const Dev& d, hipStream_t s);
+
+static void chk(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      throw Error(-3, std::string(what) + ": out of device memory");
+    throw Error(-4, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+static void* dmalloc(Dev& d, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  chk(hipMalloc(&p, bytes), "hipMalloc");
+  d.allocs.push_back(p);
+  return p;
+}
+
+template <typename T>
+static T* upload(Dev& d, const std::vector<T>& v, hipStream_t s) {
+  T* p = (T*)dmalloc(d, v.size() * sizeof(T));
+  if (!v.empty()) chk(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  return p;
+}
+
+template <typename R>
+static void* upload_complex(Dev& d, const std::vector<cplx>& v, hipStream_t s) {
+  std::vector<R> h(2 * v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    h[2 * i] = (R)v[i].real();
+    h[2 * i + 1] = (R)v[i].imag();
+  }
+  return upload(d, h, s);
+}
+
+template <typename R>
+static std::vector<R> cast(const std::vector<double>& v) {
+  return std::vector<R>(v.begin(), v.end());
+}
+
+template <typename R>
+static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<int32_t>& octant_dummy,
+                       std::vector<int32_t*>& lists, hipStream_t s) {
+  (void)octant_dummy;
+  const int lf = P.lf;
+  pd.lev.assign(lf + 1, LevelD<R>());
+  for (int l = 2; l <= lf; ++l) {
+    const Level& Lv = P.lev[l];
+    LevelD<R>& D = pd.lev[l];
+    D.nbox = Lv.nbox;
+    D.K = Lv.K;
+    D.nt = Lv.nt;
+    D.np = Lv.np;
+    // index arrays are shared between the precisions (uploaded once in `lists`)
+    D.far_ptr = lists[8 * l + 0];
+    D.far_src = lists[8 * l + 1];
+    D.far_off = lists[8 * l + 2];
+    D.farR_ptr = lists[8 * l + 3];
+    D.farR_src = lists[8 * l + 4];
+    D.farR_off = lists[8 * l + 5];
+    D.child_ptr = lists[8 * l + 6];
+    D.parent = lists[8 * l + 7];
+    D.TZ = upload_complex<R>(d, P.TZ[l], s);
+    D.TR = upload_complex<R>(d, P.TR[l], s);
+    D.TX = upload_complex<R>(d, P.TX[l], s);
+    if (!P.dTZ[l].empty()) D.dTZ = upload_complex<R>(d, P.dTZ[l], s);
+    if (l < lf) {
+      const Interp& I = P.ip[l];
+      D.p = I.p;
+      D.ntc = I.ntc;
+      D.npc = I.npc;
+      D.th_idx = upload(d, I.th_idx, s);
+      D.th_ref = upload(d, I.th_ref, s);
+      D.th_w = upload(d, cast<R>(I.th_w), s);
+      D.ph_idx = upload(d, I.ph_idx, s);
+      D.ph_w = upload(d, cast<R>(I.ph_w), s);
+      D.tht_ptr = upload(d, I.tht_ptr, s);
+      D.tht_idx = upload(d, I.tht_idx, s);
+      D.tht_ref = upload(d, I.tht_ref, s);
+      D.tht_w = upload(d, cast<R>(I.tht_w), s);
+      D.pht_ptr = upload(d, I.pht_ptr, s);
+      D.pht_idx = upload(d, I.pht_idx, s);
+      D.pht_w = upload(d, cast<R>(I.pht_w), s);
+      D.shift = upload_complex<R>(d, P.shift[l], s);
+    }
+  }
+  for (int l = 2; l <= lf; ++l) pd.lev[l].octant = reinterpret_cast<int8_t*>(lists[8 * (lf + 1) + l]);
+  const int K = P.lev[lf].K;
+  std::vector<R> qwc(K);
+  const double c0 = P.k * P.k * P.opt.eta / (4.0 * M_PI);
+  for (int q = 0; q < K; ++q) qwc[q] = (R)(c0 * P.qw[lf][q]);
+  pd.qwc = upload(d, qwc, s);
+  const size_t vb = (size_t)d.N * 2 * K * 2 * sizeof(R);
+  pd.V = dmalloc(d, vb);
+  if (P.opt.flags & CM_FLAG_DERIV) pd.dV = dmalloc(d, vb);
+}
+
+void dev_build(Dev& d, const Plan& P, hipStream_t s) {
+  chk(hipGetDevice(&d.device), "hipGetDevice");
+  set_quadrature_constants();
+  d.N = P.rwg.N;
+  d.nnz = P.nnz;
+  d.lf = P.lf;
+  d.nleaf = P.lev[P.lf].nbox;
+  d.Kleaf = P.lev[P.lf].K;
+  d.max_cols = P.opt.max_cols;
+  const int lf = P.lf;
+  // triangles
+  std::vector<TriD> tri(P.nt);
+  for (int64_t t = 0; t < P.nt; ++t) {
+    for (int v = 0; v < 3; ++v)
+      for (int c = 0; c < 3; ++c) tri[t].v[3 * v + c] = P.V[3 * P.F[3 * t + v] + c];
+    for (int c = 0; c < 3; ++c) {
+      tri[t].n[c] = P.normal[3 * t + c];
+      tri[t].c[c] = P.cent[3 * t + c];
+    }
+    tri[t].area = P.area[t];
+    tri[t].hmax = P.hmax[t];
+  }
+  d.tri = upload(d, tri, s);
+  std::vector<RwgD> rw(d.N);
+  for (int64_t i = 0; i < d.N; ++i) {
+    int64_t n = P.perm[i];
+    rw[i].t[0] = P.rwg.tri[2 * n];
+    rw[i].t[1] = P.rwg.tri[2 * n + 1];
+    rw[i].a[0] = P.rwg.loc[2 * n];
+    rw[i].a[1] = P.rwg.loc[2 * n + 1];
+    rw[i].len = P.rwg.len[n];
+  }
+  d.rwg = upload(d, rw, s);
+  d.perm = upload(d, P.perm, s);
+  d.box_of = upload(d, P.box_of, s);
+  d.box_start = upload(d, P.box_start, s);
+  d.bcol_ptr = upload(d, P.bcol_ptr, s);
+  d.bcol = upload(d, P.bcol, s);
+  d.self_off = upload(d, P.self_off, s);
+  d.row_ptr = upload(d, P.row_ptr, s);
+  {
+    const Level& Lf = P.lev[lf];
+    std::vector<double> cen(3 * (size_t)Lf.nbox);
+    for (int b = 0; b < Lf.nbox; ++b)
+      for (int c = 0; c < 3; ++c) cen[3 * b + c] = P.origin[c] + (Lf.ijk[3 * b + c] + 0.5) * Lf.a;
+    d.leaf_center = upload(d, cen, s);
+    d.leaf_dirs = upload(d, P.dirs[lf], s);
+  }
+  // index lists shared by both precisions
+  std::vector<int32_t*> lists(8 * (lf + 1) + lf + 1, nullptr);
+  for (int l = 2; l <= lf; ++l) {
+    const Level& Lv = P.lev[l];
+    lists[8 * l + 0] = upload(d, Lv.far_ptr, s);
+    lists[8 * l + 1] = upload(d, Lv.far_src, s);
+    lists[8 * l + 2] = upload(d, Lv.far_off, s);
+    lists[8 * l + 3] = upload(d, Lv.farR_ptr, s);
+    lists[8 * l + 4] = upload(d, Lv.farR_src, s);
+    lists[8 * l + 5] = upload(d, Lv.farR_off, s);
+    lists[8 * l + 6] = upload(d, Lv.child_ptr, s);
+    lists[8 * l + 7] = upload(d, Lv.parent, s);
+    std::vector<int8_t> oc(Lv.nbox);
+    for (int b = 0; b < Lv.nbox; ++b) oc[b] = (int8_t)(Lv.code[b] & 7);
+    lists[8 * (lf + 1) + l] = reinterpret_cast<int32_t*>(upload(d, oc, s));
+  }
+  std::vector<int32_t> dummy;
+  build_prec<float>(d, P, d.f32, dummy, lists, s);
+  build_prec<double>(d, P, d.f64, dummy, lists, s);
+  // near field and leaf patterns (FP64 on the device)
+  const bool deriv = (P.opt.flags & CM_FLAG_DERIV) != 0;
+  d.Zn = (double2*)dmalloc(d, (size_t)d.nnz * sizeof(double2));
+  if (deriv) d.dZn = (double2*)dmalloc(d, (size_t)d.nnz * sizeof(double2));
+  launch_leaf_patterns(P.k, d, s);
+  chk(hipGetLastError(), "leaf pattern launch");
+  launch_near_fill(P.k, P.opt.eta, d, d.nleaf, s);
+  chk(hipGetLastError(), "near fill launch");
+  // workspace
+  d.S.assign(lf + 1, nullptr);
+  d.G.assign(lf + 1, nullptr);
+  for (int l = 2; l <= lf; ++l) {
+    size_t b = (size_t)P.lev[l].nbox * 2 * P.lev[l].K * d.max_cols * sizeof(double2);
+    d.S[l] = dmalloc(d, b);
+    d.G[l] = dmalloc(d, b);
+  }
+  d.xi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
+  d.yi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
+  chk(hipStreamSynchronize(s), "device set-up");
+}
+
+void dev_free(Dev& d) {
+  for (void* p : d.allocs) (void)hipFree(p);
+  d.allocs.clear();
+}
+
+void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipStream_t s);
+
+}  // namespace cm
+
+struct cm_handle {
+  cm::Plan plan;
+  cm::Dev dev;
+  bool has_dev = false;
+};
+
+static thread_local std::string g_err;
+
+static cm_status fail(int code, const std::string& msg) {
+  g_err = msg;
+  return (cm_status)code;
+}
+
+#define CM_TRY(...)                                                    \
+  try {                                                                \
+    __VA_ARGS__                                                        \
+  } catch (const cm::Error& e) {                                       \
+    return fail(e.code, e.what());                                     \
+  } catch (const std::bad_alloc&) {                                    \
+    return fail(CM_E_OOM, "host allocation failed");                   \
+  } catch (const std::exception& e) {                                  \
+    return fail(CM_E_BADARG, e.what());                                \
+  }
+
+extern "C" {
+
+void cm_default_opts(cm_opts* o) {
+  if (!o) return;
+  o->nlv = 0;
+  o->d0 = 3.0;
+  o->interp_p = 6;
+  o->eta = 376.730313668;
+  o->flags = 0;
+  o->max_cols = 32;
+}
+
+cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri, const double* k,
+                    int32_t n_k, const cm_opts* o, void* hip_stream, cm_handle** out) {
+  g_err.clear();
+  if (out) *out = nullptr;
+  if (!xyz || !tri || !k || !o || !out) return fail(CM_E_BADARG, "null argument");
+  if (n_k != 1) return fail(CM_E_UNSUPPORTED, "exactly one wavenumber per handle is supported");
+  if (n_vert < 3 || n_tri < 2 || n_vert > (1LL << 31) - 1 || n_tri > (1LL << 31) - 1)
+    return fail(CM_E_BADARG, "mesh size out of range");
+  CM_TRY({
+    std::unique_ptr<cm_handle> h(new cm_handle());
+    cm::Opts op;
+    op.nlv = o->nlv;
+    op.d0 = o->d0;
+    op.p = o->interp_p;
+    op.eta = (o->eta > 0) ? o->eta : 376.730313668;
+    op.flags = o->flags;
+    op.max_cols = o->max_cols;
+    h->plan.build(xyz, n_vert, tri, n_tri, k[0], op);
+    if (!(o->flags & CM_FLAG_HOST_ONLY)) {
+      try {
+        cm::dev_build(h->dev, h->plan, (hipStream_t)hip_stream);
+      } catch (...) {
+        cm::dev_free(h->dev);
+        throw;
+      }
+      h->has_dev = true;
+    }
+    *out = h.release();
+    return CM_OK;
+  })
+}
+
+void cm_destroy(cm_handle* h) {
+  if (!h) return;
+  cm::dev_free(h->dev);
+  delete h;
+}
+
+cm_status cm_num_unknowns(const cm_handle* h, int64_t* n) {
+  if (!h || !n) return fail(CM_E_BADARG, "null argument");
+  *n = h->plan.rwg.N;
+  return CM_OK;
+}
+
+cm_status cm_rwg_table(const cm_handle* h, int32_t* edge_v, int32_t* tri_pm) {
+  if (!h || !edge_v || !tri_pm) return fail(CM_E_BADARG, "null argument");
+  const auto& r = h->plan.rwg;
+  std::memcpy(edge_v, r.edge.data(), r.edge.size() * sizeof(int32_t));
+  std::memcpy(tri_pm, r.tri.data(), r.tri.size() * sizeof(int32_t));
+  return CM_OK;
+}
+
+static cm_status check_vec_args(const cm_handle* h, const void* x, const void* y, int64_t ld, int32_t ncols,
+                                cm_dtype dt) {
+  if (!h || !x || !y) return fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (ncols < 1 || ncols > h->dev.max_cols) return fail(CM_E_BADARG, "ncols out of range [1, max_cols]");
+  if (ld < ncols) return fail(CM_E_BADARG, "ld < ncols");
+  if (dt != CM_C64 && dt != CM_C128) return fail(CM_E_BADARG, "bad dtype");
+  if (x == y) return fail(CM_E_BADARG, "x and y must not alias");
+  return CM_OK;
+}
+
+cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols,
+                   const int32_t* k_index, cm_dtype dt, void* hip_stream) {
+  g_err.clear();
+  cm_status st = check_vec_args(h, x, y, ld, ncols, dt);
+  if (st != CM_OK) return st;
+  if ((int)op < 0 || (int)op > 4) return fail(CM_E_BADARG, "bad op");
+  if (k_index) return fail(CM_E_UNSUPPORTED, "per-column wavenumbers are not supported by this build");
+  if (op == CM_OP_DZDK && !(h->plan.opt.flags & CM_FLAG_DERIV))
+    return fail(CM_E_NOT_BUILT, "dZ/dk needs CM_FLAG_DERIV at create");
+  CM_TRY({
+    cm::dev_apply(h->dev, h->plan, (int)op, x, y, ld, ncols, dt == CM_C128, (hipStream_t)hip_stream);
+    return CM_OK;
+  })
+}
+
+cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3) {
+  g_err.clear();
+  if (!h) return fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (!(eps1 >= 0) || !(eps2 >= 0) || !(eps3 >= 0) || eps1 > 1 || eps2 > 1 || eps3 > 1)
+    return fail(CM_E_BADARG, "thresholds must be in [0, 1]");
+  CM_TRY({
+    cm::dev_sai_build(h->dev, h->plan, eps1, eps2, eps3, nullptr);
+    return CM_OK;
+  })
+}
+
+cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols, cm_dtype dt,
+                       void* hip_stream) {
+  g_err.clear();
+  cm_status st = check_vec_args(h, x, y, ld, ncols, dt);
+  if (st != CM_OK) return st;
+  CM_TRY({
+    cm::dev_sai_apply(h->dev, h->plan, x, y, ld, ncols, dt == CM_C128, (hipStream_t)hip_stream);
+    return CM_OK;
+  })
+}
+
+cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_t* row_ptr, int32_t* col,
+                         double* val) {
+  g_err.clear();
+  if (!h || !nnz) return fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
+  const cm::Plan& P = h->plan;
+  const cm::Dev& d = h->dev;
+  if (which == 0 || which == 1) {
+    if (which == 1 && !d.dZn) return fail(CM_E_NOT_BUILT, "dZ/dk near field needs CM_FLAG_DERIV");
+    *nnz = P.nnz;
+    if (!row_ptr && !col && !val) return CM_OK;
+    if (!row_ptr || !col || !val) return fail(CM_E_BADARG, "null output array");
+    CM_TRY({
+      std::vector<double2> v(P.nnz);
+      cm::chk(hipMemcpy(v.data(), which ? d.dZn : d.Zn, P.nnz * sizeof(double2), hipMemcpyDeviceToHost),
+              "export copy");
+      const int64_t N = P.rwg.N;
+      row_ptr[0] = 0;
+      for (int64_t m = 0; m < N; ++m) {
+        int64_t i = P.iperm[m];
+        row_ptr[m + 1] = row_ptr[m] + (P.row_ptr[i + 1] - P.row_ptr[i]);
+      }
+      for (int64_t m = 0; m < N; ++m) {
+        int64_t i = P.iperm[m];
+        int b = P.box_of[i];
+        int64_t src = P.row_ptr[i], dst = row_ptr[m];
+        int ncl = P.bcol_ptr[b + 1] - P.bcol_ptr[b];
+        for (int t = 0; t < ncl; ++t) {
+          col[dst + t] = P.perm[P.bcol[P.bcol_ptr[b] + t]];
+          val[2 * (dst + t)] = v[src + t].x;
+          val[2 * (dst + t) + 1] = v[src + t].y;
+        }
+      }
+      return CM_OK;
+    })
+  }
+  if (which == 2) {
+    if (!d.sai_val) return fail(CM_E_NOT_BUILT, "SAI not built");
+    *nnz = d.sai_nnz;
+    if (!row_ptr && !col && !val) return CM_OK;
+    if (!row_ptr || !col || !val) return fail(CM_E_BADARG, "null output array");
+    CM_TRY({
+      const int64_t N = P.rwg.N;
+      std::vector<int64_t> ptr(N + 1);
+      std::vector<int32_t> c(d.sai_nnz);
+      std::vector<double2> v(d.sai_nnz);
+      cm::chk(hipMemcpy(ptr.data(), d.sai_ptr, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost), "export");
+      cm::chk(hipMemcpy(c.data(), d.sai_col, d.sai_nnz * sizeof(int32_t), hipMemcpyDeviceToHost), "export");
+      cm::chk(hipMemcpy(v.data(), d.sai_val, d.sai_nnz * sizeof(double2), hipMemcpyDeviceToHost), "export");
+      row_ptr[0] = 0;
+      for (int64_t m = 0; m < N; ++m) {
+        int64_t i = P.iperm[m];
+        row_ptr[m + 1] = row_ptr[m] + (ptr[i + 1] - ptr[i]);
+      }
+      for (int64_t m = 0; m < N; ++m) {
+        int64_t i = P.iperm[m];
+        int64_t dst = row_ptr[m];
+        for (int64_t t = ptr[i]; t < ptr[i + 1]; ++t, ++dst) {
+          col[dst] = P.perm[c[t]];
+          val[2 * dst] = v[t].x;
+          val[2 * dst + 1] = v[t].y;
+        }
+      }
+      return CM_OK;
+    })
+  }
+  return fail(CM_E_BADARG, "which must be 0, 1 or 2");
+}
+
+cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* needed) {
+  if (!h) return fail(CM_E_BADARG, "null argument");
+  std::string s = h->plan.stats_json();
+  if (needed) *needed = (int64_t)s.size() + 1;
+  if (!buf || buf_len < (int64_t)s.size() + 1) return fail(CM_E_BADARG, "buffer too small");
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return CM_OK;
+}
+
+const char* cm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

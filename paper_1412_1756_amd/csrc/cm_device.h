@@ -1,0 +1,87 @@
+// Device-side data of a handle and the kernel launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "cm_plan.h"
+
+namespace cm {
+
+// Triangle record used by the fill kernels (17 doubles).
+struct TriD {
+  double v[9];      // vertices
+  double n[3];      // unit normal
+  double c[3];      // centroid
+  double area, hmax;
+};
+// RWG record in internal (box-sorted) order.
+struct RwgD {
+  int32_t t[2];     // T+, T-
+  int32_t a[2];     // local vertex opposite the edge in T+, T-
+  double len;
+};
+
+template <typename R>
+struct LevelD {
+  int nbox = 0, K = 0, nt = 0, np = 0;
+  int32_t *far_ptr = nullptr, *far_src = nullptr, *far_off = nullptr;
+  int32_t *farR_ptr = nullptr, *farR_src = nullptr, *farR_off = nullptr;
+  int32_t *child_ptr = nullptr, *parent = nullptr;
+  int8_t* octant = nullptr;                 // child position in its parent (code & 7)
+  void *TZ = nullptr, *TR = nullptr, *TX = nullptr, *dTZ = nullptr;  // kNoff x K complex<R>
+  // interpolation from level l+1 into this level (l = 2..lf-1)
+  int p = 0, ntc = 0, npc = 0;
+  int32_t *th_idx = nullptr, *th_ref = nullptr, *ph_idx = nullptr;
+  R *th_w = nullptr, *ph_w = nullptr;
+  int32_t *tht_ptr = nullptr, *tht_idx = nullptr, *tht_ref = nullptr, *pht_ptr = nullptr, *pht_idx = nullptr;
+  R *tht_w = nullptr, *pht_w = nullptr;
+  void* shift = nullptr;                    // 8 x K complex<R>: exp(ik khat.(r_child - r_parent))
+};
+
+template <typename R>
+struct PrecD {
+  void* V = nullptr;                        // N x 2 x K_leaf complex<R>, leaf radiation patterns
+  void* dV = nullptr;                       // d/dk of V (CM_FLAG_DERIV)
+  R* qwc = nullptr;                         // K_leaf: (k^2 eta / 4 pi) w_q
+  std::vector<LevelD<R>> lev;
+};
+
+struct Dev {
+  int device = 0;
+  int64_t N = 0, nnz = 0;
+  int lf = 0, nleaf = 0, Kleaf = 0, max_cols = 0;
+  TriD* tri = nullptr;
+  RwgD* rwg = nullptr;
+  int32_t *perm = nullptr, *box_of = nullptr, *box_start = nullptr;
+  int32_t *bcol_ptr = nullptr, *bcol = nullptr, *self_off = nullptr;
+  int64_t* row_ptr = nullptr;
+  double* leaf_center = nullptr;            // 3 x nleaf
+  double* leaf_dirs = nullptr;              // 9 x K_leaf
+  double2* Zn = nullptr;                    // near-field values (nnz)
+  double2* dZn = nullptr;                   // dZ_near/dk values (nnz)
+  PrecD<float> f32;
+  PrecD<double> f64;
+  // workspace (sized for max_cols, complex double; reused as complex float)
+  std::vector<void*> S, G, dS, dG;          // per level
+  void *xi = nullptr, *yi = nullptr, *dxi = nullptr;
+  // SAI
+  int64_t sai_nnz = 0;
+  int64_t* sai_ptr = nullptr;               // internal rows of P (N+1)
+  int32_t* sai_col = nullptr;               // internal column indices
+  double2* sai_val = nullptr;
+  std::vector<void*> allocs;
+};
+
+void dev_build(Dev& d, const Plan& P, hipStream_t s);
+void dev_free(Dev& d);
+// op: 0 Z, 1 R, 2 X, 3 Z^H, 4 dZ/dk
+void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
+               hipStream_t s);
+void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipStream_t s);
+void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64,
+                   hipStream_t s);
+
+}  // namespace cm

@@ -1,0 +1,113 @@
+// Host-side plan of the MLFMA: RWG table, octree, interaction lists, angular
+// sampling, translators, interpolation and shift tables.  Pure C++ (no HIP).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace cm {
+
+using cplx = std::complex<double>;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// RWG basis functions (eq. (4)), public order: interior edges sorted by
+// (smaller vertex, larger vertex); T+ = lower-numbered triangle.
+struct Rwg {
+  int64_t N = 0;
+  std::vector<int32_t> edge;   // 2N
+  std::vector<int32_t> tri;    // 2N: T+, T-
+  std::vector<int32_t> loc;    // 2N: local vertex (0..2) of T+/T- opposite the edge
+  std::vector<double> len;     // N
+};
+
+// One octree level.  Boxes are the occupied cubes of side a, Morton-sorted.
+struct Level {
+  int l = 0;
+  double a = 0;
+  int L = 0, nt = 0, np = 0, K = 0;          // truncation and sampling (nt x np)
+  std::vector<double> theta, wtheta;          // nt Gauss-Legendre nodes (theta ascending)
+  int nbox = 0;
+  std::vector<uint64_t> code;
+  std::vector<int32_t> ijk;                   // 3 nbox integer box coordinates
+  std::vector<int32_t> parent;                // index at level l-1
+  std::vector<int32_t> child_ptr;             // nbox+1, range of children at level l+1
+  // translation lists (receiver-major CSR): source box and offset id
+  std::vector<int32_t> far_ptr, far_src, far_off;     // Z and X
+  std::vector<int32_t> farR_ptr, farR_src, farR_off;  // R (leaf level adds neighbours)
+};
+
+// Local Lagrange interpolation from level c = l+1 (child) to level l (parent),
+// separable: theta first (with reflection over the poles), then phi.
+struct Interp {
+  int p = 0;
+  int ntc = 0, npc = 0, ntp = 0, npp = 0;
+  std::vector<int32_t> th_idx;  std::vector<int32_t> th_ref; std::vector<double> th_w;   // ntp*p
+  std::vector<int32_t> ph_idx;  std::vector<double> ph_w;                                // npp*p
+  // gather form of the weighted transposes (anterpolation), CSR over child index
+  std::vector<int32_t> tht_ptr, tht_idx, tht_ref; std::vector<double> tht_w;
+  std::vector<int32_t> pht_ptr, pht_idx; std::vector<double> pht_w;
+};
+
+struct Opts {
+  int nlv = 0;
+  double d0 = 3.0;
+  int p = 6;
+  double eta = 376.730313668;
+  uint32_t flags = 0;
+  int max_cols = 32;
+};
+
+// Offsets between boxes at one level are coded as (dx+3)*49 + (dy+3)*7 + (dz+3).
+constexpr int kNoff = 343;
+inline int off_id(int dx, int dy, int dz) { return (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3); }
+
+struct Plan {
+  Opts opt;
+  double k = 0;
+  // mesh
+  int64_t nv = 0, nt = 0;
+  std::vector<double> V;        // 3 nv
+  std::vector<int32_t> F;       // 3 nt
+  std::vector<double> area, hmax, cent, normal;  // per triangle
+  Rwg rwg;
+  // tree
+  double origin[3] = {0, 0, 0};
+  double side = 0;
+  int nlv = 0, lf = 0;          // leaf level = nlv - 1
+  std::vector<Level> lev;       // 0..lf
+  std::vector<Interp> ip;       // ip[l] maps level l+1 -> l, for l = 2..lf-1
+  std::vector<int32_t> perm;    // internal index -> public RWG index
+  std::vector<int32_t> iperm;   // public -> internal
+  std::vector<int32_t> box_start;  // leaf box -> first internal unknown (nleaf+1)
+  std::vector<int32_t> box_of;     // internal unknown -> leaf box
+  // near field (leaf): per box, near boxes sorted; unified column list per box
+  std::vector<int32_t> near_ptr, near_box;     // CSR over leaf boxes
+  std::vector<int32_t> bcol_ptr, bcol;         // per box: concatenated internal columns
+  std::vector<int32_t> self_off;               // per box: offset of own columns in its row
+  std::vector<int64_t> row_ptr;                // internal rows -> value offset (N+1)
+  int64_t nnz = 0;
+  // tables (FP64)
+  std::vector<std::vector<cplx>> TZ, TR, TX, dTZ;   // [level][kNoff*K] (used offsets only)
+  std::vector<std::vector<uint8_t>> off_used;        // [level][kNoff]
+  std::vector<std::vector<cplx>> shift;             // [level l][8*K_l]: child l+1 -> l
+  std::vector<std::vector<double>> qw;              // [level][K] quadrature weights
+  std::vector<std::vector<double>> dirs;            // [level][9*K]: khat, theta-hat, phi-hat
+
+  void build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri, double k,
+             const Opts& o);
+  void check_coverage() const;
+  std::string stats_json() const;
+};
+
+// spherical Bessel j_l and Neumann y_l, l = 0..L
+void sph_jy(int L, double x, std::vector<double>& j, std::vector<double>& y);
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+}  // namespace cm

@@ -1,0 +1,132 @@
+"""Python face of the C ABI: marshals numpy meshes and torch tensors."""
+import ctypes as C
+import json
+
+import numpy as np
+
+from . import _lib
+from ._lib import CmError, check, lib
+
+
+class Operator:
+    """MLFMA operator of one mesh at one wavenumber.
+
+    Parameters mirror ``cm_opts``: nlv (levels including level 0), d0 (digits
+    of the truncation rule, eq. (30)), interp_p (local Lagrange points),
+    max_cols (largest batch).  host_only=True builds only the host plan (no
+    GPU needed); deriv=True also builds dZ/dk tables.
+    """
+
+    def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
+                 deriv=False, check_coverage=False, stream=None):
+        L = lib()
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        F = np.ascontiguousarray(F, dtype=np.int32)
+        o = _lib.cm_opts()
+        L.cm_default_opts(C.byref(o))
+        o.nlv = int(nlv)
+        o.d0 = float(d0)
+        o.interp_p = int(interp_p)
+        if eta is not None:
+            o.eta = float(eta)
+        o.max_cols = int(max_cols)
+        o.flags = ((_lib.CM_FLAG_HOST_ONLY if host_only else 0) | (_lib.CM_FLAG_DERIV if deriv else 0)
+                   | (_lib.CM_FLAG_CHECK if check_coverage else 0))
+        kk = np.array([float(k)], dtype=np.float64)
+        h = C.c_void_p()
+        s = self._stream_ptr(stream) if not host_only else None
+        st = L.cm_create(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], kk.ctypes.data, 1, C.byref(o), s,
+                         C.byref(h))
+        check(st)
+        self._h = h
+        self.k = float(k)
+        self.host_only = host_only
+        self.max_cols = int(max_cols)
+        n = C.c_int64()
+        check(L.cm_num_unknowns(h, C.byref(n)))
+        self.N = int(n.value)
+
+    @staticmethod
+    def _stream_ptr(stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return C.c_void_p(stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ host queries
+    def rwg_table(self):
+        e = np.zeros((self.N, 2), dtype=np.int32)
+        t = np.zeros((self.N, 2), dtype=np.int32)
+        check(lib().cm_rwg_table(self._h, e.ctypes.data, t.ctypes.data))
+        return e, t
+
+    def stats(self):
+        need = C.c_int64()
+        lib().cm_stats(self._h, None, 0, C.byref(need))
+        buf = C.create_string_buffer(int(need.value))
+        check(lib().cm_stats(self._h, buf, need.value, C.byref(need)))
+        return json.loads(buf.value.decode())
+
+    def export_near(self, which=0):
+        """Near-field (which=0), dZ_near/dk (1) or SAI (2) matrix as scipy CSR
+        in public unknown order."""
+        import scipy.sparse as sp
+        nnz = C.c_int64()
+        check(lib().cm_export_near(self._h, which, C.byref(nnz), None, None, None))
+        ptr = np.zeros(self.N + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(2 * nnz.value, dtype=np.float64)
+        check(lib().cm_export_near(self._h, which, C.byref(nnz), ptr.ctypes.data, col.ctypes.data,
+                                   val.ctypes.data))
+        return sp.csr_matrix((val[0::2] + 1j * val[1::2], col, ptr), shape=(self.N, self.N))
+
+    # ------------------------------------------------------------ device applies
+    def _vec_args(self, x, out):
+        import torch
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError("x must be a CUDA (HIP) torch tensor")
+        if x.dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("x must be complex64 or complex128")
+        squeeze = x.dim() == 1
+        X = x.reshape(-1, 1) if squeeze else x
+        if X.shape[0] != self.N:
+            raise ValueError(f"x has {X.shape[0]} rows, operator has N={self.N}")
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        if out is None:
+            out = torch.empty((self.N, X.shape[1]), dtype=X.dtype, device=X.device)
+        elif out.dim() == 1:
+            out = out.reshape(-1, 1)
+        if out.stride(1) != 1 or out.stride(0) != X.stride(0):
+            raise ValueError("out must be row-major with the same row stride as x")
+        dt = _lib.CM_C128 if X.dtype == torch.complex128 else _lib.CM_C64
+        return X, out, dt, squeeze
+
+    def apply(self, x, op="Z", out=None, stream=None):
+        """y = op(x) for x of shape (N,) or (N, ncols) on the GPU."""
+        X, Y, dt, squeeze = self._vec_args(x, out)
+        st = lib().cm_apply(self._h, _lib.OPS[op], C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                            X.stride(0), X.shape[1], None, dt, self._stream_ptr(stream))
+        check(st)
+        return Y.reshape(-1) if squeeze else Y
+
+    def sai_build(self, eps1=0.01, eps2=0.014, eps3=0.18):
+        check(lib().cm_sai_build(self._h, eps1, eps2, eps3))
+
+    def sai_apply(self, x, out=None, stream=None):
+        X, Y, dt, squeeze = self._vec_args(x, out)
+        st = lib().cm_sai_apply(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.stride(0),
+                                X.shape[1], dt, self._stream_ptr(stream))
+        check(st)
+        return Y.reshape(-1) if squeeze else Y
