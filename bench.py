@@ -1,0 +1,192 @@
+"""Benchmark: MLFMA Z.x matvecs/s at N = 122,880 (PEC sphere, radius 4
+wavelengths, 6-level tree) on one MI355X -- FP32 batched (far field in complex
+FP32, near field FP64) against FP64 single-vector, each with its relative
+2-norm error against the CPU FP64 oracle on sampled rows.
+
+One "step" is one apply of Z to a block of `--ncols` right-hand sides (the
+whole hot path: near-field product, aggregation, interpolation, translation,
+anterpolation, disaggregation).  Inputs are resident in HBM before timing
+starts; the library launches on torch's current stream, which is what the
+HIP events bracket.  Prints ONE JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # B/s
+FP32_PEAK = 157.3e12         # flop/s, vector (256 CU x 128 lanes x 2 x 2.4 GHz)
+FP64_PEAK = 78.6e12          # flop/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ncols", type=int, default=32)
+    ap.add_argument("--d0", type=float, default=5.0)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--nlv", type=int, default=6)
+    ap.add_argument("--rows", type=int, default=6, help="oracle rows for error and CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no error, no CPU baseline)")
+    return ap.parse_args()
+
+
+def stage_model(st, nc, cb):
+    """Algorithmic bytes and flops per apply, per stage, from the plan
+    statistics.  cb = bytes per far-field complex number (8 FP32, 16 FP64)."""
+    N = st["N"]
+    lev = {x["l"]: x for x in st["levels"]}
+    lf = max(lev)
+    Kf = lev[lf]["K"]
+    nleaf = lev[lf]["nbox"]
+    p = st["interp_p"]
+    m = {}
+    m["near"] = dict(bytes=st["nnz_near"] * 16 + st["near_cols_total"] * 4 + 2 * N * nc * cb,
+                     flops=8.0 * st["nnz_near"] * nc, fp="f64")
+    m["aggregate"] = dict(bytes=N * 2 * Kf * cb + N * nc * cb + nleaf * 2 * Kf * nc * cb,
+                          flops=8.0 * N * 2 * Kf * nc, fp="f32" if cb == 8 else "f64")
+    m["disagg"] = dict(bytes=N * 2 * Kf * cb + nleaf * 2 * Kf * nc * cb + 2 * N * nc * cb,
+                       flops=8.0 * N * 2 * Kf * nc, fp=m["aggregate"]["fp"])
+    for l in range(2, lf + 1):
+        L = lev[l]
+        pat = L["nbox"] * 2 * L["K"] * nc * cb
+        m[f"m2l_l{l}"] = dict(bytes=2 * pat + 343 * L["K"] * cb, flops=8.0 * L["far_pairs"] * 2 * L["K"] * nc,
+                              fp=m["aggregate"]["fp"])
+        if l < lf:
+            C = lev[l + 1]
+            cpat = C["nbox"] * 2 * C["K"] * nc * cb
+            fl = C["nbox"] * nc * (2 * L["nt"] * C["np"] * p * 4 + 2 * L["K"] * p * 4 + 2 * L["K"] * 8)
+            m[f"interp_l{l}"] = dict(bytes=cpat + pat, flops=float(fl), fp=m["aggregate"]["fp"])
+            m[f"anterp_l{l + 1}"] = dict(bytes=2 * cpat + pat, flops=float(fl), fp=m["aggregate"]["fp"])
+    m["permute"] = dict(bytes=2 * N * nc * cb, flops=0.0, fp=m["aggregate"]["fp"])
+    return m
+
+
+def roofline(stage, times, calls, model):
+    mdl = model[stage]
+    t = times[stage]["ms"] / times[stage]["calls"] * 1e-3
+    peak_f = FP32_PEAK if mdl["fp"] == "f32" else FP64_PEAK
+    intensity = mdl["flops"] / max(mdl["bytes"], 1)
+    if intensity * HBM_PEAK > peak_f:           # above the ridge: arithmetic-bound
+        return {"kernel": stage, "bound": "alu", "achieved": mdl["flops"] / t / 1e12, "peak": peak_f / 1e12,
+                "unit": "TFLOP/s", "frac": mdl["flops"] / t / peak_f, "traffic": None,
+                "avg_launch_ms": t * 1e3, "alg_flops": mdl["flops"], "alg_bytes": mdl["bytes"]}
+    return {"kernel": stage, "bound": "hbm", "achieved": mdl["bytes"] / t / 1e9, "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s", "frac": mdl["bytes"] / t / HBM_PEAK, "traffic": None,
+            "avg_launch_ms": t * 1e3, "alg_flops": mdl["flops"], "alg_bytes": mdl["bytes"]}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU sharding is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads
+    from paper_1412_1756_amd import Operator
+
+    name = "sphere_r4_n122880"
+    V, F, spec = workloads.workload(name)
+    k = spec["k"]
+    dev = torch.device("cuda:0")
+    op = Operator(V, F, k, nlv=a.nlv, d0=a.d0, interp_p=a.p, max_cols=max(a.ncols, 1))
+    N = op.N
+    st = op.stats()
+    x1 = workloads.cn01(N, 0)
+    X32 = torch.tensor(workloads.cn01_block(N, a.ncols, 100), dtype=torch.complex64, device=dev)
+    X32[:, 0] = torch.tensor(x1, dtype=torch.complex64, device=dev)
+    X64 = torch.tensor(x1, dtype=torch.complex128, device=dev).reshape(N, 1)
+    Y32 = torch.empty_like(X32)
+    Y64 = torch.empty_like(X64)
+    torch.cuda.synchronize()
+
+    def timed(X, Y, steps, warm, stage_timing=True):
+        for _ in range(warm):
+            op.apply(X, out=Y)
+        torch.cuda.synchronize()
+        op.stage_timing(stage_timing)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            op.apply(X, out=Y)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        times = op.stage_times() if stage_timing else {}
+        op.stage_timing(False)
+        return e0.elapsed_time(e1) / steps, wall, times
+
+    # untimed-stage pass (pure throughput), then a pass with per-stage events
+    ms32, wall32, _ = timed(X32, Y32, a.steps, a.warmup, stage_timing=False)
+    ms64, wall64, _ = timed(X64, Y64, a.steps, a.warmup, stage_timing=False)
+    _, _, times32 = timed(X32, Y32, max(3, a.steps // 4), 1)
+    _, _, times64 = timed(X64, Y64, max(3, a.steps // 4), 1)
+
+    y32 = Y32[:, 0].cpu().numpy().astype(np.complex128)
+    y64 = Y64[:, 0].cpu().numpy()
+
+    model32 = stage_model(st, a.ncols, 8)
+    model64 = stage_model(st, 1, 16)
+    dom32 = max((s for s in times32 if s in model32), key=lambda s: times32[s]["ms"])
+    dom64 = max((s for s in times64 if s in model64), key=lambda s: times64[s]["ms"])
+    roof = roofline(dom32, times32, None, model32)
+    roof64 = roofline(dom64, times64, None, model64)
+    stage_frac = {s: round(v["ms"] / sum(u["ms"] for u in times32.values()), 4) for s, v in times32.items()}
+
+    out = {
+        "metric": "MLFMA Z·x matvecs/s at N=122,880: FP32 batched vs FP64 single, at stated rel err",
+        "value": a.ncols * 1000.0 / ms32,
+        "unit": "matvecs/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms32,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 far field / c128 near field",
+        "data": "synthetic",
+        "config": {"workload": name, "N": N, "nlv": a.nlv, "d0": a.d0, "interp_p": a.p, "ncols": a.ncols,
+                   "k": k, "mesh": "icosphere nsub 6, radius 4 wavelengths"},
+        "fp64_single": {"matvecs_per_s": 1000.0 / ms64, "ms_per_matvec": ms64, "dtype": "c128",
+                        "roofline": roof64},
+        "roofline": roof,
+        "stage_fraction_fp32_batched": stage_frac,
+        "stage_fraction_fp64_single": {s: round(v["ms"] / sum(u["ms"] for u in times64.values()), 4)
+                                       for s, v in times64.items()},
+        "stage_ms_fp32_batched": {s: round(v["ms"] / v["calls"], 4) for s, v in times32.items()},
+        "stage_ms_fp64_single": {s: round(v["ms"] / v["calls"], 4) for s, v in times64.items()},
+    }
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle import efie
+        from oracle.rwg import build_rwg
+        rows = np.sort(np.random.default_rng(2).choice(N, a.rows, replace=False))
+        geo = efie.Geometry(V, F)
+        rwg = build_rwg(V, F)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            Zr = efie.rows_Z(V, F, k, rows, geo=geo, rwg=rwg)
+            t_rows = time.perf_counter() - t0
+        ref = Zr @ x1
+        e32 = float(np.linalg.norm(y32[rows] - ref) / np.linalg.norm(ref))
+        e64 = float(np.linalg.norm(y64[rows] - ref) / np.linalg.norm(ref))
+        out["config"]["rel_err_fp32_batched"] = e32
+        out["fp64_single"]["rel_err"] = e64
+        out["config"]["rel_err_rows"] = int(a.rows)
+        out["cpu_baseline"] = {"value": 1.0 / (t_rows / a.rows * N), "unit": "matvecs/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{a.rows} of {N} rows of Z filled by the FP64 oracle and applied to x "
+                                         f"({t_rows:.1f} s), extrapolated x N/{a.rows} to one full Z.x"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -139,6 +139,18 @@ cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_
    Returns CM_E_BADARG if buf_len is too small (needed size in *needed). */
 cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* needed);
 
+/* Per-stage timing of applies: with enable != 0, every later cm_apply /
+   cm_sai_apply on this handle brackets each kernel stage with HIP events
+   recorded on the apply's own stream (small overhead); enable = 0 turns it
+   off.  Either call resets the accumulated times. */
+cm_status cm_stage_timing(cm_handle* h, int32_t enable);
+
+/* Accumulated stage times since cm_stage_timing as JSON
+   {"near": {"ms": total, "calls": n}, "m2l_l5": {...}, ...}, NUL-terminated
+   into buf (needed size in *needed; CM_E_BADARG if buf_len is too small).
+   Synchronises with the recorded events. */
+cm_status cm_stage_times(cm_handle* h, char* buf, int64_t buf_len, int64_t* needed);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* cm_last_error(void);
 

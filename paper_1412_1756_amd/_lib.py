@@ -12,7 +12,8 @@ CM_C64, CM_C128 = 0, 1
 CM_FLAG_HOST_ONLY, CM_FLAG_DERIV, CM_FLAG_CHECK = 1, 2, 4
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
-           "cm_sai_build", "cm_sai_apply", "cm_export_near", "cm_stats", "cm_last_error"]
+           "cm_sai_build", "cm_sai_apply", "cm_export_near", "cm_stats", "cm_stage_timing", "cm_stage_times",
+           "cm_last_error"]
 
 
 class cm_opts(C.Structure):
@@ -59,6 +60,10 @@ def lib():
     L.cm_export_near.restype = C.c_int
     L.cm_stats.argtypes = [vp, C.c_char_p, i64, C.POINTER(i64)]
     L.cm_stats.restype = C.c_int
+    L.cm_stage_timing.argtypes = [vp, i32]
+    L.cm_stage_timing.restype = C.c_int
+    L.cm_stage_times.argtypes = [vp, C.c_char_p, i64, C.POINTER(i64)]
+    L.cm_stage_times.restype = C.c_int
     L.cm_last_error.argtypes = []
     L.cm_last_error.restype = C.c_char_p
     _lib = L

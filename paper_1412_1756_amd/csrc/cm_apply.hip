@@ -120,179 +120,462 @@ __global__ void __launch_bounds__(256) k_near(const int64_t* __restrict__ row_pt
 }
 
 // ---------------------------------------------------------------- aggregation
-// S_b(q) = sum_{j in box b} V_j(q) x_j  (eq. (13) summed over the box), 2 components
-template <typename R>
+// S_b(q) = sum_{j in box b} V_j(q) x_j  (eq. (13) summed over the box), 2 components.
+// CG columns per thread (1, or 4 when nc % 4 == 0): one leaf-pattern load feeds
+// CG complex multiply-adds.
+template <typename R, int CG>
 __global__ void __launch_bounds__(256) k_aggregate(const C2<R>* __restrict__ V, const C2<R>* __restrict__ xi,
                                                    C2<R>* __restrict__ S, const int32_t* __restrict__ box_start,
                                                    int K, int nc) {
   const int b = blockIdx.x;
   const int j0 = box_start[b], j1 = box_start[b + 1];
-  const int tot = 2 * K * nc;
+  const int ncg = nc / CG;
+  const int tot = 2 * K * ncg;
   for (int o = blockIdx.y * blockDim.x + threadIdx.x; o < tot; o += gridDim.y * blockDim.x) {
-    const int c = o % nc, cq = o / nc;
-    C2<R> acc = mk<R>(0, 0);
-    for (int j = j0; j < j1; ++j) acc = cfma(acc, V[(int64_t)j * 2 * K + cq], xi[(int64_t)j * nc + c]);
-    S[(int64_t)b * tot + o] = acc;
+    const int cg = o % ncg, cq = o / ncg;
+    C2<R> acc[CG];
+#pragma unroll
+    for (int u = 0; u < CG; ++u) acc[u] = mk<R>(0, 0);
+    for (int j = j0; j < j1; ++j) {
+      const C2<R> v = V[(int64_t)j * 2 * K + cq];
+      const C2<R>* xr = xi + (int64_t)j * nc + cg * CG;
+#pragma unroll
+      for (int u = 0; u < CG; ++u) acc[u] = cfma(acc[u], v, xr[u]);
+    }
+    C2<R>* out = S + ((int64_t)b * 2 * K + cq) * nc + cg * CG;
+#pragma unroll
+    for (int u = 0; u < CG; ++u) out[u] = acc[u];
   }
 }
 
 // ---------------------------------------------------------------- interpolation up
-// S_parent(q) = sum_children exp(ik khat_q.(r_c - r_p)) [I_phi I_theta S_child](q)
-// theta first (child theta -> parent theta, with pole reflections), then phi.
-template <typename R>
-__global__ void __launch_bounds__(256) k_interp_up(const C2<R>* __restrict__ Sc, C2<R>* __restrict__ Sp,
+// S_parent(q) = sum_children exp(ik khat_q.(r_c - r_p)) [I_theta I_phi S_child](q).
+// The local Lagrange operators in theta and phi commute (the phi stencil is
+// invariant under the half-turn phi -> phi + pi that the pole reflection uses),
+// so phi is interpolated first, within each child theta row (row-local global
+// reads), into an LDS grid [ntc][npp][cs]; the theta stencil then reads LDS.
+// Block = (parent box, column slice of width cs, component); every thread
+// owns up to JMAX parent samples, accumulated in registers over the children.
+template <typename R, int JMAX>
+__global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restrict__ Sc, C2<R>* __restrict__ Sp,
                                                    const int32_t* __restrict__ child_ptr,
-                                                   const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc) {
+                                                   const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
+                                                   int cs, int tpc) {
   extern __shared__ unsigned char smem_raw[];
-  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [2][ntp][npc]
-  const int m = blockIdx.x, c = blockIdx.y;
+  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [ntc][npp][cs]
   const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, p = P.p, Kp = P.K;
-  const int half = npc / 2;
+  const int nchunk = (ntp + tpc - 1) / tpc;
+  const int m = blockIdx.x / nchunk, tp0 = (blockIdx.x % nchunk) * tpc;
+  const int c0 = blockIdx.y * cs, comp = blockIdx.z;
+  const int cw = min(cs, nc - c0);
+  const int hp = npp / 2;
   const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift);
-  C2<R>* out = Sp + (int64_t)m * 2 * Kp * nc;
-  for (int e = threadIdx.x; e < 2 * Kp; e += blockDim.x) out[(int64_t)e * nc + c] = mk<R>(0, 0);
+  const int nout = min(tpc, ntp - tp0) * npp * cs;   // this block's parent rows tp0 .. tp0+tpc-1
+  const int nmid = ntc * npp * cs;
+  C2<R> acc[JMAX];
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) acc[j] = mk<R>(0, 0);
   for (int ch = child_ptr[m]; ch < child_ptr[m + 1]; ++ch) {
-    const C2<R>* src = Sc + (int64_t)ch * 2 * Kc * nc;
+    const C2<R>* src = Sc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
     const int oc = octant[ch];
     __syncthreads();
-    for (int e = threadIdx.x; e < 2 * ntp * npc; e += blockDim.x) {
-      const int uc = e % npc, tp = (e / npc) % ntp, comp = e / (npc * ntp);
-      C2<R> acc = mk<R>(0, 0);
-      for (int j = 0; j < p; ++j) {
-        const int tc = P.th_idx[tp * p + j];
-        const int rf = P.th_ref[tp * p + j];
-        const R w = rf ? -P.th_w[tp * p + j] : P.th_w[tp * p + j];
-        const int u = rf ? (uc + half) % npc : uc;
-        const C2<R> v = src[((int64_t)comp * Kc + tc * npc + u) * nc + c];
-        acc.x = fma(w, v.x, acc.x);
-        acc.y = fma(w, v.y, acc.y);
+    for (int e = threadIdx.x; e < nmid; e += blockDim.x) {
+      const int c = e % cs, up = (e / cs) % npp, tc = e / (cs * npp);
+      C2<R> a = mk<R>(0, 0);
+      if (c < cw) {
+        const C2<R>* row = src + (int64_t)tc * npc * nc + c;
+        for (int j = 0; j < p; ++j) {
+          const R w = P.ph_w[up * p + j];
+          const C2<R> v = row[(int64_t)P.ph_idx[up * p + j] * nc];
+          a.x = fma(w, v.x, a.x);
+          a.y = fma(w, v.y, a.y);
+        }
       }
-      tmp[e] = acc;
+      tmp[e] = a;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 2 * Kp; e += blockDim.x) {
-      const int up = e % npp, tp = (e / npp) % ntp, comp = e / (npp * ntp);
-      const C2<R>* row = tmp + (comp * ntp + tp) * npc;
-      C2<R> acc = mk<R>(0, 0);
-      for (int j = 0; j < p; ++j) {
-        const R w = P.ph_w[up * p + j];
-        const C2<R> v = row[P.ph_idx[up * p + j]];
-        acc.x = fma(w, v.x, acc.x);
-        acc.y = fma(w, v.y, acc.y);
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+      const int o = threadIdx.x + j * blockDim.x;
+      if (o < nout) {
+        const int c = o % cs, up = (o / cs) % npp, tp = tp0 + o / (cs * npp);
+        C2<R> a = mk<R>(0, 0);
+        for (int t = 0; t < p; ++t) {
+          const int tc = P.th_idx[tp * p + t];
+          const int rf = P.th_ref[tp * p + t];
+          const R w = rf ? -P.th_w[tp * p + t] : P.th_w[tp * p + t];
+          const C2<R> v = tmp[(tc * npp + (rf ? (up + hp) % npp : up)) * cs + c];
+          a.x = fma(w, v.x, a.x);
+          a.y = fma(w, v.y, a.y);
+        }
+        acc[j] = cfma(acc[j], a, shift[oc * Kp + tp * npp + up]);
       }
-      const C2<R> sh = shift[oc * Kp + tp * npp + up];
-      C2<R>& o = out[(int64_t)e * nc + c];
-      o = cfma(o, acc, sh);
+    }
+  }
+  C2<R>* out = Sp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) {
+    const int o = threadIdx.x + j * blockDim.x;
+    if (o < nout) {
+      const int c = o % cs, q = tp0 * npp + o / cs;
+      if (c < cw) out[(int64_t)q * nc + c] = acc[j];
     }
   }
 }
 
 // ---------------------------------------------------------------- translation
-// G_m(q) (+)= sum_{m' in list(m)} T_off(m,m')(q) S_m'(q)  (eq. (10)/(16)/(20), diagonal)
-template <typename R>
-__global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
-                                             const int32_t* __restrict__ off, const C2<R>* __restrict__ T,
-                                             const C2<R>* __restrict__ S, C2<R>* __restrict__ G, int K, int nc) {
-  const int m = blockIdx.x;
-  const int tot = 2 * K * nc;
-  const int o = blockIdx.y * blockDim.x + threadIdx.x;
-  if (o >= tot) return;
-  const int q = (o / nc) % K;
-  C2<R> acc = mk<R>(0, 0);
-  for (int e = ptr[m]; e < ptr[m + 1]; ++e)
-    acc = cfma(acc, T[(int64_t)off[e] * K + q], S[(int64_t)src[e] * tot + o]);
-  G[(int64_t)m * tot + o] = acc;
+// G_m(q) = sum_{m' in list(m)} T_off(m,m')(q) S_m'(q)  (diagonal translation,
+// eqs. (10)/(16)/(20)).  Block = (tile of kTile consecutive receivers,
+// direction chunk, column chunk).  The tile's sources are the union of its
+// receivers' lists; each source pattern element is loaded once and applied to
+// every receiver of the tile that lists it (register accumulators).  With
+// STAGE the block's translator rows are staged in LDS first.
+template <typename R, bool STAGE>
+__global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tsrc,
+                                             const int16_t* __restrict__ toff, const C2<R>* __restrict__ T,
+                                             int n_off, const C2<R>* __restrict__ S, C2<R>* __restrict__ G,
+                                             int nbox, int K, int nc, int cw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<R>* Ts = reinterpret_cast<C2<R>*>(smem_raw);    // [n_off][qb]
+  const int tile = blockIdx.x;
+  const int qb = blockDim.x / cw;                     // directions per block
+  const int c = blockIdx.z * cw + (int)(threadIdx.x % cw);
+  const int ql = threadIdx.x / cw;
+  const int q = blockIdx.y * qb + ql;
+  const bool act = (ql < qb) && (q < K) && (c < nc);
+  if (STAGE) {
+    for (int e = threadIdx.x; e < n_off * qb; e += blockDim.x) {
+      const int f = e / qb, qq = blockIdx.y * qb + e % qb;
+      Ts[e] = (qq < K) ? T[(int64_t)f * K + qq] : mk<R>(0, 0);
+    }
+    __syncthreads();
+  }
+  C2<R> a0[kTile], a1[kTile];
+#pragma unroll
+  for (int r = 0; r < kTile; ++r) a0[r] = a1[r] = mk<R>(0, 0);
+  const int e0 = tptr[tile], e1 = tptr[tile + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int sb = tsrc[e];
+    C2<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
+    if (act) {
+      s0 = S[(((int64_t)sb * 2 + 0) * K + q) * nc + c];
+      s1 = S[(((int64_t)sb * 2 + 1) * K + q) * nc + c];
+    }
+    const int16_t* of = toff + (int64_t)e * kTile;
+#pragma unroll
+    for (int r = 0; r < kTile; ++r) {
+      const int f = of[r];
+      if (f >= 0) {
+        const C2<R> t = STAGE ? (act ? Ts[f * qb + ql] : mk<R>(0, 0)) : (act ? T[(int64_t)f * K + q] : mk<R>(0, 0));
+        a0[r] = cfma(a0[r], t, s0);
+        a1[r] = cfma(a1[r], t, s1);
+      }
+    }
+  }
+  if (!act) return;
+#pragma unroll
+  for (int r = 0; r < kTile; ++r) {
+    const int m = tile * kTile + r;
+    if (m < nbox) {
+      G[(((int64_t)m * 2 + 0) * K + q) * nc + c] = a0[r];
+      G[(((int64_t)m * 2 + 1) * K + q) * nc + c] = a1[r];
+    }
+  }
 }
 
 // ---------------------------------------------------------------- anterpolation down
-// G_child += A [exp(-ik khat.(r_c - r_p)) G_parent],  A = W_c^-1 I^T W_p (gather form)
+// G_child += W_c^-1 I^T W_p [exp(-ik khat.(r_c - r_p)) G_parent]: the weighted
+// transposes of the two stencils, phi first (row-local reads of the parent
+// into an LDS grid [ntp][npc][cs]), then theta from LDS.  Block = (child box,
+// column slice, component).
 template <typename R>
-__global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ Gp, C2<R>* __restrict__ Gc,
+__global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restrict__ Gp, C2<R>* __restrict__ Gc,
                                                      const int32_t* __restrict__ parent,
-                                                     const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc) {
+                                                     const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
+                                                     int cs) {
   extern __shared__ unsigned char smem_raw[];
-  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [2][ntp][npc]
-  const int ch = blockIdx.x, c = blockIdx.y;
+  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [ntp][npc][cs]
+  const int ch = blockIdx.x, c0 = blockIdx.y * cs, comp = blockIdx.z;
+  const int cw = min(cs, nc - c0);
   const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, Kp = P.K;
-  const int half = npc / 2;
+  const int hc = npc / 2;
   const int m = parent[ch], oc = octant[ch];
-  const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift);
-  const C2<R>* g = Gp + (int64_t)m * 2 * Kp * nc;
-  for (int e = threadIdx.x; e < 2 * ntp * npc; e += blockDim.x) {
-    const int uc = e % npc, tp = (e / npc) % ntp, comp = e / (npc * ntp);
-    C2<R> acc = mk<R>(0, 0);
-    for (int j = P.pht_ptr[uc]; j < P.pht_ptr[uc + 1]; ++j) {
-      const int up = P.pht_idx[j];
-      const R w = P.pht_w[j];
-      const C2<R> v = g[((int64_t)comp * Kp + tp * npp + up) * nc + c];
-      const C2<R> sh = shift[oc * Kp + tp * npp + up];
-      C2<R> t = mk<R>(0, 0);
-      t = cfma_conj(t, sh, v);
-      acc.x = fma(w, t.x, acc.x);
-      acc.y = fma(w, t.y, acc.y);
+  const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift) + oc * Kp;
+  const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+  for (int e = threadIdx.x; e < ntp * npc * cs; e += blockDim.x) {
+    const int c = e % cs, uc = (e / cs) % npc, tp = e / (cs * npc);
+    C2<R> a = mk<R>(0, 0);
+    if (c < cw) {
+      for (int j = P.pht_ptr[uc]; j < P.pht_ptr[uc + 1]; ++j) {
+        const int up = P.pht_idx[j];
+        const R w = P.pht_w[j];
+        const C2<R> v = g[(int64_t)(tp * npp + up) * nc + c];
+        C2<R> t = mk<R>(0, 0);
+        t = cfma_conj(t, shift[tp * npp + up], v);
+        a.x = fma(w, t.x, a.x);
+        a.y = fma(w, t.y, a.y);
+      }
     }
-    tmp[e] = acc;
+    tmp[e] = a;
   }
   __syncthreads();
-  C2<R>* out = Gc + (int64_t)ch * 2 * Kc * nc;
-  for (int e = threadIdx.x; e < 2 * Kc; e += blockDim.x) {
-    const int uc = e % npc, tc = (e / npc) % ntc, comp = e / (npc * ntc);
-    C2<R> acc = mk<R>(0, 0);
+  C2<R>* out = Gc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
+  for (int e = threadIdx.x; e < ntc * npc * cs; e += blockDim.x) {
+    const int c = e % cs, uc = (e / cs) % npc, tc = e / (cs * npc);
+    if (c >= cw) continue;
+    C2<R> a = mk<R>(0, 0);
     for (int j = P.tht_ptr[tc]; j < P.tht_ptr[tc + 1]; ++j) {
       const int tp = P.tht_idx[j];
       const int rf = P.tht_ref[j];
       const R w = rf ? -P.tht_w[j] : P.tht_w[j];
-      const C2<R> v = tmp[(comp * ntp + tp) * npc + (rf ? (uc + half) % npc : uc)];
-      acc.x = fma(w, v.x, acc.x);
-      acc.y = fma(w, v.y, acc.y);
+      const C2<R> v = tmp[(tp * npc + (rf ? (uc + hc) % npc : uc)) * cs + c];
+      a.x = fma(w, v.x, a.x);
+      a.y = fma(w, v.y, a.y);
     }
-    C2<R>& o = out[(int64_t)e * nc + c];
-    o.x += acc.x;
-    o.y += acc.y;
+    C2<R>& o = out[(int64_t)(tc * npc + uc) * nc + c];
+    o.x += a.x;
+    o.y += a.y;
+  }
+}
+
+
+// Staged variants (used whenever both LDS grids fit): the input grid of the
+// block is copied to LDS once (coalesced), the phi stencil runs LDS -> LDS, the
+// theta stencil reads LDS.  Interpolation: A = child [ntc][npc][cs],
+// B = [ntc][npp][cs].  Anterpolation: A = conj-shifted parent [ntp][npp][cs],
+// B = [ntp][npc][cs].
+template <typename R, int JMAX>
+__global__ void __launch_bounds__(256) k_interp_up(const C2<R>* __restrict__ Sc, C2<R>* __restrict__ Sp,
+                                                   const int32_t* __restrict__ child_ptr,
+                                                   const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
+                                                   int cs, int tpc) {
+  extern __shared__ unsigned char smem_raw[];
+  const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, p = P.p, Kp = P.K;
+  C2<R>* A = reinterpret_cast<C2<R>*>(smem_raw);            // [ntc][npc][cs]
+  C2<R>* B = A + ntc * npc * cs;                             // [ntc][npp][cs]
+  // stencil tables: phi (index, weight) per parent phi, theta (index | reflect<<30, weight) per parent theta
+  R* phW = reinterpret_cast<R*>(B + ntc * npp * cs);       // weights first (alignment)
+  R* thW = phW + npp * p;
+  int32_t* phI = reinterpret_cast<int32_t*>(thW + ntp * p);
+  int32_t* thI = phI + npp * p;
+  for (int e = threadIdx.x; e < npp * p; e += blockDim.x) {
+    phI[e] = P.ph_idx[e] * cs;
+    phW[e] = P.ph_w[e];
+  }
+  for (int e = threadIdx.x; e < ntp * p; e += blockDim.x) {
+    thI[e] = P.th_idx[e] | (P.th_ref[e] << 30);
+    thW[e] = P.th_ref[e] ? -P.th_w[e] : P.th_w[e];
+  }
+  const int nchunk = (ntp + tpc - 1) / tpc;
+  const int m = blockIdx.x / nchunk, tp0 = (blockIdx.x % nchunk) * tpc;
+  const int c0 = blockIdx.y * cs, comp = blockIdx.z;
+  const int cw = min(cs, nc - c0);
+  const int hp = npp / 2;
+  const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift);
+  const int nout = min(tpc, ntp - tp0) * npp * cs;
+  C2<R> acc[JMAX];
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) acc[j] = mk<R>(0, 0);
+  for (int ch = child_ptr[m]; ch < child_ptr[m + 1]; ++ch) {
+    const C2<R>* src = Sc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
+    const int oc = octant[ch];
+    __syncthreads();
+    for (int e = threadIdx.x; e < Kc * cs; e += blockDim.x) {
+      const int c = e % cs, q = e / cs;
+      A[e] = (c < cw) ? src[(int64_t)q * nc + c] : mk<R>(0, 0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ntc * npp * cs; e += blockDim.x) {
+      const int c = e % cs, up = (e / cs) % npp, tc = e / (cs * npp);
+      const C2<R>* row = A + tc * npc * cs + c;
+      const int32_t* ii = phI + up * p;
+      const R* ww = phW + up * p;
+      C2<R> a = mk<R>(0, 0);
+      for (int j = 0; j < p; ++j) {
+        const R w = ww[j];
+        const C2<R> v = row[ii[j]];
+        a.x = fma(w, v.x, a.x);
+        a.y = fma(w, v.y, a.y);
+      }
+      B[e] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+      const int o = threadIdx.x + j * blockDim.x;
+      if (o < nout) {
+        const int c = o % cs, up = (o / cs) % npp, tp = tp0 + o / (cs * npp);
+        const int upr = (up + hp) % npp;
+        C2<R> a = mk<R>(0, 0);
+        for (int t = 0; t < p; ++t) {
+          const int code = thI[tp * p + t];
+          const int tc = code & 0x3fffffff;
+          const R w = thW[tp * p + t];
+          const C2<R> v = B[(tc * npp + ((code >> 30) ? upr : up)) * cs + c];
+          a.x = fma(w, v.x, a.x);
+          a.y = fma(w, v.y, a.y);
+        }
+        acc[j] = cfma(acc[j], a, shift[oc * Kp + tp * npp + up]);
+      }
+    }
+  }
+  C2<R>* out = Sp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) {
+    const int o = threadIdx.x + j * blockDim.x;
+    if (o < nout) {
+      const int c = o % cs, q = tp0 * npp + o / cs;
+      if (c < cw) out[(int64_t)q * nc + c] = acc[j];
+    }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ Gp, C2<R>* __restrict__ Gc,
+                                                     const int32_t* __restrict__ parent,
+                                                     const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
+                                                     int cs) {
+  extern __shared__ unsigned char smem_raw[];
+  const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, Kp = P.K;
+  C2<R>* A = reinterpret_cast<C2<R>*>(smem_raw);            // [ntp][npp][cs]
+  C2<R>* B = A + Kp * cs;                                    // [ntp][npc][cs]
+  // transposed stencils (CSR) copied to LDS
+  const int nph = P.pht_ptr[npc], nth = P.tht_ptr[ntc];
+  R* phW = reinterpret_cast<R*>(B + ntp * npc * cs);       // weights first (alignment)
+  R* thW = phW + nph;
+  int32_t* phP = reinterpret_cast<int32_t*>(thW + nth);
+  int32_t* thP = phP + npc + 1;
+  int32_t* phI = thP + ntc + 1;
+  int32_t* thI = phI + nph;
+  for (int e = threadIdx.x; e <= npc; e += blockDim.x) phP[e] = P.pht_ptr[e];
+  for (int e = threadIdx.x; e <= ntc; e += blockDim.x) thP[e] = P.tht_ptr[e];
+  for (int e = threadIdx.x; e < nph; e += blockDim.x) {
+    phI[e] = P.pht_idx[e] * cs;
+    phW[e] = P.pht_w[e];
+  }
+  for (int e = threadIdx.x; e < nth; e += blockDim.x) {
+    thI[e] = P.tht_idx[e] | (P.tht_ref[e] << 30);
+    thW[e] = P.tht_ref[e] ? -P.tht_w[e] : P.tht_w[e];
+  }
+  const int ch = blockIdx.x, c0 = blockIdx.y * cs, comp = blockIdx.z;
+  const int cw = min(cs, nc - c0);
+  const int hc = npc / 2;
+  const int m = parent[ch], oc = octant[ch];
+  const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift) + oc * Kp;
+  const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+  for (int e = threadIdx.x; e < Kp * cs; e += blockDim.x) {
+    const int c = e % cs, q = e / cs;
+    C2<R> t = mk<R>(0, 0);
+    if (c < cw) t = cfma_conj(t, shift[q], g[(int64_t)q * nc + c]);
+    A[e] = t;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ntp * npc * cs; e += blockDim.x) {
+    const int c = e % cs, uc = (e / cs) % npc, tp = e / (cs * npc);
+    const C2<R>* row = A + tp * npp * cs + c;
+    C2<R> a = mk<R>(0, 0);
+    for (int j = phP[uc]; j < phP[uc + 1]; ++j) {
+      const R w = phW[j];
+      const C2<R> v = row[phI[j]];
+      a.x = fma(w, v.x, a.x);
+      a.y = fma(w, v.y, a.y);
+    }
+    B[e] = a;
+  }
+  __syncthreads();
+  C2<R>* out = Gc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
+  for (int e = threadIdx.x; e < ntc * npc * cs; e += blockDim.x) {
+    const int c = e % cs, uc = (e / cs) % npc, tc = e / (cs * npc);
+    if (c >= cw) continue;
+    const int ucr = (uc + hc) % npc;
+    C2<R> a = mk<R>(0, 0);
+    for (int j = thP[tc]; j < thP[tc + 1]; ++j) {
+      const int code = thI[j];
+      const int tp = code & 0x3fffffff;
+      const R w = thW[j];
+      const C2<R> v = B[(tp * npc + ((code >> 30) ? ucr : uc)) * cs + c];
+      a.x = fma(w, v.x, a.x);
+      a.y = fma(w, v.y, a.y);
+    }
+    C2<R>& o = out[(int64_t)(tc * npc + uc) * nc + c];
+    o.x += a.x;
+    o.y += a.y;
   }
 }
 
 // ---------------------------------------------------------------- disaggregation
 // y_i = y_near_i + sum_q (k^2 eta/4pi) w_q conj(V_i(q)) . G_box(i)(q), written to
-// the public position perm[i] (conjugated for Z^H).  One wavefront per unknown.
+// the public position perm[i] (conjugated for Z^H).  nc == 1: one wavefront
+// per unknown, lanes over directions.
 template <typename R>
-__global__ void __launch_bounds__(256) k_disagg(const C2<R>* __restrict__ V, const C2<R>* __restrict__ G,
-                                                const R* __restrict__ qwc, const C2<R>* __restrict__ yi,
-                                                const int32_t* __restrict__ box_of, const int32_t* __restrict__ perm,
-                                                int K, int nc, int64_t N, C2<R>* __restrict__ y, int64_t ld,
-                                                int conj_out) {
+__global__ void __launch_bounds__(256) k_disagg1(const C2<R>* __restrict__ V, const C2<R>* __restrict__ G,
+                                                 const R* __restrict__ qwc, const C2<R>* __restrict__ yi,
+                                                 const int32_t* __restrict__ box_of, const int32_t* __restrict__ perm,
+                                                 int K, int64_t N, C2<R>* __restrict__ y, int64_t ld, int conj_out) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= N) return;
-  const int NC = pow2ceil(nc);
-  const int S = 64 / NC;
-  const int c = lane % NC, s = lane / NC;
   const int b = box_of[i];
   const C2<R>* v = V + i * 2 * K;
-  const C2<R>* g = G + (int64_t)b * 2 * K * nc;
+  const C2<R>* g = G + (int64_t)b * 2 * K;
   R ax = 0, ay = 0;
-  if (c < nc) {
-    for (int cq = s; cq < 2 * K; cq += S) {
-      const R w = qwc[cq % K];
-      const C2<R> a = v[cq];
-      const C2<R> gg = g[(int64_t)cq * nc + c];
-      // w conj(a) gg
-      ax = fma(w * a.x, gg.x, ax);
-      ax = fma(w * a.y, gg.y, ax);
-      ay = fma(w * a.x, gg.y, ay);
-      ay = fma(-w * a.y, gg.x, ay);
-    }
+  for (int cq = lane; cq < 2 * K; cq += 64) {
+    const R w = qwc[cq < K ? cq : cq - K];
+    const C2<R> a = v[cq];
+    const C2<R> gg = g[cq];
+    ax = fma(w * a.x, gg.x, ax);
+    ax = fma(w * a.y, gg.y, ax);
+    ay = fma(w * a.x, gg.y, ay);
+    ay = fma(-w * a.y, gg.x, ay);
   }
-  for (int o = NC; o < 64; o <<= 1) {
+  for (int o = 1; o < 64; o <<= 1) {
     ax += __shfl_xor(ax, o, 64);
     ay += __shfl_xor(ay, o, 64);
   }
-  if (s == 0 && c < nc) {
-    C2<R> r = yi[i * nc + c];
+  if (lane == 0) {
+    C2<R> r = yi[i];
     r.x += ax;
     r.y += ay;
     if (conj_out) r.y = -r.y;
-    y[(int64_t)perm[i] * ld + c] = r;
+    y[(int64_t)perm[i] * ld] = r;
+  }
+}
+
+// Batched: one block per leaf box, thread = (unknown of the box, CG columns).
+template <typename R, int CG>
+__global__ void __launch_bounds__(256) k_disagg(const C2<R>* __restrict__ V, const C2<R>* __restrict__ G,
+                                                const R* __restrict__ qwc, const C2<R>* __restrict__ yi,
+                                                const int32_t* __restrict__ box_start,
+                                                const int32_t* __restrict__ perm, int K, int nc,
+                                                C2<R>* __restrict__ y, int64_t ld, int conj_out) {
+  const int b = blockIdx.x;
+  const int j0 = box_start[b], nb = box_start[b + 1] - j0;
+  const int ncg = nc / CG;
+  const C2<R>* g = G + (int64_t)b * 2 * K * nc;
+  for (int o = threadIdx.x; o < nb * ncg; o += blockDim.x) {
+    const int cg = o % ncg, ii = o / ncg;
+    const int64_t i = j0 + ii;
+    const C2<R>* v = V + i * 2 * K;
+    C2<R> acc[CG];
+#pragma unroll
+    for (int u = 0; u < CG; ++u) acc[u] = mk<R>(0, 0);
+    for (int cq = 0; cq < 2 * K; ++cq) {
+      const R w = qwc[cq < K ? cq : cq - K];
+      C2<R> a = v[cq];
+      a.x *= w;
+      a.y *= w;
+      const C2<R>* gr = g + (int64_t)cq * nc + cg * CG;
+#pragma unroll
+      for (int u = 0; u < CG; ++u) acc[u] = cfma_conj(acc[u], a, gr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < CG; ++u) {
+      C2<R> r = yi[i * nc + cg * CG + u];
+      r.x += acc[u].x;
+      r.y += acc[u].y;
+      if (conj_out) r.y = -r.y;
+      y[(int64_t)perm[i] * ld + cg * CG + u] = r;
+    }
   }
 }
 
@@ -333,8 +616,61 @@ static inline void chk(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(-4, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static void check_lds(size_t bytes) {
-  if (bytes > 65536) throw Error(-7, "angular grid too large for the one-tile interpolation kernel (LDS > 64 KiB)");
+static hipEvent_t take_event(Dev& d) {
+  if (!d.event_pool.empty()) {
+    hipEvent_t e = d.event_pool.back();
+    d.event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  chk(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+void stage_begin(Dev& d, hipStream_t s, int stage) {
+  if (!d.timing) return;
+  if (d.marks.size() > 65536) collect_stage_times(d);
+  Dev::Mark m{stage, take_event(d), take_event(d)};
+  chk(hipEventRecord(m.a, s), "hipEventRecord");
+  d.marks.push_back(m);
+}
+
+void stage_end(Dev& d, hipStream_t s) {
+  if (!d.timing) return;
+  chk(hipEventRecord(d.marks.back().b, s), "hipEventRecord");
+}
+
+void collect_stage_times(Dev& d) {
+  if (d.stage_ms.size() < 256) {
+    d.stage_ms.assign(256, 0.0);
+    d.stage_calls.assign(256, 0);
+  }
+  for (auto& m : d.marks) {
+    chk(hipEventSynchronize(m.b), "hipEventSynchronize");
+    float ms = 0.f;
+    chk(hipEventElapsedTime(&ms, m.a, m.b), "hipEventElapsedTime");
+    d.stage_ms[m.stage] += ms;
+    d.stage_calls[m.stage] += 1;
+    d.event_pool.push_back(m.a);
+    d.event_pool.push_back(m.b);
+  }
+  d.marks.clear();
+}
+
+// column slice width for the interpolation kernels: the LDS grid and the
+// per-thread register outputs must fit
+template <typename R>
+static int interp_cs(int nc, int rows_lds, int cols_lds, int nout_per_col, int jmax, int threads) {
+  const size_t lds_cap = 64 * 1024;
+  int cs = nc;
+  while (cs > 1 && ((size_t)rows_lds * cols_lds * cs * sizeof(C2<R>) > lds_cap || nout_per_col * cs > jmax * threads))
+    --cs;
+  return cs;
+}
+
+static void set_lds_limit(const void* f, size_t bytes) {
+  if (bytes > 64 * 1024) chk(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
+                             "hipFuncSetAttribute");
 }
 
 template <typename R>
@@ -349,47 +685,123 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   const int kind = (op == 1) ? 1 : (op == 2) ? 2 : 0;   // 0 Z, 1 R, 2 X
   {
     int64_t tot = N * nc;
+    stage_begin(d, s, 0);
     hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
                        d.perm, xi, N, conj);
+    stage_end(d, s);
   }
   const dim3 rows_grid((unsigned)((N + 3) / 4));
+  stage_begin(d, s, 1);
   hipLaunchKernelGGL(k_near<R>, rows_grid, dim3(256), 0, s, d.row_ptr, d.box_of, d.bcol_ptr, d.bcol, d.self_off,
                      d.box_start, (const double2*)d.Zn, (const CR*)xi, yi, N, nc, kind);
+  stage_end(d, s);
   // upward pass
   {
     const int K = P.lev[lf].K;
-    int gy = std::max(1, std::min(8, (2 * K * nc + 255) / 256));
-    hipLaunchKernelGGL(k_aggregate<R>, dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)pd.V, (const CR*)xi,
-                       (CR*)d.S[lf], d.box_start, K, nc);
+    stage_begin(d, s, 2);
+    if (nc % 4 == 0) {
+      int tot = 2 * K * nc / 4;
+      int gy = std::max(1, std::min(16, (tot + 255) / 256));
+      hipLaunchKernelGGL((k_aggregate<R, 4>), dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)pd.V, (const CR*)xi,
+                         (CR*)d.S[lf], d.box_start, K, nc);
+    } else {
+      int tot = 2 * K * nc;
+      int gy = std::max(1, std::min(16, (tot + 255) / 256));
+      hipLaunchKernelGGL((k_aggregate<R, 1>), dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)pd.V, (const CR*)xi,
+                         (CR*)d.S[lf], d.box_start, K, nc);
+    }
+    stage_end(d, s);
   }
+  constexpr int kJ = sizeof(R) == 4 ? 16 : 8;
   for (int l = lf - 1; l >= 2; --l) {
     LevelD<R>& Lp = pd.lev[l];
-    size_t sh = (size_t)2 * Lp.nt * Lp.npc * sizeof(CR);
-    check_lds(sh);
-    hipLaunchKernelGGL(k_interp_up<R>, dim3(Lp.nbox, nc), dim3(256), sh, s, (const CR*)d.S[l + 1], (CR*)d.S[l],
-                       Lp.child_ptr, pd.lev[l + 1].octant, Lp, P.lev[l + 1].K, nc);
+    const int Kc = P.lev[l + 1].K;
+    const int per_col = (Lp.ntc * Lp.npc + Lp.ntc * Lp.np) * (int)sizeof(CR);   // staged LDS per column
+    const int tables = (Lp.np + Lp.nt) * Lp.p * (4 + (int)sizeof(R));
+    const dim3 blk(256);
+    stage_begin(d, s, 3 + 10 * l);
+    if (per_col + tables <= 96 * 1024 && Lp.np <= kJ * 256) {
+      int cs = std::max(1, std::min(nc, (64 * 1024 - tables) / per_col));
+      while (cs > 1 && std::min(Lp.nt * Lp.np, kJ * 256) * cs > kJ * 256) --cs;
+      const int tpc = std::max(1, std::min(Lp.nt, kJ * 256 / (Lp.np * cs)));
+      const int nchunk = (Lp.nt + tpc - 1) / tpc;
+      const size_t sh = (size_t)per_col * cs + tables;
+      set_lds_limit((const void*)k_interp_up<R, kJ>, sh);
+      hipLaunchKernelGGL((k_interp_up<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s,
+                         (const CR*)d.S[l + 1], (CR*)d.S[l], Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc);
+    } else {
+      const int cs = interp_cs<R>(nc, Lp.ntc, Lp.np, std::min(Lp.nt * Lp.np, kJ * 256), kJ, 256);
+      const int tpc = std::max(1, std::min(Lp.nt, kJ * 256 / (Lp.np * cs)));
+      const int nchunk = (Lp.nt + tpc - 1) / tpc;
+      const size_t sh = (size_t)Lp.ntc * Lp.np * cs * sizeof(CR);
+      if (sh > 160 * 1024 || tpc * Lp.np * cs > kJ * 256)
+        throw Error(-7, "angular grid too large for the interpolation kernel");
+      set_lds_limit((const void*)k_interp_up_direct<R, kJ>, sh);
+      hipLaunchKernelGGL((k_interp_up_direct<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s,
+                         (const CR*)d.S[l + 1], (CR*)d.S[l], Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc);
+    }
+    stage_end(d, s);
   }
   // translations
   for (int l = 2; l <= lf; ++l) {
     LevelD<R>& Lv = pd.lev[l];
     const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
-    const int32_t* ptr = (kind == 1) ? Lv.farR_ptr : Lv.far_ptr;
-    const int32_t* src = (kind == 1) ? Lv.farR_src : Lv.far_src;
-    const int32_t* off = (kind == 1) ? Lv.farR_off : Lv.far_off;
-    int gy = (2 * Lv.K * nc + 255) / 256;
-    hipLaunchKernelGGL(k_m2l<R>, dim3(Lv.nbox, gy), dim3(256), 0, s, ptr, src, off, (const CR*)T,
-                       (const CR*)d.S[l], (CR*)d.G[l], Lv.K, nc);
+    const int32_t* tptr = (kind == 1) ? Lv.tileR_ptr : Lv.tile_ptr;
+    const int32_t* tsrc = (kind == 1) ? Lv.tileR_src : Lv.tile_src;
+    const int16_t* toff = (kind == 1) ? Lv.tileR_off : Lv.tile_off;
+    const int cw = std::min(nc, 32);
+    const int threads = (nc == 1) ? 64 : 256;           // single vector: more, smaller blocks
+    const int qb = threads / cw;
+    const size_t sh = (size_t)Lv.n_off * qb * sizeof(CR);
+    const bool stage = (cw >= 8) && sh <= 64 * 1024;
+    dim3 grid(Lv.ntile, (Lv.K + qb - 1) / qb, (nc + cw - 1) / cw);
+    stage_begin(d, s, 4 + 10 * l);
+    if (stage)
+      hipLaunchKernelGGL((k_m2l<R, true>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off,
+                         (const CR*)d.S[l], (CR*)d.G[l], Lv.nbox, Lv.K, nc, cw);
+    else
+      hipLaunchKernelGGL((k_m2l<R, false>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off,
+                         (const CR*)d.S[l], (CR*)d.G[l], Lv.nbox, Lv.K, nc, cw);
+    stage_end(d, s);
   }
   // downward pass
   for (int l = 2; l < lf; ++l) {
     LevelD<R>& Lp = pd.lev[l];
-    size_t sh = (size_t)2 * Lp.nt * Lp.npc * sizeof(CR);
-    check_lds(sh);
-    hipLaunchKernelGGL(k_anterp_down<R>, dim3(pd.lev[l + 1].nbox, nc), dim3(256), sh, s, (const CR*)d.G[l],
-                       (CR*)d.G[l + 1], pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, P.lev[l + 1].K, nc);
+    const int Kc = P.lev[l + 1].K;
+    const int per_col = (Lp.nt * Lp.np + Lp.nt * Lp.npc) * (int)sizeof(CR);
+    const Interp& Ip = P.ip[l];
+    const int tables = (Lp.npc + 1 + Lp.ntc + 1) * 4 +
+                       (int)(Ip.pht_idx.size() + Ip.tht_idx.size()) * (4 + (int)sizeof(R)) + 16;
+    stage_begin(d, s, 5 + 10 * (l + 1));
+    if (per_col + tables <= 96 * 1024) {
+      const int cs = std::max(1, std::min(nc, (64 * 1024 - tables) / per_col));
+      const size_t sh = (size_t)per_col * cs + tables;
+      set_lds_limit((const void*)k_anterp_down<R>, sh);
+      hipLaunchKernelGGL(k_anterp_down<R>, dim3(pd.lev[l + 1].nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s,
+                         (const CR*)d.G[l], (CR*)d.G[l + 1], pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc,
+                         cs);
+    } else {
+      const int cs = interp_cs<R>(nc, Lp.nt, Lp.npc, 0, 1, 1);
+      const size_t sh = (size_t)Lp.nt * Lp.npc * cs * sizeof(CR);
+      if (sh > 160 * 1024) throw Error(-7, "anterpolation LDS grid exceeds 160 KiB");
+      set_lds_limit((const void*)k_anterp_down_direct<R>, sh);
+      hipLaunchKernelGGL(k_anterp_down_direct<R>, dim3(pd.lev[l + 1].nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s,
+                         (const CR*)d.G[l], (CR*)d.G[l + 1], pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc,
+                         cs);
+    }
+    stage_end(d, s);
   }
-  hipLaunchKernelGGL(k_disagg<R>, rows_grid, dim3(256), 0, s, (const CR*)pd.V, (const CR*)d.G[lf],
-                     (const R*)pd.qwc, (const CR*)yi, d.box_of, d.perm, P.lev[lf].K, nc, N, (CR*)y, ld, conj);
+  stage_begin(d, s, 6);
+  if (nc == 1)
+    hipLaunchKernelGGL(k_disagg1<R>, rows_grid, dim3(256), 0, s, (const CR*)pd.V, (const CR*)d.G[lf],
+                       (const R*)pd.qwc, (const CR*)yi, d.box_of, d.perm, P.lev[lf].K, N, (CR*)y, ld, conj);
+  else if (nc % 4 == 0)
+    hipLaunchKernelGGL((k_disagg<R, 4>), dim3(d.nleaf), dim3(256), 0, s, (const CR*)pd.V, (const CR*)d.G[lf],
+                       (const R*)pd.qwc, (const CR*)yi, d.box_start, d.perm, P.lev[lf].K, nc, (CR*)y, ld, conj);
+  else
+    hipLaunchKernelGGL((k_disagg<R, 1>), dim3(d.nleaf), dim3(256), 0, s, (const CR*)pd.V, (const CR*)d.G[lf],
+                       (const R*)pd.qwc, (const CR*)yi, d.box_start, d.perm, P.lev[lf].K, nc, (CR*)y, ld, conj);
+  stage_end(d, s);
   chk(hipGetLastError(), "apply launch");
 }
 
@@ -409,8 +821,10 @@ static void sai_apply_impl(Dev& d, const void* x, void* y, int64_t ld, int nc, h
   int64_t tot = N * nc;
   hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
                      d.perm, (CR*)d.xi, N, 0);
+  stage_begin(d, s, 7);
   hipLaunchKernelGGL(k_sai_apply<R>, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, d.sai_ptr, d.sai_col,
                      (const double2*)d.sai_val, (const CR*)d.xi, d.perm, (CR*)y, ld, N, nc);
+  stage_end(d, s);
   chk(hipGetLastError(), "sai apply launch");
 }
 

@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -75,6 +77,14 @@ static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<in
     D.farR_off = lists[8 * l + 5];
     D.child_ptr = lists[8 * l + 6];
     D.parent = lists[8 * l + 7];
+    D.n_off = Lv.n_off_used;
+    D.ntile = (Lv.nbox + kTile - 1) / kTile;
+    D.tile_ptr = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 0];
+    D.tile_src = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 1];
+    D.tile_off = reinterpret_cast<int16_t*>(lists[8 * (lf + 1) + (lf + 1) + 6 * l + 2]);
+    D.tileR_ptr = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 3];
+    D.tileR_src = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 4];
+    D.tileR_off = reinterpret_cast<int16_t*>(lists[8 * (lf + 1) + (lf + 1) + 6 * l + 5]);
     D.TZ = upload_complex<R>(d, P.TZ[l], s);
     D.TR = upload_complex<R>(d, P.TR[l], s);
     D.TX = upload_complex<R>(d, P.TX[l], s);
@@ -159,7 +169,7 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
     d.leaf_dirs = upload(d, P.dirs[lf], s);
   }
   // index lists shared by both precisions
-  std::vector<int32_t*> lists(8 * (lf + 1) + lf + 1, nullptr);
+  std::vector<int32_t*> lists(8 * (lf + 1) + (lf + 1) + 6 * (lf + 1), nullptr);
   for (int l = 2; l <= lf; ++l) {
     const Level& Lv = P.lev[l];
     lists[8 * l + 0] = upload(d, Lv.far_ptr, s);
@@ -173,6 +183,13 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
     std::vector<int8_t> oc(Lv.nbox);
     for (int b = 0; b < Lv.nbox; ++b) oc[b] = (int8_t)(Lv.code[b] & 7);
     lists[8 * (lf + 1) + l] = reinterpret_cast<int32_t*>(upload(d, oc, s));
+    const int tb = 8 * (lf + 1) + (lf + 1) + 6 * l;
+    lists[tb + 0] = upload(d, Lv.tile_ptr, s);
+    lists[tb + 1] = upload(d, Lv.tile_src, s);
+    lists[tb + 2] = reinterpret_cast<int32_t*>(upload(d, Lv.tile_off, s));
+    lists[tb + 3] = upload(d, Lv.tileR_ptr, s);
+    lists[tb + 4] = upload(d, Lv.tileR_src, s);
+    lists[tb + 5] = reinterpret_cast<int32_t*>(upload(d, Lv.tileR_off, s));
   }
   std::vector<int32_t> dummy;
   build_prec<float>(d, P, d.f32, dummy, lists, s);
@@ -201,6 +218,13 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
 void dev_free(Dev& d) {
   for (void* p : d.allocs) (void)hipFree(p);
   d.allocs.clear();
+  for (auto& m : d.marks) {
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  d.marks.clear();
+  for (auto e : d.event_pool) (void)hipEventDestroy(e);
+  d.event_pool.clear();
 }
 
 void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipStream_t s);
@@ -420,6 +444,47 @@ cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* need
   if (!buf || buf_len < (int64_t)s.size() + 1) return fail(CM_E_BADARG, "buffer too small");
   std::memcpy(buf, s.c_str(), s.size() + 1);
   return CM_OK;
+}
+
+cm_status cm_stage_timing(cm_handle* h, int32_t enable) {
+  g_err.clear();
+  if (!h) return fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
+  CM_TRY({
+    cm::collect_stage_times(h->dev);
+    h->dev.timing = (enable != 0);
+    std::fill(h->dev.stage_ms.begin(), h->dev.stage_ms.end(), 0.0);
+    std::fill(h->dev.stage_calls.begin(), h->dev.stage_calls.end(), 0);
+    return CM_OK;
+  })
+}
+
+cm_status cm_stage_times(cm_handle* h, char* buf, int64_t buf_len, int64_t* needed) {
+  g_err.clear();
+  if (!h) return fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
+  CM_TRY({
+    cm::collect_stage_times(h->dev);
+    static const char* names[8] = {"permute", "near", "aggregate", "interp", "m2l", "anterp", "disagg", "sai"};
+    std::string s = "{";
+    bool first = true;
+    for (int id = 0; id < (int)h->dev.stage_ms.size(); ++id) {
+      if (!h->dev.stage_calls[id]) continue;
+      char item[128];
+      int base = id % 10, lvl = id / 10;
+      std::string nm = names[base];
+      if (base >= 3 && base <= 5) nm += "_l" + std::to_string(lvl);
+      std::snprintf(item, sizeof item, "%s\"%s\": {\"ms\": %.9g, \"calls\": %lld}", first ? "" : ", ", nm.c_str(),
+                    h->dev.stage_ms[id], (long long)h->dev.stage_calls[id]);
+      s += item;
+      first = false;
+    }
+    s += "}";
+    if (needed) *needed = (int64_t)s.size() + 1;
+    if (!buf || buf_len < (int64_t)s.size() + 1) return fail(CM_E_BADARG, "buffer too small");
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return CM_OK;
+  })
 }
 
 const char* cm_last_error(void) { return g_err.c_str(); }

@@ -31,7 +31,11 @@ struct LevelD {
   int32_t *farR_ptr = nullptr, *farR_src = nullptr, *farR_off = nullptr;
   int32_t *child_ptr = nullptr, *parent = nullptr;
   int8_t* octant = nullptr;                 // child position in its parent (code & 7)
-  void *TZ = nullptr, *TR = nullptr, *TX = nullptr, *dTZ = nullptr;  // kNoff x K complex<R>
+  int n_off = 0;                            // translators stored for the used offsets only
+  void *TZ = nullptr, *TR = nullptr, *TX = nullptr, *dTZ = nullptr;  // n_off x K complex<R>
+  int ntile = 0;
+  int32_t *tile_ptr = nullptr, *tile_src = nullptr, *tileR_ptr = nullptr, *tileR_src = nullptr;
+  int16_t *tile_off = nullptr, *tileR_off = nullptr;
   // interpolation from level l+1 into this level (l = 2..lf-1)
   int p = 0, ntc = 0, npc = 0;
   int32_t *th_idx = nullptr, *th_ref = nullptr, *ph_idx = nullptr;
@@ -73,7 +77,23 @@ struct Dev {
   int32_t* sai_col = nullptr;               // internal column indices
   double2* sai_val = nullptr;
   std::vector<void*> allocs;
+  // optional per-stage timing (HIP events on the apply stream)
+  bool timing = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<double> stage_ms;
+  std::vector<int64_t> stage_calls;
 };
+
+// stage ids for timing: 0 permute, 1 near, 2 aggregate, 3 interp, 4 m2l,
+// 5 anterp, 6 disagg, 7 sai; the level is added as 10*l for per-level stages.
+void stage_begin(Dev& d, hipStream_t s, int stage);
+void stage_end(Dev& d, hipStream_t s);
+void collect_stage_times(Dev& d);
 
 void dev_build(Dev& d, const Plan& P, hipStream_t s);
 void dev_free(Dev& d);

@@ -470,13 +470,19 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     for (int32_t f : Lv.farR_off) off_used[l][f] = 1;
     for (int32_t f : Lv.far_off) off_used[l][f] = 1;
     const int K = Lv.K, Lt = Lv.L;
-    TZ[l].assign((size_t)kNoff * K, cplx(0));
-    TR[l].assign((size_t)kNoff * K, cplx(0));
-    TX[l].assign((size_t)kNoff * K, cplx(0));
-    if (want_d) dTZ[l].assign((size_t)kNoff * K, cplx(0));
     std::vector<int> offs;
+    Lv.off_compact.assign(kNoff, -1);
     for (int f = 0; f < kNoff; ++f)
-      if (off_used[l][f]) offs.push_back(f);
+      if (off_used[l][f]) {
+        Lv.off_compact[f] = (int32_t)offs.size();
+        offs.push_back(f);
+      }
+    Lv.n_off_used = (int)offs.size();
+    const size_t nu = std::max<size_t>(1, offs.size());
+    TZ[l].assign(nu * K, cplx(0));
+    TR[l].assign(nu * K, cplx(0));
+    TX[l].assign(nu * K, cplx(0));
+    if (want_d) dTZ[l].assign(nu * K, cplx(0));
     parallel_for((int64_t)offs.size(), [&](int64_t oi) {
       int f = offs[oi];
       int dx = f / 49 - 3, dy = (f / 7) % 7 - 3, dz = f % 7 - 3;
@@ -517,7 +523,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
           sx += cx[n] * P;
           sd += cd[n] * P;
         }
-        size_t idx = (size_t)f * K + q;
+        size_t idx = (size_t)oi * K + q;
         TZ[l][idx] = sz;
         TR[l][idx] = sr;
         TX[l][idx] = sx;
@@ -527,6 +533,40 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     for (size_t i = 0; i < TZ[l].size(); ++i)
       if (!std::isfinite(TZ[l][i].real()) || !std::isfinite(TZ[l][i].imag()))
         throw Error(-6, "non-finite translator entry");
+  }
+
+  // ---- receiver tiles for the translation kernel
+  for (int l = 2; l <= lf; ++l) {
+    Level& Lv = lev[l];
+    auto make = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& src,
+                    const std::vector<int32_t>& off, std::vector<int32_t>& tptr, std::vector<int32_t>& tsrc,
+                    std::vector<int16_t>& toff) {
+      const int ntile = (Lv.nbox + kTile - 1) / kTile;
+      tptr.assign(ntile + 1, 0);
+      for (int t = 0; t < ntile; ++t) {
+        std::vector<std::pair<int, std::pair<int, int>>> ent;   // (source, (receiver slot, compact off))
+        for (int r = 0; r < kTile; ++r) {
+          int m = t * kTile + r;
+          if (m >= Lv.nbox) break;
+          for (int e = ptr[m]; e < ptr[m + 1]; ++e) ent.push_back({src[e], {r, Lv.off_compact[off[e]]}});
+        }
+        std::sort(ent.begin(), ent.end());
+        size_t i = 0;
+        while (i < ent.size()) {
+          int sbox = ent[i].first;
+          tsrc.push_back(sbox);
+          size_t base = toff.size();
+          toff.resize(base + kTile, (int16_t)-1);
+          while (i < ent.size() && ent[i].first == sbox) {
+            toff[base + ent[i].second.first] = (int16_t)ent[i].second.second;
+            ++i;
+          }
+        }
+        tptr[t + 1] = (int32_t)tsrc.size();
+      }
+    };
+    make(Lv.far_ptr, Lv.far_src, Lv.far_off, Lv.tile_ptr, Lv.tile_src, Lv.tile_off);
+    make(Lv.farR_ptr, Lv.farR_src, Lv.farR_off, Lv.tileR_ptr, Lv.tileR_src, Lv.tileR_off);
   }
 
   // ---- interpolation (child l+1 -> parent l, l = 2..lf-1) and shift phases
@@ -666,14 +706,15 @@ std::string Plan::stats_json() const {
   s.precision(17);
   s << "{\"N\": " << rwg.N << ", \"n_tri\": " << nt << ", \"k\": " << k << ", \"nlv\": " << nlv
     << ", \"d0\": " << opt.d0 << ", \"interp_p\": " << opt.p << ", \"root_side\": " << side
-    << ", \"nnz_near\": " << nnz << ", \"levels\": [";
+    << ", \"nnz_near\": " << nnz << ", \"near_cols_total\": " << bcol.size()
+    << ", \"n_leaf\": " << lev[lf].nbox << ", \"levels\": [";
   for (int l = 0; l <= lf; ++l) {
     const Level& Lv = lev[l];
     if (l) s << ", ";
     s << "{\"l\": " << l << ", \"a\": " << Lv.a << ", \"nbox\": " << Lv.nbox << ", \"L\": " << Lv.L
       << ", \"nt\": " << Lv.nt << ", \"np\": " << Lv.np << ", \"K\": " << Lv.K
       << ", \"far_pairs\": " << (Lv.far_src.size()) << ", \"farR_pairs\": " << (Lv.farR_src.size())
-      << "}";
+      << ", \"tile_sources\": " << Lv.tile_src.size() << ", \"n_off_used\": " << Lv.n_off_used << "}";
   }
   s << "]}";
   return s.str();

@@ -41,7 +41,17 @@ struct Level {
   // translation lists (receiver-major CSR): source box and offset id
   std::vector<int32_t> far_ptr, far_src, far_off;     // Z and X
   std::vector<int32_t> farR_ptr, farR_src, farR_off;  // R (leaf level adds neighbours)
+  // receiver tiles of kTile consecutive boxes: union of their sources and, per
+  // (tile, source), the compact translator index for each receiver (-1: none)
+  std::vector<int32_t> tile_ptr, tile_src;
+  std::vector<int16_t> tile_off;
+  std::vector<int32_t> tileR_ptr, tileR_src;
+  std::vector<int16_t> tileR_off;
+  std::vector<int32_t> off_compact;                   // kNoff -> compact id (-1 unused)
+  int n_off_used = 0;
 };
+
+constexpr int kTile = 16;
 
 // Local Lagrange interpolation from level c = l+1 (child) to level l (parent),
 // separable: theta first (with reflection over the poles), then phi.
@@ -94,7 +104,7 @@ struct Plan {
   std::vector<int64_t> row_ptr;                // internal rows -> value offset (N+1)
   int64_t nnz = 0;
   // tables (FP64)
-  std::vector<std::vector<cplx>> TZ, TR, TX, dTZ;   // [level][kNoff*K] (used offsets only)
+  std::vector<std::vector<cplx>> TZ, TR, TX, dTZ;   // [level][n_off_used*K] (compact offset index)
   std::vector<std::vector<uint8_t>> off_used;        // [level][kNoff]
   std::vector<std::vector<cplx>> shift;             // [level l][8*K_l]: child l+1 -> l
   std::vector<std::vector<double>> qw;              // [level][K] quadrature weights

@@ -78,6 +78,18 @@ class Operator:
         check(lib().cm_stats(self._h, buf, need.value, C.byref(need)))
         return json.loads(buf.value.decode())
 
+    def stage_timing(self, enable=True):
+        """Enable (or disable) HIP-event timing of every kernel stage."""
+        check(lib().cm_stage_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage: {"ms": total milliseconds, "calls": launches}} since stage_timing()."""
+        need = C.c_int64()
+        lib().cm_stage_times(self._h, None, 0, C.byref(need))
+        buf = C.create_string_buffer(int(need.value) + 256)
+        check(lib().cm_stage_times(self._h, buf, need.value + 256, C.byref(need)))
+        return json.loads(buf.value.decode())
+
     def export_near(self, which=0):
         """Near-field (which=0), dZ_near/dk (1) or SAI (2) matrix as scipy CSR
         in public unknown order."""

@@ -1,0 +1,147 @@
+"""Host-side checks of the C-ABI library that need no GPU: symbol exports,
+the host plan (RWG order, octree, interaction lists) and argument/mesh error
+paths.  No compute call reaches the device here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.rwg import build_rwg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1412_1756_amd import _lib
+    return _lib.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "cmmlfma.h")).read()
+    declared = set(re.findall(r"\b(cm_[a-z_]+)\s*\(", hdr))
+    assert {"cm_create", "cm_apply", "cm_sai_apply", "cm_sai_build", "cm_destroy"} <= declared
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    from paper_1412_1756_amd import _lib
+    assert set(_lib.EXPORTS) == declared
+
+
+def _op(V, F, nlv, **kw):
+    from paper_1412_1756_amd import Operator
+    return Operator(V, F, 2 * np.pi, nlv=nlv, host_only=True, **kw)
+
+
+def test_rwg_order_matches_oracle():
+    for V, F in (workloads.icosphere(3, 0.5), workloads.plate(20, 12, 0.1)):
+        op = _op(V, F, 3)
+        e, t = op.rwg_table()
+        r = build_rwg(V, F)
+        assert op.N == r["N"]
+        np.testing.assert_array_equal(e, r["edge"])
+        np.testing.assert_array_equal(t, r["tri"])
+
+
+def _python_tree(V, F, nlv):
+    """Independent recount of boxes and far pairs (per level) from RWG midpoints."""
+    r = build_rwg(V, F)
+    mid = 0.5 * (V[r["edge"][:, 0]] + V[r["edge"][:, 1]])
+    lo, hi = V.min(0), V.max(0)
+    side = (hi - lo).max() * (1 + 1e-9)
+    origin = 0.5 * (lo + hi) - 0.5 * side
+    lf = nlv - 1
+    ijk = np.clip(np.floor((mid - origin) / (side / 2 ** lf)).astype(int), 0, 2 ** lf - 1)
+    leaf = np.unique(ijk, axis=0)
+    boxes = {lf: leaf}
+    for l in range(lf - 1, -1, -1):
+        boxes[l] = np.unique(boxes[l + 1] // 2, axis=0)
+    far = {}
+    for l in range(2, lf + 1):
+        B = boxes[l]
+        d = np.abs(B[:, None, :] - B[None, :, :]).max(-1)
+        P = B // 2
+        dp = np.abs(P[:, None, :] - P[None, :, :]).max(-1)
+        far[l] = int(np.sum((d >= 2) & (dp <= 1)))
+    leafd = np.abs(leaf[:, None, :] - leaf[None, :, :]).max(-1)
+    cnt = np.bincount([tuple(map(tuple, leaf)).index(tuple(x)) for x in ijk], minlength=len(leaf)) if len(leaf) < 400 else None
+    nnz = None
+    if cnt is not None:
+        nnz = int(np.sum((leafd <= 1) * cnt[:, None] * cnt[None, :]))
+    return {l: len(b) for l, b in boxes.items()}, far, nnz
+
+
+@pytest.mark.parametrize("mesh", ["sphere", "plate"])
+def test_tree_and_lists_match_independent_count(mesh):
+    if mesh == "sphere":
+        V, F = workloads.icosphere(3, 0.5)
+        nlv = 3
+    else:
+        V, F = workloads.plate(30, 30, 0.1)
+        nlv = 4
+    op = _op(V, F, nlv, check_coverage=True)
+    st = op.stats()
+    nb, far, nnz = _python_tree(V, F, nlv)
+    for lv in st["levels"]:
+        assert lv["nbox"] == nb[lv["l"]]
+        if lv["l"] >= 2:
+            assert lv["far_pairs"] == far[lv["l"]]
+    assert st["nnz_near"] == nnz
+
+
+def test_config2_plan_sizes():
+    V, F = workloads.icosphere(6, 4.0)
+    st = _op(V, F, 6).stats()
+    assert st["N"] == 122880
+    assert st["nnz_near"] == 49211256
+    lv = {x["l"]: x for x in st["levels"]}
+    assert [lv[l]["nbox"] for l in range(1, 6)] == [8, 56, 272, 1160, 4568]
+    assert [lv[l]["L"] for l in range(2, 6)] == [33, 20, 13, 8]
+    assert [lv[l]["far_pairs"] for l in range(2, 6)] == [2504, 12216, 54000, 207456]
+
+
+def test_truncation_rule_per_level():
+    V, F = workloads.icosphere(3, 0.5)
+    from oracle.translators import truncation_L
+    for d0 in (3.0, 5.0):
+        st = _op(V, F, 3, d0=d0).stats()
+        lv = st["levels"][2]
+        assert lv["L"] == truncation_L(2 * np.pi, lv["a"], d0)
+        assert lv["K"] == 2 * (lv["L"] + 1) ** 2
+
+
+def test_errors(L):
+    from paper_1412_1756_amd import CmError
+    V, F = workloads.plate(4, 4, 0.1)
+    with pytest.raises(CmError) as e:
+        _op(V, np.concatenate([F, F[:1]]), 3)          # non-manifold edge
+    assert e.value.code == -2
+    V2 = V.copy()
+    V2[F[3, 0]] = V2[F[3, 1]]                          # zero-area triangle
+    with pytest.raises(CmError) as e:
+        _op(V2, F, 3)
+    assert e.value.code == -2
+    V3 = V.copy()
+    V3[5, 2] = np.nan
+    with pytest.raises(CmError) as e:
+        _op(V3, F, 3)
+    assert e.value.code == -2
+    with pytest.raises(CmError) as e:
+        _op(V, F, 2)                                   # too few levels
+    assert e.value.code == -1
+    with pytest.raises(CmError) as e:
+        _op(V, F, 3, interp_p=5)
+    assert e.value.code == -1
+    Vs, Fs = workloads.icosphere(2, 0.5)
+    with pytest.raises(CmError) as e:
+        _op(Vs, Fs, 6)                                 # leaf boxes smaller than the mesh
+    assert e.value.code == -2
+    # a host-only handle refuses device work before touching any pointer
+    Vs, Fs = workloads.icosphere(3, 0.5)
+    op = _op(Vs, Fs, 3)
+    st = L.cm_apply(op._h, 0, C.c_void_p(16), C.c_void_p(32), 1, 1, None, 1, None)
+    assert st == -5
+    st = L.cm_apply(None, 0, C.c_void_p(16), C.c_void_p(32), 1, 1, None, 1, None)
+    assert st == -1
