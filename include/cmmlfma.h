@@ -55,7 +55,9 @@ typedef enum {
   CM_E_NOT_BUILT = -5,    /* handle has no device data (host-only plan) or the
                              SAI has not been built                             */
   CM_E_NUMERIC = -6,      /* non-finite translator or table entry               */
-  CM_E_UNSUPPORTED = -7   /* option combination not implemented                 */
+  CM_E_UNSUPPORTED = -7,  /* option combination not implemented                 */
+  CM_E_NOT_CONVERGED = -8 /* iterative solver stopped before its tolerance; the
+                             outputs hold the last iterate                      */
 } cm_status;
 
 typedef enum {
@@ -126,6 +128,35 @@ cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3);
 /* y = P x (same vector conventions as cm_apply).  Asynchronous. */
 cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols,
                        cm_dtype dt, void* hip_stream);
+
+/* Right-preconditioned GMRES(restart) for Z x = b (the inner solves
+   Z^-1 u of section IV), x = P u with the SAI P when precond != 0 (needs
+   cm_sai_build).  b, x: device, N complex128 (FP64 Krylov vectors and
+   Gram-Schmidt); far_dtype selects the far field of the Z products (CM_C128
+   FP64, CM_C64 FP32).  x0 = 0; stops when ||b - Z x|| <= tol ||b|| or after
+   maxit iterations (CM_E_NOT_CONVERGED).  *iters and *relres (may be NULL)
+   receive the iteration count and the final true relative residual.
+   Synchronises with hip_stream. */
+cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t restart, int32_t maxit, double tol,
+                   int32_t precond, cm_dtype far_dtype, int32_t* iters, double* relres, void* hip_stream);
+
+/* Characteristic modes by the implicitly restarted Arnoldi method on
+   OP = Z^-1 R (eq. (24)): the nev eigenvalues mu of largest magnitude, with
+   exact-shift restarts of an ncv-vector factorisation (nev < ncv <= N), each
+   OP product one R apply and one GMRES solve (gmres_restart, gmres_maxit,
+   gmres_tol, precond as in cm_gmres).  v0: device start vector (N complex128,
+   nonzero; the caller draws it).  Outputs (host): lambda[2*nev] interleaved
+   complex characteristic values lambda = i (1 - 1/mu), largest |mu| (smallest
+   |lambda|) first; ritz_resid[nev] (may be NULL) the relative Ritz residual
+   estimates; J (device, may be NULL) the N x nev Ritz vectors, column-major,
+   unit 2-norm; *nconv the number with residual <= tol; counters[4] (may be
+   NULL): OP products, GMRES iterations, operator applies, restarts.  Returns
+   CM_E_NOT_CONVERGED if fewer than nev converged within maxrestart restarts.
+   Synchronises. */
+cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
+                  int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond,
+                  cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
+                  int64_t* counters, void* hip_stream);
 
 /* Copy the near-field matrix to host (public unknown order, CSR by row):
    row_ptr (N+1, int64), col (nnz, int32), val (nnz complex128 interleaved).

@@ -7,13 +7,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcmmlfma.so")
 
 CM_OK, CM_E_BADARG, CM_E_MESH, CM_E_OOM, CM_E_HIP, CM_E_NOT_BUILT, CM_E_NUMERIC, CM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+CM_E_NOT_CONVERGED = -8
 OPS = {"Z": 0, "R": 1, "X": 2, "ZH": 3, "DZDK": 4}
 CM_C64, CM_C128 = 0, 1
 CM_FLAG_HOST_ONLY, CM_FLAG_DERIV, CM_FLAG_CHECK = 1, 2, 4
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
-           "cm_sai_build", "cm_sai_apply", "cm_export_near", "cm_stats", "cm_stage_timing", "cm_stage_times",
-           "cm_last_error"]
+           "cm_sai_build", "cm_sai_apply", "cm_gmres", "cm_eigs", "cm_export_near", "cm_stats", "cm_stage_timing",
+           "cm_stage_times", "cm_last_error"]
 
 
 class cm_opts(C.Structure):
@@ -60,6 +61,10 @@ def lib():
     L.cm_export_near.restype = C.c_int
     L.cm_stats.argtypes = [vp, C.c_char_p, i64, C.POINTER(i64)]
     L.cm_stats.restype = C.c_int
+    L.cm_gmres.argtypes = [vp, vp, vp, i32, i32, dbl, i32, C.c_int, C.POINTER(i32), C.POINTER(dbl), vp]
+    L.cm_gmres.restype = C.c_int
+    L.cm_eigs.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, i32, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
+    L.cm_eigs.restype = C.c_int
     L.cm_stage_timing.argtypes = [vp, i32]
     L.cm_stage_timing.restype = C.c_int
     L.cm_stage_times.argtypes = [vp, C.c_char_p, i64, C.POINTER(i64)]

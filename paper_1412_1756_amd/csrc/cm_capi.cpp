@@ -9,7 +9,6 @@
 #include <new>
 #include <string>
 
-#include "../../include/cmmlfma.h"
 #include "cm_device.h"
 
 namespace cm {
@@ -218,6 +217,12 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
 void dev_free(Dev& d) {
   for (void* p : d.allocs) (void)hipFree(p);
   d.allocs.clear();
+  if (d.sai_ptr) (void)hipFree(d.sai_ptr);
+  if (d.sai_col) (void)hipFree(d.sai_col);
+  if (d.sai_val) (void)hipFree(d.sai_val);
+  d.sai_ptr = nullptr;
+  d.sai_col = nullptr;
+  d.sai_val = nullptr;
   for (auto& m : d.marks) {
     (void)hipEventDestroy(m.a);
     (void)hipEventDestroy(m.b);
@@ -231,17 +236,15 @@ void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipSt
 
 }  // namespace cm
 
-struct cm_handle {
-  cm::Plan plan;
-  cm::Dev dev;
-  bool has_dev = false;
-};
-
 static thread_local std::string g_err;
 
 static cm_status fail(int code, const std::string& msg) {
   g_err = msg;
   return (cm_status)code;
+}
+
+namespace cm {
+cm_status driver_fail(int code, const std::string& msg) { return fail(code, msg); }
 }
 
 #define CM_TRY(...)                                                    \

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "../../include/cmmlfma.h"
 #include "cm_plan.h"
 
 namespace cm {
@@ -105,3 +106,10 @@ void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, in
                    hipStream_t s);
 
 }  // namespace cm
+
+// the opaque handle of the C ABI
+struct cm_handle {
+  cm::Plan plan;
+  cm::Dev dev;
+  bool has_dev = false;
+};

@@ -1,0 +1,499 @@
+// Krylov drivers (sections IV and V): right-preconditioned GMRES(m) for the
+// inner solves Z^-1 v, and the implicitly restarted Arnoldi iteration (exact
+// shifts) on OP = Z^-1 R, whose largest-magnitude eigenvalues mu give the
+// characteristic values of smallest magnitude, lambda = i (1 - 1/mu)
+// (eqs. (23)-(24)).  Krylov vectors live on the device in FP64 and are
+// orthogonalised there (classical Gram-Schmidt with one DGKS correction);
+// the small Hessenberg matrices (<= a few hundred) are factorised on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <numeric>
+#include <vector>
+
+#include "cm_device.h"
+
+namespace cm {
+
+void blas_multidot(const double2* V, int64_t ldv, const double2* w, int64_t N, int nk, double2* h, hipStream_t s);
+void blas_gemv_sub(const double2* V, int64_t ldv, const double2* h, int nk, double2* w, int64_t N, hipStream_t s);
+void blas_axpby(const double2* x, double2 alpha, double2* y, int64_t N, int accumulate, hipStream_t s);
+void blas_basis_update(const double2* V, int64_t ldv, const double2* Q, int ldq, int nk, int nc, double2* Vout,
+                       int64_t N, hipStream_t s);
+void blas_to_c64(const double2* x, float2* y, int64_t N, hipStream_t s);
+void blas_to_c128(const float2* x, double2* y, int64_t N, hipStream_t s);
+
+static void chk_d(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) throw Error(-3, std::string(what) + ": out of device memory");
+    throw Error(-4, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  explicit DevBuf(size_t bytes) { chk_d(hipMalloc(&p, std::max<size_t>(bytes, 16)), "driver workspace"); }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  double2* d() const { return (double2*)p; }
+};
+
+// Shared machinery: the operator applications on FP64 vectors, and the
+// orthogonalisation of w against V[0..j).
+class KrylovCtx {
+ public:
+  KrylovCtx(Dev& d, const Plan& P, bool far64, hipStream_t s)
+      : d_(d), P_(P), far64_(far64), s_(s), N_(d.N), t32a_(d.N * sizeof(float2)), t32b_(d.N * sizeof(float2)),
+        hdev_(1024 * sizeof(double2)) {}
+
+  int64_t N() const { return N_; }
+  hipStream_t stream() const { return s_; }
+
+  // y = op(x), op 0 = Z, 1 = R; far field in FP64 or FP32
+  void apply(int op, const double2* x, double2* y) {
+    ++n_apply;
+    if (far64_) {
+      dev_apply(d_, P_, op, x, y, 1, 1, true, s_);
+    } else {
+      blas_to_c64(x, (float2*)t32a_.p, N_, s_);
+      dev_apply(d_, P_, op, t32a_.p, t32b_.p, 1, 1, false, s_);
+      blas_to_c128((const float2*)t32b_.p, y, N_, s_);
+    }
+  }
+  void precond(const double2* x, double2* y) { dev_sai_apply(d_, P_, x, y, 1, 1, true, s_); }
+
+  double norm(const double2* w) {
+    blas_multidot(w, N_, w, N_, 1, hdev_.d(), s_);
+    double2 h;
+    chk_d(hipMemcpyAsync(&h, hdev_.p, sizeof h, hipMemcpyDeviceToHost, s_), "norm");
+    chk_d(hipStreamSynchronize(s_), "norm");
+    return std::sqrt(std::max(h.x, 0.0));
+  }
+
+  // Orthogonalise w against V[0..j) (columns of length N, stride N); h[0..j)
+  // receives the coefficients, the return value is ||w|| afterwards.
+  double orth(const double2* V, int j, double2* w, std::vector<cplx>& h) {
+    h.assign(j, cplx(0));
+    double before = norm(w);
+    if (j == 0) return before;
+    std::vector<double2> hh(j);
+    for (int pass = 0; pass < 2; ++pass) {
+      blas_multidot(V, N_, w, N_, j, hdev_.d(), s_);
+      blas_gemv_sub(V, N_, hdev_.d(), j, w, N_, s_);
+      chk_d(hipMemcpyAsync(hh.data(), hdev_.p, j * sizeof(double2), hipMemcpyDeviceToHost, s_), "orth");
+      chk_d(hipStreamSynchronize(s_), "orth");
+      for (int k = 0; k < j; ++k) h[k] += cplx(hh[k].x, hh[k].y);
+      double after = norm(w);
+      if (after > 0.717 * before) return after;   // DGKS: one correction when cancellation occurred
+      before = after;
+    }
+    return norm(w);
+  }
+
+  void scale_copy(const double2* x, cplx a, double2* y) {
+    blas_axpby(x, make_double2(a.real(), a.imag()), y, N_, 0, s_);
+  }
+  void axpy(const double2* x, cplx a, double2* y) { blas_axpby(x, make_double2(a.real(), a.imag()), y, N_, 1, s_); }
+
+  // Vout[:, c] = sum_k V[:, k] Q(k, c), c < nc, Q column-major host matrix (ldq rows)
+  void combine(const double2* V, int nk, const std::vector<cplx>& Q, int ldq, int nc, double2* Vout) {
+    std::vector<double2> q(Q.size());
+    for (size_t i = 0; i < Q.size(); ++i) q[i] = make_double2(Q[i].real(), Q[i].imag());
+    DevBuf qd(q.size() * sizeof(double2));
+    chk_d(hipMemcpyAsync(qd.p, q.data(), q.size() * sizeof(double2), hipMemcpyHostToDevice, s_), "combine");
+    blas_basis_update(V, N_, qd.d(), ldq, nk, nc, Vout, N_, s_);
+    chk_d(hipStreamSynchronize(s_), "combine");
+  }
+
+  int64_t n_apply = 0;
+
+ private:
+  Dev& d_;
+  const Plan& P_;
+  bool far64_;
+  hipStream_t s_;
+  int64_t N_;
+  DevBuf t32a_, t32b_, hdev_;
+};
+
+// ---------------------------------------------------------------- GMRES
+struct GmresResult {
+  int iters = 0;
+  double relres = 0;
+  bool converged = false;
+};
+
+// Solve Z x = b, right-preconditioned by the SAI P (x = P u) when precond.
+static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int maxit, double tol, bool precond) {
+  const int64_t N = K.N();
+  DevBuf Vb((size_t)(m + 1) * N * sizeof(double2)), w(N * sizeof(double2)), z(N * sizeof(double2)),
+      u(N * sizeof(double2));
+  double2* V = Vb.d();
+  GmresResult res;
+  chk_d(hipMemsetAsync(x, 0, N * sizeof(double2), K.stream()), "gmres");
+  const double bn = K.norm(b);
+  if (bn == 0) {
+    res.converged = true;
+    return res;
+  }
+  // r = b (x0 = 0)
+  K.scale_copy(b, 1.0, w.d());
+  double beta = bn;
+  std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), h;
+  while (res.iters < maxit) {
+    K.scale_copy(w.d(), 1.0 / beta, V);
+    std::fill(H.begin(), H.end(), cplx(0));
+    std::fill(g.begin(), g.end(), cplx(0));
+    g[0] = beta;
+    int jend = -1;
+    for (int j = 0; j < m && res.iters < maxit; ++j) {
+      const double2* vj = V + (size_t)j * N;
+      if (precond) {
+        K.precond(vj, z.d());
+        K.apply(0, z.d(), w.d());
+      } else {
+        K.apply(0, vj, w.d());
+      }
+      double hn = K.orth(V, j + 1, w.d(), h);
+      for (int k = 0; k <= j; ++k) H[(size_t)j * (m + 1) + k] = h[k];
+      H[(size_t)j * (m + 1) + j + 1] = hn;
+      if (hn > 0) K.scale_copy(w.d(), 1.0 / hn, V + (size_t)(j + 1) * N);
+      // previous rotations on column j
+      cplx* col = &H[(size_t)j * (m + 1)];
+      for (int k = 0; k < j; ++k) {
+        cplx a = col[k], c2 = col[k + 1];
+        col[k] = std::conj(cs[k]) * a + std::conj(sn[k]) * c2;
+        col[k + 1] = -sn[k] * a + cs[k] * c2;
+      }
+      // new rotation zeroing col[j+1]
+      double r = std::hypot(std::abs(col[j]), std::abs(col[j + 1]));
+      if (r == 0) {
+        cs[j] = 1;
+        sn[j] = 0;
+      } else {
+        cs[j] = col[j] / r;
+        sn[j] = col[j + 1] / r;
+      }
+      col[j] = r;
+      col[j + 1] = 0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = std::conj(cs[j]) * g[j];
+      ++res.iters;
+      jend = j;
+      if (std::abs(g[j + 1]) / bn <= tol || hn == 0) break;
+    }
+    // y = H^-1 g (upper triangular), u = V y, x += P u
+    const int n = jend + 1;
+    std::vector<cplx> y(n);
+    for (int k = n - 1; k >= 0; --k) {
+      cplx s = g[k];
+      for (int c = k + 1; c < n; ++c) s -= H[(size_t)c * (m + 1) + k] * y[c];
+      y[k] = s / H[(size_t)k * (m + 1) + k];
+    }
+    K.combine(V, n, y, n, 1, u.d());
+    if (precond) {
+      K.precond(u.d(), z.d());
+      K.axpy(z.d(), 1.0, x);
+    } else {
+      K.axpy(u.d(), 1.0, x);
+    }
+    // explicit residual
+    K.apply(0, x, z.d());
+    K.scale_copy(b, 1.0, w.d());
+    K.axpy(z.d(), -1.0, w.d());
+    beta = K.norm(w.d());
+    res.relres = beta / bn;
+    if (res.relres <= tol) {
+      res.converged = true;
+      break;
+    }
+  }
+  return res;
+}
+
+// ---------------------------------------------------------------- small dense helpers
+using Mat = std::vector<cplx>;   // column-major
+static inline cplx& at(Mat& A, int ld, int r, int c) { return A[(size_t)c * ld + r]; }
+
+static void rotation(cplx x, cplx y, double& c, cplx& s) {
+  double ax = std::abs(x), r = std::hypot(ax, std::abs(y));
+  if (r == 0) {
+    c = 1;
+    s = 0;
+  } else if (ax == 0) {
+    c = 0;
+    s = std::conj(y) / std::abs(y);
+  } else {
+    c = ax / r;
+    s = (x / ax) * std::conj(y) / r;
+  }
+}
+
+// One implicit single-shift QR step on the active window [lo, hi] of the
+// upper Hessenberg A (n x n): A <- G^H A G, Z <- Z G.
+static void qr_sweep(Mat& A, int n, int lo, int hi, cplx mu, Mat* Z, int nz, bool full) {
+  cplx x = at(A, n, lo, lo) - mu, y = at(A, n, lo + 1, lo);
+  for (int i = lo; i < hi; ++i) {
+    if (i > lo) {
+      x = at(A, n, i, i - 1);
+      y = at(A, n, i + 1, i - 1);
+    }
+    double c;
+    cplx s;
+    rotation(x, y, c, s);
+    int c0 = full ? std::max(0, i - 1) : std::max(lo, i - 1);
+    int r1 = std::min(hi + 1, i + 3);
+    if (full) r1 = std::min(n, i + 3);
+    // left rotation on rows i, i+1 over columns c0..n-1 (or ..hi in a window)
+    for (int k = c0; k < (full ? n : hi + 1); ++k) {
+      cplx a = at(A, n, i, k), b = at(A, n, i + 1, k);
+      at(A, n, i, k) = c * a + s * b;
+      at(A, n, i + 1, k) = -std::conj(s) * a + c * b;
+    }
+    for (int r = (full ? 0 : lo); r < r1; ++r) {
+      cplx a = at(A, n, r, i), b = at(A, n, r, i + 1);
+      at(A, n, r, i) = c * a + std::conj(s) * b;
+      at(A, n, r, i + 1) = -s * a + c * b;
+    }
+    if (i > lo) at(A, n, i + 1, i - 1) = 0;
+    if (Z)
+      for (int r = 0; r < nz; ++r) {
+        cplx a = at(*Z, nz, r, i), b = at(*Z, nz, r, i + 1);
+        at(*Z, nz, r, i) = c * a + std::conj(s) * b;
+        at(*Z, nz, r, i + 1) = -s * a + c * b;
+      }
+  }
+}
+
+// Complex Schur form of an upper Hessenberg matrix: A = Z T Z^H (T overwrites A).
+static bool schur(Mat& A, int n, Mat& Z) {
+  Z.assign((size_t)n * n, cplx(0));
+  for (int i = 0; i < n; ++i) at(Z, n, i, i) = 1;
+  int hi = n - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int l = hi;
+    while (l > 0) {
+      double sd = std::abs(at(A, n, l, l - 1));
+      double dd = std::abs(at(A, n, l - 1, l - 1)) + std::abs(at(A, n, l, l));
+      if (sd <= 1e-15 * (dd > 0 ? dd : 1.0)) {
+        at(A, n, l, l - 1) = 0;
+        break;
+      }
+      --l;
+    }
+    if (l == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    cplx a = at(A, n, hi - 1, hi - 1), b = at(A, n, hi - 1, hi), c = at(A, n, hi, hi - 1), d = at(A, n, hi, hi);
+    cplx tr = a + d, det = a * d - b * c;
+    cplx disc = std::sqrt(tr * tr / 4.0 - det);
+    cplx m1 = tr / 2.0 + disc, m2 = tr / 2.0 - disc;
+    cplx mu = (std::abs(m1 - d) < std::abs(m2 - d)) ? m1 : m2;
+    if (iter > 0 && iter % 12 == 0) mu = d + cplx(std::abs(at(A, n, hi, hi - 1)), 0.0);   // exceptional shift
+    qr_sweep(A, n, l, hi, mu, &Z, n, true);
+    ++iter;
+    if (++total > 200 * n) return false;
+  }
+  return true;
+}
+
+// Eigenvectors of the Hessenberg matrix H from its Schur form: columns of Y.
+static void schur_vectors(const Mat& T, const Mat& Z, int n, Mat& Y) {
+  Y.assign((size_t)n * n, cplx(0));
+  double tn = 0;
+  for (auto& v : T) tn = std::max(tn, std::abs(v));
+  std::vector<cplx> y(n);
+  for (int i = 0; i < n; ++i) {
+    std::fill(y.begin(), y.end(), cplx(0));
+    y[i] = 1;
+    cplx li = T[(size_t)i * n + i];
+    for (int r = i - 1; r >= 0; --r) {
+      cplx s = 0;
+      for (int c = r + 1; c <= i; ++c) s += T[(size_t)c * n + r] * y[c];
+      cplx den = T[(size_t)r * n + r] - li;
+      if (std::abs(den) < 1e-14 * tn) den = 1e-14 * tn;
+      y[r] = -s / den;
+    }
+    double nr = 0;
+    for (int r = 0; r < n; ++r) {
+      cplx s = 0;
+      for (int c = 0; c <= i; ++c) s += Z[(size_t)c * n + r] * y[c];
+      Y[(size_t)i * n + r] = s;
+      nr += std::norm(s);
+    }
+    nr = std::sqrt(nr);
+    for (int r = 0; r < n; ++r) Y[(size_t)i * n + r] /= nr;
+  }
+}
+
+// ---------------------------------------------------------------- implicitly restarted Arnoldi
+struct EigsResult {
+  int nconv = 0, restarts = 0;
+  int64_t n_op = 0, gmres_iters = 0, n_matvec = 0;
+  std::vector<cplx> mu;       // Ritz values of OP, largest magnitude first
+  std::vector<double> resid;  // Ritz residual estimates |beta e_m^T y| / |mu|
+};
+
+static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double tol, const double2* v0, int gm_m,
+                       int gm_maxit, double gm_tol, bool precond, double2* Xout) {
+  const int64_t N = K.N();
+  DevBuf Vb((size_t)ncv * N * sizeof(double2)), Vt((size_t)ncv * N * sizeof(double2)), f(N * sizeof(double2)),
+      ru(N * sizeof(double2));
+  double2* V = Vb.d();
+  double2* Vw = Vt.d();
+  EigsResult out;
+  Mat H((size_t)ncv * ncv, cplx(0));
+  std::vector<cplx> h;
+  double nv0 = K.norm(v0);
+  if (!(nv0 > 0)) throw Error(-1, "start vector is zero");
+  K.scale_copy(v0, 1.0 / nv0, V);
+  int j0 = 0;
+  double beta = 0;
+  const int kkeep = std::min(ncv - 1, nev + std::max(1, (ncv - nev) / 3));
+  Mat T, Z, Y;
+  std::vector<int> order;
+  for (int rs = 0;; ++rs) {
+    for (int j = j0; j < ncv; ++j) {
+      // w = Z^-1 R v_j
+      K.apply(1, V + (size_t)j * N, ru.d());
+      GmresResult g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, precond);
+      out.gmres_iters += g.iters;
+      ++out.n_op;
+      double hn = K.orth(V, j + 1, f.d(), h);
+      for (int k = 0; k <= j; ++k) at(H, ncv, k, j) = h[k];
+      if (j + 1 < ncv) {
+        at(H, ncv, j + 1, j) = hn;
+        K.scale_copy(f.d(), 1.0 / hn, V + (size_t)(j + 1) * N);
+      } else {
+        beta = hn;
+      }
+    }
+    // Ritz pairs of H
+    T = H;
+    if (!schur(T, ncv, Z)) throw Error(-6, "Hessenberg QR did not converge");
+    schur_vectors(T, Z, ncv, Y);
+    order.resize(ncv);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      return std::abs(T[(size_t)a * ncv + a]) > std::abs(T[(size_t)b * ncv + b]);
+    });
+    out.mu.assign(nev, 0);
+    out.resid.assign(nev, 0);
+    int nconv = 0;
+    for (int i = 0; i < nev; ++i) {
+      int c = order[i];
+      cplx mu = T[(size_t)c * ncv + c];
+      double r = beta * std::abs(Y[(size_t)c * ncv + ncv - 1]) / std::max(std::abs(mu), 1e-300);
+      out.mu[i] = mu;
+      out.resid[i] = r;
+      if (r <= tol) ++nconv;
+    }
+    out.nconv = nconv;
+    out.restarts = rs;
+    if (nconv >= nev || rs >= maxrestart) break;
+    // implicit restart: the ncv - kkeep unwanted Ritz values are the shifts
+    Mat Q((size_t)ncv * ncv, cplx(0));
+    for (int i = 0; i < ncv; ++i) at(Q, ncv, i, i) = 1;
+    for (int i = kkeep; i < ncv; ++i) {
+      int c = order[i];
+      qr_sweep(H, ncv, 0, ncv - 1, T[(size_t)c * ncv + c], &Q, ncv, true);
+    }
+    // new factorisation of length kkeep
+    cplx hk = at(H, ncv, kkeep, kkeep - 1);
+    cplx sig = at(Q, ncv, ncv - 1, kkeep - 1);
+    K.combine(V, ncv, Q, ncv, kkeep + 1, Vw);
+    // f+ = V Q e_{k} h_{k,k-1} + f sigma  (f holds the last residual, norm beta)
+    DevBuf fn(N * sizeof(double2));
+    K.scale_copy(Vw + (size_t)kkeep * N, hk, fn.d());
+    K.axpy(f.d(), sig, fn.d());
+    std::swap(V, Vw);
+    double b2 = K.norm(fn.d());
+    for (int c = 0; c < ncv; ++c)
+      for (int r = 0; r < ncv; ++r)
+        if (c >= kkeep || r >= kkeep) at(H, ncv, r, c) = 0;
+    if (b2 == 0) throw Error(-6, "Arnoldi restart produced a zero residual");
+    at(H, ncv, kkeep, kkeep - 1) = b2;
+    K.scale_copy(fn.d(), 1.0 / b2, V + (size_t)kkeep * N);
+    j0 = kkeep;
+  }
+  // Ritz vectors of the wanted values: X = V Y_wanted
+  if (Xout) {
+    Mat Yw((size_t)ncv * nev);
+    for (int i = 0; i < nev; ++i)
+      for (int r = 0; r < ncv; ++r) Yw[(size_t)i * ncv + r] = Y[(size_t)order[i] * ncv + r];
+    K.combine(V, ncv, Yw, ncv, nev, Xout);
+  }
+  out.n_matvec = K.n_apply;
+  return out;
+}
+
+}  // namespace cm
+
+// ---------------------------------------------------------------- C ABI entry points
+namespace cm {
+cm_status driver_fail(int code, const std::string& msg);
+}
+
+extern "C" cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t restart, int32_t maxit, double tol,
+                              int32_t precond, cm_dtype far_dtype, int32_t* iters, double* relres,
+                              void* hip_stream) {
+  if (!h || !b || !x) return cm::driver_fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (restart < 1 || restart > 1000 || maxit < 1 || !(tol > 0)) return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters");
+  if (precond && !h->dev.sai_val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (b == x) return cm::driver_fail(CM_E_BADARG, "b and x must not alias");
+  try {
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
+    cm::GmresResult r = cm::gmres(K, (const double2*)b, (double2*)x, restart, maxit, tol, precond != 0);
+    if (iters) *iters = r.iters;
+    if (relres) *relres = r.relres;
+    return r.converged ? CM_OK : CM_E_NOT_CONVERGED;
+  } catch (const cm::Error& e) {
+    return cm::driver_fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return cm::driver_fail(CM_E_OOM, e.what());
+  }
+}
+
+extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
+                             int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond,
+                             cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
+                             int64_t* counters, void* hip_stream) {
+  if (!h || !v0 || !lambda) return cm::driver_fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (nev < 1 || ncv <= nev || ncv > 1000 || ncv > h->dev.N || maxrestart < 0 || !(tol > 0))
+    return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
+  if (gmres_restart < 1 || gmres_maxit < 1 || !(gmres_tol > 0)) return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters");
+  if (precond && !h->dev.sai_val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  try {
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
+    cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
+                                gmres_tol, precond != 0, (double2*)J);
+    for (int i = 0; i < nev; ++i) {
+      // lambda = i (1 - 1/mu)
+      cm::cplx lam = cm::cplx(0, 1) * (1.0 - 1.0 / r.mu[i]);
+      lambda[2 * i] = lam.real();
+      lambda[2 * i + 1] = lam.imag();
+      if (ritz_resid) ritz_resid[i] = r.resid[i];
+    }
+    if (nconv) *nconv = r.nconv;
+    if (counters) {
+      counters[0] = r.n_op;
+      counters[1] = r.gmres_iters;
+      counters[2] = r.n_matvec;
+      counters[3] = r.restarts;
+    }
+    return r.nconv >= nev ? CM_OK : CM_E_NOT_CONVERGED;
+  } catch (const cm::Error& e) {
+    return cm::driver_fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return cm::driver_fail(CM_E_OOM, e.what());
+  }
+}

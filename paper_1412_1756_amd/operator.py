@@ -142,3 +142,45 @@ class Operator:
                                 X.shape[1], dt, self._stream_ptr(stream))
         check(st)
         return Y.reshape(-1) if squeeze else Y
+
+    # ------------------------------------------------------------ Krylov drivers
+    def gmres(self, b, restart=50, maxit=500, tol=1e-6, precond=True, far="fp64", stream=None,
+              raise_on_fail=False):
+        """Solve Z x = b (b: CUDA complex128 tensor of N).  Returns
+        (x, iterations, final relative residual, converged)."""
+        import torch
+        b = b.contiguous()
+        if b.dtype != torch.complex128 or b.numel() != self.N:
+            raise TypeError("b must be a complex128 CUDA tensor of N entries")
+        x = torch.empty_like(b)
+        it = C.c_int32()
+        rr = C.c_double()
+        st = lib().cm_gmres(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), restart, maxit, tol,
+                            1 if precond else 0, _lib.CM_C128 if far == "fp64" else _lib.CM_C64, C.byref(it),
+                            C.byref(rr), self._stream_ptr(stream))
+        if st not in (_lib.CM_OK, _lib.CM_E_NOT_CONVERGED) or (raise_on_fail and st != _lib.CM_OK):
+            check(st)
+        return x, int(it.value), float(rr.value), st == _lib.CM_OK
+
+    def eigs(self, nev, ncv, v0, tol=1e-8, maxrestart=50, gmres_restart=50, gmres_maxit=1000, gmres_tol=1e-8,
+             precond=True, far="fp64", vectors=True, stream=None):
+        """Characteristic values by implicitly restarted Arnoldi on Z^-1 R.
+        v0: CUDA complex128 start vector.  Returns dict(lam, resid, J, nconv,
+        n_op, gmres_iters, n_matvec, restarts, converged)."""
+        import torch
+        v0 = v0.contiguous()
+        lam = np.zeros(2 * nev)
+        res = np.zeros(nev)
+        cnt = np.zeros(4, dtype=np.int64)
+        J = torch.empty((nev, self.N), dtype=torch.complex128, device=v0.device) if vectors else None
+        nconv = C.c_int32()
+        st = lib().cm_eigs(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
+                           gmres_maxit, gmres_tol, 1 if precond else 0,
+                           _lib.CM_C128 if far == "fp64" else _lib.CM_C64, lam.ctypes.data, res.ctypes.data,
+                           C.c_void_p(J.data_ptr()) if vectors else None, C.byref(nconv), cnt.ctypes.data,
+                           self._stream_ptr(stream))
+        if st not in (_lib.CM_OK, _lib.CM_E_NOT_CONVERGED):
+            check(st)
+        return dict(lam=lam[0::2] + 1j * lam[1::2], resid=res, J=(J.T if vectors else None), nconv=int(nconv.value),
+                    n_op=int(cnt[0]), gmres_iters=int(cnt[1]), n_matvec=int(cnt[2]), restarts=int(cnt[3]),
+                    converged=(st == _lib.CM_OK))

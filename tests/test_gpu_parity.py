@@ -197,3 +197,89 @@ def test_config2_sampled_rows(torch_cuda):
     print(f"cfg2 fp64 {e64:.3e} fp32-batched {e32:.3e}", flush=True)
     assert e64 < TOL64
     assert e32 < TOL32
+
+
+def test_sai_matches_oracle(torch_cuda, cfg1):
+    """SAI of the near field with the plate thresholds of the paper
+    (0.01 / 0.014 / 0.18): P entries against the oracle's least squares on the
+    oracle's own near field, and y = P x through the device apply."""
+    torch = torch_cuda
+    from oracle.sai import near_mask, sai
+    V, F, Z = cfg1
+    op = _op(V, F, 3, ACC64, max_cols=4)
+    eps = (0.01, 0.014, 0.18)
+    op.sai_build(*eps)
+    Pg = op.export_near(2).toarray()
+    Zn = np.where(near_mask(V, F, 3), Z, 0)
+    Po = sai(Zn, *eps)
+    # patterns agree except where an entry sits on a threshold to rounding
+    assert np.count_nonzero(Pg) > 0
+    both = (Pg != 0) & (Po != 0)
+    assert both.sum() >= 0.999 * max(np.count_nonzero(Pg), np.count_nonzero(Po))
+    assert np.abs(Pg[both] - Po[both]).max() < 1e-9 * np.abs(Po).max()
+    x = workloads.cn01(Z.shape[0], 0)
+    for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-6)):
+        y = op.sai_apply(torch.tensor(x, dtype=dt, device="cuda")).cpu().numpy()
+        assert relerr(y, Pg @ x) < tol
+    # a good right preconditioner: I - Z_near P is small on the pattern
+    R = np.eye(Z.shape[0]) - Zn @ Pg
+    print("||I - Zn P||_F / sqrt(N) =", np.linalg.norm(R) / np.sqrt(Z.shape[0]), flush=True)
+
+
+def test_gmres_solves_against_dense_solve(torch_cuda, cfg1):
+    """SAI-preconditioned GMRES through the FP64 MLFMA: the solution of the
+    MLFMA system matches numpy.linalg.solve on the oracle's dense Z to the
+    MLFMA error times the conditioning, and the true residual meets tol."""
+    torch = torch_cuda
+    V, F, Z = cfg1
+    N = Z.shape[0]
+    op = _op(V, F, 3, ACC64, max_cols=1)
+    op.sai_build(0.01, 0.014, 0.18)
+    b = workloads.cn01(N, 4)
+    x, it, rr, ok = op.gmres(torch.tensor(b, dtype=torch.complex128, device="cuda"), restart=40, maxit=400,
+                             tol=1e-8)
+    x = x.cpu().numpy()
+    xe = np.linalg.solve(Z, b)
+    print(f"gmres: {it} iterations, relres {rr:.2e}, err vs dense {relerr(x, xe):.2e}", flush=True)
+    assert ok and rr <= 1e-8
+    # the MLFMA product differs from the dense Z by <= TOL64 relative, so the
+    # oracle residual of the MLFMA solution is bounded by TOL64 ||Z|| ||x|| / ||b||
+    bound = TOL64 * np.linalg.norm(Z, 2) * np.linalg.norm(x) / np.linalg.norm(b)
+    print(f"oracle residual {relerr(Z @ x, b):.2e}, bound {bound:.2e}", flush=True)
+    assert relerr(Z @ x, b) < bound
+    # the preconditioner pays: fewer iterations than unpreconditioned GMRES
+    _, it0, _, _ = op.gmres(torch.tensor(b, dtype=torch.complex128, device="cuda"), restart=40, maxit=400,
+                            tol=1e-8, precond=False)
+    print(f"unpreconditioned: {it0} iterations", flush=True)
+    assert it < it0
+    # non-convergence is reported, not raised
+    _, it1, rr1, ok1 = op.gmres(torch.tensor(b, dtype=torch.complex128, device="cuda"), restart=5, maxit=1,
+                                tol=1e-12)
+    assert not ok1 and it1 == 1
+
+
+def test_arnoldi_characteristic_values_match_qz(torch_cuda, cfg1):
+    """IRA on Z^-1 R with SAI-preconditioned GMRES inner solves: the 10
+    smallest characteristic values of the 1,920-unknown sphere against dense
+    QZ of the oracle's (X, R), within 1e-3 (clusters compared as sorted sets)."""
+    torch = torch_cuda
+    from oracle import modes
+    V, F, Z = cfg1
+    N = Z.shape[0]
+    op = _op(V, F, 3, ACC64, max_cols=1)
+    op.sai_build(0.01, 0.014, 0.18)
+    v0 = torch.tensor(workloads.cn01(N, 3), dtype=torch.complex128, device="cuda")
+    r = op.eigs(10, 30, v0, tol=1e-6, maxrestart=30, gmres_tol=1e-8)
+    lam = r["lam"]
+    print("IRA", np.sort(lam.real), "resid", r["resid"].max(), "restarts", r["restarts"], "op", r["n_op"],
+          "gmres its", r["gmres_iters"], flush=True)
+    ref = np.sort(modes.qz_modes(Z.imag, Z.real, nev=10).real)
+    assert r["nconv"] >= 10
+    assert np.abs(lam.imag).max() < 1e-3
+    assert np.abs(np.sort(lam.real) - ref).max() < 1e-3
+    # Ritz vectors: X J = lambda R J with the oracle's dense matrices
+    J = r["J"].cpu().numpy()
+    for i in range(10):
+        j = J[:, i]
+        res = np.linalg.norm(Z.imag @ j - lam[i].real * (Z.real @ j)) / np.linalg.norm(Z.imag @ j)
+        assert res < 1e-2
