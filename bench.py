@@ -32,8 +32,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--ncols", type=int, default=32)
-    ap.add_argument("--d0", type=float, default=5.0)
-    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--d0", type=float, default=5.0, help="digits (truncation rule) of the FP32 batched path")
+    ap.add_argument("--p", type=int, default=10, help="interpolation points of the FP32 batched path")
+    ap.add_argument("--d0-64", type=float, default=6.0, help="digits of the FP64 single-vector path")
+    ap.add_argument("--p-64", type=int, default=12, help="interpolation points of the FP64 path")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration under rocprofv3)")
     ap.add_argument("--nlv", type=int, default=6)
     ap.add_argument("--rows", type=int, default=6, help="oracle rows for error and CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no error, no CPU baseline)")
@@ -85,6 +89,23 @@ def roofline(stage, times, calls, model):
             "avg_launch_ms": t * 1e3, "alg_flops": mdl["flops"], "alg_bytes": mdl["bytes"]}
 
 
+def measured_traffic(stage, path_tag, cfg):
+    """HBM bytes per launch of a stage from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated), or None when
+    there is none for this stage or the kernel source changed since."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f)).get(f"{stage}/{path_tag}")
+    if not rec or rec.get("config") != cfg:
+        return None
+    src = open(os.path.join(ROOT, "paper_1412_1756_amd", "csrc", "cm_apply.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -99,9 +120,11 @@ def main():
     V, F, spec = workloads.workload(name)
     k = spec["k"]
     dev = torch.device("cuda:0")
-    op = Operator(V, F, k, nlv=a.nlv, d0=a.d0, interp_p=a.p, max_cols=max(a.ncols, 1))
-    N = op.N
-    st = op.stats()
+    op32 = Operator(V, F, k, nlv=a.nlv, d0=a.d0, interp_p=a.p, max_cols=max(a.ncols, 1))
+    op64 = Operator(V, F, k, nlv=a.nlv, d0=a.d0_64, interp_p=a.p_64, max_cols=1)
+    N = op32.N
+    st = op32.stats()
+    st64 = op64.stats()
     x1 = workloads.cn01(N, 0)
     X32 = torch.tensor(workloads.cn01_block(N, a.ncols, 100), dtype=torch.complex64, device=dev)
     X32[:, 0] = torch.tensor(x1, dtype=torch.complex64, device=dev)
@@ -110,7 +133,7 @@ def main():
     Y64 = torch.empty_like(X64)
     torch.cuda.synchronize()
 
-    def timed(X, Y, steps, warm, stage_timing=True):
+    def timed(op, X, Y, steps, warm, stage_timing=True):
         for _ in range(warm):
             op.apply(X, out=Y)
         torch.cuda.synchronize()
@@ -129,20 +152,27 @@ def main():
         return e0.elapsed_time(e1) / steps, wall, times
 
     # untimed-stage pass (pure throughput), then a pass with per-stage events
-    ms32, wall32, _ = timed(X32, Y32, a.steps, a.warmup, stage_timing=False)
-    ms64, wall64, _ = timed(X64, Y64, a.steps, a.warmup, stage_timing=False)
-    _, _, times32 = timed(X32, Y32, max(3, a.steps // 4), 1)
-    _, _, times64 = timed(X64, Y64, max(3, a.steps // 4), 1)
+    ms32, wall32, _ = timed(op32, X32, Y32, a.steps, a.warmup, stage_timing=False)
+    ms64, wall64, _ = timed(op64, X64, Y64, a.steps, a.warmup, stage_timing=False)
+    _, _, times32 = timed(op32, X32, Y32, max(3, a.steps // 4), 1)
+    _, _, times64 = timed(op64, X64, Y64, max(3, a.steps // 4), 1)
+    if a.copy_calib:
+        src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)       # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     y32 = Y32[:, 0].cpu().numpy().astype(np.complex128)
     y64 = Y64[:, 0].cpu().numpy()
 
     model32 = stage_model(st, a.ncols, 8)
-    model64 = stage_model(st, 1, 16)
+    model64 = stage_model(st64, 1, 16)
     dom32 = max((s for s in times32 if s in model32), key=lambda s: times32[s]["ms"])
     dom64 = max((s for s in times64 if s in model64), key=lambda s: times64[s]["ms"])
     roof = roofline(dom32, times32, None, model32)
     roof64 = roofline(dom64, times64, None, model64)
+    roof["traffic"] = measured_traffic(dom32, "fp32_batched", f"d0 {a.d0:g}, p {a.p}, {a.ncols} columns")
+    roof64["traffic"] = measured_traffic(dom64, "fp64_single", f"d0 {a.d0_64:g}, p {a.p_64}, 1 columns")
     stage_frac = {s: round(v["ms"] / sum(u["ms"] for u in times32.values()), 4) for s, v in times32.items()}
 
     out = {
@@ -156,7 +186,7 @@ def main():
         "config": {"workload": name, "N": N, "nlv": a.nlv, "d0": a.d0, "interp_p": a.p, "ncols": a.ncols,
                    "k": k, "mesh": "icosphere nsub 6, radius 4 wavelengths"},
         "fp64_single": {"matvecs_per_s": 1000.0 / ms64, "ms_per_matvec": ms64, "dtype": "c128",
-                        "roofline": roof64},
+                        "d0": a.d0_64, "interp_p": a.p_64, "roofline": roof64},
         "roofline": roof,
         "stage_fraction_fp32_batched": stage_frac,
         "stage_fraction_fp64_single": {s: round(v["ms"] / sum(u["ms"] for u in times64.values()), 4)
