@@ -119,14 +119,90 @@ __global__ void __launch_bounds__(256) k_near(const int64_t* __restrict__ row_pt
   if (s == 0 && c < nc) yi[i * nc + c] = mk<R>((R)ax, (R)ay);
 }
 
+
+// Batched near field: one block per leaf box computes the dense block product
+// (rows of the box) x (near columns) x (nc columns).  x rows of a chunk of
+// near columns are staged in LDS; each thread owns (row, 4 columns) outputs
+// and reads its row's FP64 values once per chunk (shared by the threads of
+// the row).  FP64 products and sums.
+template <typename R>
+__global__ void __launch_bounds__(256) k_near_box(const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ box_start,
+                                                  const int32_t* __restrict__ bcol_ptr, const int32_t* __restrict__ bcol,
+                                                  const int32_t* __restrict__ self_off, const double2* __restrict__ Zn,
+                                                  const C2<R>* __restrict__ xi, C2<R>* __restrict__ yi, int nc,
+                                                  int mode) {
+  constexpr int TC = 32, OPT = 2;
+  __shared__ C2<R> xs[TC * 64];
+  const int b = blockIdx.x;
+  const int r0 = box_start[b], nb = box_start[b + 1] - r0;
+  const int32_t* cols = bcol + bcol_ptr[b];
+  int t0 = 0, t1 = bcol_ptr[b + 1] - bcol_ptr[b];
+  if (mode == 1) {
+    t0 = self_off[b];
+    t1 = t0 + nb;
+  }
+  const int ncg = nc / 4;
+  const int nout = nb * ncg;
+  for (int base = 0; base < nout; base += (int)blockDim.x * OPT) {
+    double2 acc[OPT][4];
+#pragma unroll
+    for (int u = 0; u < OPT; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[u][q] = make_double2(0.0, 0.0);
+    for (int tc0 = t0; tc0 < t1; tc0 += TC) {
+      const int tn = min(TC, t1 - tc0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < tn * nc; e += blockDim.x) {
+        const int tt = e / nc, c = e % nc;
+        xs[tt * nc + c] = xi[(int64_t)cols[tc0 + tt] * nc + c];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < OPT; ++u) {
+        const int o = base + u * blockDim.x + threadIdx.x;
+        if (o >= nout) continue;
+        const int ii = o / ncg, cg = o % ncg;
+        const double2* z = Zn + row_ptr[r0 + ii] + tc0;
+        for (int tt = 0; tt < tn; ++tt) {
+          double2 v = z[tt];
+          if (mode == 1) v.y = 0.0;
+          if (mode == 2) {
+            v.x = v.y;
+            v.y = 0.0;
+          }
+          const C2<R>* xr = xs + tt * nc + cg * 4;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double xr_ = (double)xr[q].x, xim = (double)xr[q].y;
+            acc[u][q].x = fma(v.x, xr_, acc[u][q].x);
+            acc[u][q].x = fma(-v.y, xim, acc[u][q].x);
+            acc[u][q].y = fma(v.x, xim, acc[u][q].y);
+            acc[u][q].y = fma(v.y, xr_, acc[u][q].y);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < OPT; ++u) {
+      const int o = base + u * blockDim.x + threadIdx.x;
+      if (o >= nout) continue;
+      const int ii = o / ncg, cg = o % ncg;
+      C2<R>* out = yi + (int64_t)(r0 + ii) * nc + cg * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[q] = mk<R>((R)acc[u][q].x, (R)acc[u][q].y);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- aggregation
 // S_b(q) = sum_{j in box b} V_j(q) x_j  (eq. (13) summed over the box), 2 components.
 // CG columns per thread (1, or 4 when nc % 4 == 0): one leaf-pattern load feeds
 // CG complex multiply-adds.
 template <typename R, int CG>
 __global__ void __launch_bounds__(256) k_aggregate(const C2<R>* __restrict__ V, const C2<R>* __restrict__ xi,
-                                                   C2<R>* __restrict__ S, const int32_t* __restrict__ box_start,
-                                                   int K, int nc) {
+                                                   int ldx, C2<R>* __restrict__ S, int ldS,
+                                                   const int32_t* __restrict__ box_start, int K, int nc) {
   const int b = blockIdx.x;
   const int j0 = box_start[b], j1 = box_start[b + 1];
   const int ncg = nc / CG;
@@ -138,11 +214,11 @@ __global__ void __launch_bounds__(256) k_aggregate(const C2<R>* __restrict__ V, 
     for (int u = 0; u < CG; ++u) acc[u] = mk<R>(0, 0);
     for (int j = j0; j < j1; ++j) {
       const C2<R> v = V[(int64_t)j * 2 * K + cq];
-      const C2<R>* xr = xi + (int64_t)j * nc + cg * CG;
+      const C2<R>* xr = xi + (int64_t)j * ldx + cg * CG;
 #pragma unroll
       for (int u = 0; u < CG; ++u) acc[u] = cfma(acc[u], v, xr[u]);
     }
-    C2<R>* out = S + ((int64_t)b * 2 * K + cq) * nc + cg * CG;
+    C2<R>* out = S + ((int64_t)b * 2 * K + cq) * ldS + cg * CG;
 #pragma unroll
     for (int u = 0; u < CG; ++u) out[u] = acc[u];
   }
@@ -160,7 +236,7 @@ template <typename R, int JMAX>
 __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restrict__ Sc, C2<R>* __restrict__ Sp,
                                                    const int32_t* __restrict__ child_ptr,
                                                    const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
-                                                   int cs, int tpc) {
+                                                   int cs, int tpc, int ldp, int accum) {
   extern __shared__ unsigned char smem_raw[];
   C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [ntc][npp][cs]
   const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, p = P.p, Kp = P.K;
@@ -176,17 +252,17 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) acc[j] = mk<R>(0, 0);
   for (int ch = child_ptr[m]; ch < child_ptr[m + 1]; ++ch) {
-    const C2<R>* src = Sc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
+    const C2<R>* src = Sc + ((int64_t)ch * 2 + comp) * Kc * ldp + c0;
     const int oc = octant[ch];
     __syncthreads();
     for (int e = threadIdx.x; e < nmid; e += blockDim.x) {
       const int c = e % cs, up = (e / cs) % npp, tc = e / (cs * npp);
       C2<R> a = mk<R>(0, 0);
       if (c < cw) {
-        const C2<R>* row = src + (int64_t)tc * npc * nc + c;
+        const C2<R>* row = src + (int64_t)tc * npc * ldp + c;
         for (int j = 0; j < p; ++j) {
           const R w = P.ph_w[up * p + j];
-          const C2<R> v = row[(int64_t)P.ph_idx[up * p + j] * nc];
+          const C2<R> v = row[(int64_t)P.ph_idx[up * p + j] * ldp];
           a.x = fma(w, v.x, a.x);
           a.y = fma(w, v.y, a.y);
         }
@@ -212,13 +288,21 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
       }
     }
   }
-  C2<R>* out = Sp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+  C2<R>* out = Sp + ((int64_t)m * 2 + comp) * Kp * ldp + c0;
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) {
     const int o = threadIdx.x + j * blockDim.x;
     if (o < nout) {
       const int c = o % cs, q = tp0 * npp + o / cs;
-      if (c < cw) out[(int64_t)q * nc + c] = acc[j];
+      if (c < cw) {
+        C2<R>& o = out[(int64_t)q * ldp + c];
+        if (accum) {
+          o.x += acc[j].x;
+          o.y += acc[j].y;
+        } else {
+          o = acc[j];
+        }
+      }
     }
   }
 }
@@ -234,7 +318,7 @@ template <typename R, bool STAGE>
 __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tsrc,
                                              const int16_t* __restrict__ toff, const C2<R>* __restrict__ T,
                                              int n_off, const C2<R>* __restrict__ S, C2<R>* __restrict__ G,
-                                             int nbox, int K, int nc, int cw) {
+                                             int nbox, int K, int nc, int cw, int ldp, int accum) {
   extern __shared__ unsigned char smem_raw[];
   C2<R>* Ts = reinterpret_cast<C2<R>*>(smem_raw);    // [n_off][qb]
   const int tile = blockIdx.x;
@@ -254,12 +338,20 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
 #pragma unroll
   for (int r = 0; r < kTile; ++r) a0[r] = a1[r] = mk<R>(0, 0);
   const int e0 = tptr[tile], e1 = tptr[tile + 1];
+  // software pipelining: the next source's pattern loads are in flight while
+  // the current one is applied to the tile's receivers
+  C2<R> n0 = mk<R>(0, 0), n1 = mk<R>(0, 0);
+  if (act && e0 < e1) {
+    const int sb = tsrc[e0];
+    n0 = S[(((int64_t)sb * 2 + 0) * K + q) * ldp + c];
+    n1 = S[(((int64_t)sb * 2 + 1) * K + q) * ldp + c];
+  }
   for (int e = e0; e < e1; ++e) {
-    const int sb = tsrc[e];
-    C2<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
-    if (act) {
-      s0 = S[(((int64_t)sb * 2 + 0) * K + q) * nc + c];
-      s1 = S[(((int64_t)sb * 2 + 1) * K + q) * nc + c];
+    const C2<R> s0 = n0, s1 = n1;
+    if (act && e + 1 < e1) {
+      const int sb = tsrc[e + 1];
+      n0 = S[(((int64_t)sb * 2 + 0) * K + q) * ldp + c];
+      n1 = S[(((int64_t)sb * 2 + 1) * K + q) * ldp + c];
     }
     const int16_t* of = toff + (int64_t)e * kTile;
 #pragma unroll
@@ -277,8 +369,17 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
   for (int r = 0; r < kTile; ++r) {
     const int m = tile * kTile + r;
     if (m < nbox) {
-      G[(((int64_t)m * 2 + 0) * K + q) * nc + c] = a0[r];
-      G[(((int64_t)m * 2 + 1) * K + q) * nc + c] = a1[r];
+      C2<R>& g0 = G[(((int64_t)m * 2 + 0) * K + q) * ldp + c];
+      C2<R>& g1 = G[(((int64_t)m * 2 + 1) * K + q) * ldp + c];
+      if (accum) {
+        g0.x += a0[r].x;
+        g0.y += a0[r].y;
+        g1.x += a1[r].x;
+        g1.y += a1[r].y;
+      } else {
+        g0 = a0[r];
+        g1 = a1[r];
+      }
     }
   }
 }
@@ -292,7 +393,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restrict__ Gp, C2<R>* __restrict__ Gc,
                                                      const int32_t* __restrict__ parent,
                                                      const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
-                                                     int cs) {
+                                                     int cs, int ldp) {
   extern __shared__ unsigned char smem_raw[];
   C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [ntp][npc][cs]
   const int ch = blockIdx.x, c0 = blockIdx.y * cs, comp = blockIdx.z;
@@ -301,7 +402,7 @@ __global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restr
   const int hc = npc / 2;
   const int m = parent[ch], oc = octant[ch];
   const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift) + oc * Kp;
-  const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+  const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * ldp + c0;
   for (int e = threadIdx.x; e < ntp * npc * cs; e += blockDim.x) {
     const int c = e % cs, uc = (e / cs) % npc, tp = e / (cs * npc);
     C2<R> a = mk<R>(0, 0);
@@ -309,7 +410,7 @@ __global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restr
       for (int j = P.pht_ptr[uc]; j < P.pht_ptr[uc + 1]; ++j) {
         const int up = P.pht_idx[j];
         const R w = P.pht_w[j];
-        const C2<R> v = g[(int64_t)(tp * npp + up) * nc + c];
+        const C2<R> v = g[(int64_t)(tp * npp + up) * ldp + c];
         C2<R> t = mk<R>(0, 0);
         t = cfma_conj(t, shift[tp * npp + up], v);
         a.x = fma(w, t.x, a.x);
@@ -319,7 +420,7 @@ __global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restr
     tmp[e] = a;
   }
   __syncthreads();
-  C2<R>* out = Gc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
+  C2<R>* out = Gc + ((int64_t)ch * 2 + comp) * Kc * ldp + c0;
   for (int e = threadIdx.x; e < ntc * npc * cs; e += blockDim.x) {
     const int c = e % cs, uc = (e / cs) % npc, tc = e / (cs * npc);
     if (c >= cw) continue;
@@ -332,7 +433,7 @@ __global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restr
       a.x = fma(w, v.x, a.x);
       a.y = fma(w, v.y, a.y);
     }
-    C2<R>& o = out[(int64_t)(tc * npc + uc) * nc + c];
+    C2<R>& o = out[(int64_t)(tc * npc + uc) * ldp + c];
     o.x += a.x;
     o.y += a.y;
   }
@@ -348,7 +449,7 @@ template <typename R, int JMAX>
 __global__ void __launch_bounds__(256) k_interp_up(const C2<R>* __restrict__ Sc, C2<R>* __restrict__ Sp,
                                                    const int32_t* __restrict__ child_ptr,
                                                    const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
-                                                   int cs, int tpc) {
+                                                   int cs, int tpc, int ldp, int accum) {
   extern __shared__ unsigned char smem_raw[];
   const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, p = P.p, Kp = P.K;
   C2<R>* A = reinterpret_cast<C2<R>*>(smem_raw);            // [ntc][npc][cs]
@@ -377,12 +478,12 @@ __global__ void __launch_bounds__(256) k_interp_up(const C2<R>* __restrict__ Sc,
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) acc[j] = mk<R>(0, 0);
   for (int ch = child_ptr[m]; ch < child_ptr[m + 1]; ++ch) {
-    const C2<R>* src = Sc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
+    const C2<R>* src = Sc + ((int64_t)ch * 2 + comp) * Kc * ldp + c0;
     const int oc = octant[ch];
     __syncthreads();
     for (int e = threadIdx.x; e < Kc * cs; e += blockDim.x) {
       const int c = e % cs, q = e / cs;
-      A[e] = (c < cw) ? src[(int64_t)q * nc + c] : mk<R>(0, 0);
+      A[e] = (c < cw) ? src[(int64_t)q * ldp + c] : mk<R>(0, 0);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < ntc * npp * cs; e += blockDim.x) {
@@ -419,29 +520,41 @@ __global__ void __launch_bounds__(256) k_interp_up(const C2<R>* __restrict__ Sc,
       }
     }
   }
-  C2<R>* out = Sp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+  C2<R>* out = Sp + ((int64_t)m * 2 + comp) * Kp * ldp + c0;
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) {
     const int o = threadIdx.x + j * blockDim.x;
     if (o < nout) {
       const int c = o % cs, q = tp0 * npp + o / cs;
-      if (c < cw) out[(int64_t)q * nc + c] = acc[j];
+      if (c < cw) {
+        C2<R>& o = out[(int64_t)q * ldp + c];
+        if (accum) {
+          o.x += acc[j].x;
+          o.y += acc[j].y;
+        } else {
+          o = acc[j];
+        }
+      }
     }
   }
 }
 
+// Per-parent anterpolation: the block stages its parent's pattern once, then
+// for each child applies the conjugated shift (LDS -> LDS), the phi-transpose
+// stencil (LDS -> LDS) and the theta-transpose stencil (LDS -> child, RMW).
+// LDS: P0 [Kp][cs], A [Kp][cs], B [ntp][npc][cs], stencil tables.
 template <typename R>
 __global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ Gp, C2<R>* __restrict__ Gc,
-                                                     const int32_t* __restrict__ parent,
+                                                     const int32_t* __restrict__ child_ptr,
                                                      const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
-                                                     int cs) {
+                                                     int cs, int ldp) {
   extern __shared__ unsigned char smem_raw[];
   const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, Kp = P.K;
-  C2<R>* A = reinterpret_cast<C2<R>*>(smem_raw);            // [ntp][npp][cs]
+  C2<R>* P0 = reinterpret_cast<C2<R>*>(smem_raw);           // [ntp][npp][cs]
+  C2<R>* A = P0 + Kp * cs;                                   // shifted copy
   C2<R>* B = A + Kp * cs;                                    // [ntp][npc][cs]
-  // transposed stencils (CSR) copied to LDS
   const int nph = P.pht_ptr[npc], nth = P.tht_ptr[ntc];
-  R* phW = reinterpret_cast<R*>(B + ntp * npc * cs);       // weights first (alignment)
+  R* phW = reinterpret_cast<R*>(B + ntp * npc * cs);
   R* thW = phW + nph;
   int32_t* phP = reinterpret_cast<int32_t*>(thW + nth);
   int32_t* thP = phP + npc + 1;
@@ -457,49 +570,53 @@ __global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ G
     thI[e] = P.tht_idx[e] | (P.tht_ref[e] << 30);
     thW[e] = P.tht_ref[e] ? -P.tht_w[e] : P.tht_w[e];
   }
-  const int ch = blockIdx.x, c0 = blockIdx.y * cs, comp = blockIdx.z;
+  const int m = blockIdx.x, c0 = blockIdx.y * cs, comp = blockIdx.z;
   const int cw = min(cs, nc - c0);
   const int hc = npc / 2;
-  const int m = parent[ch], oc = octant[ch];
-  const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift) + oc * Kp;
-  const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * nc + c0;
+  const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * ldp + c0;
   for (int e = threadIdx.x; e < Kp * cs; e += blockDim.x) {
     const int c = e % cs, q = e / cs;
-    C2<R> t = mk<R>(0, 0);
-    if (c < cw) t = cfma_conj(t, shift[q], g[(int64_t)q * nc + c]);
-    A[e] = t;
+    P0[e] = (c < cw) ? g[(int64_t)q * ldp + c] : mk<R>(0, 0);
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < ntp * npc * cs; e += blockDim.x) {
-    const int c = e % cs, uc = (e / cs) % npc, tp = e / (cs * npc);
-    const C2<R>* row = A + tp * npp * cs + c;
-    C2<R> a = mk<R>(0, 0);
-    for (int j = phP[uc]; j < phP[uc + 1]; ++j) {
-      const R w = phW[j];
-      const C2<R> v = row[phI[j]];
-      a.x = fma(w, v.x, a.x);
-      a.y = fma(w, v.y, a.y);
+  for (int ch = child_ptr[m]; ch < child_ptr[m + 1]; ++ch) {
+    const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift) + octant[ch] * Kp;
+    __syncthreads();
+    for (int e = threadIdx.x; e < Kp * cs; e += blockDim.x) {
+      C2<R> t = mk<R>(0, 0);
+      A[e] = cfma_conj(t, shift[e / cs], P0[e]);
     }
-    B[e] = a;
-  }
-  __syncthreads();
-  C2<R>* out = Gc + ((int64_t)ch * 2 + comp) * Kc * nc + c0;
-  for (int e = threadIdx.x; e < ntc * npc * cs; e += blockDim.x) {
-    const int c = e % cs, uc = (e / cs) % npc, tc = e / (cs * npc);
-    if (c >= cw) continue;
-    const int ucr = (uc + hc) % npc;
-    C2<R> a = mk<R>(0, 0);
-    for (int j = thP[tc]; j < thP[tc + 1]; ++j) {
-      const int code = thI[j];
-      const int tp = code & 0x3fffffff;
-      const R w = thW[j];
-      const C2<R> v = B[(tp * npc + ((code >> 30) ? ucr : uc)) * cs + c];
-      a.x = fma(w, v.x, a.x);
-      a.y = fma(w, v.y, a.y);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ntp * npc * cs; e += blockDim.x) {
+      const int c = e % cs, uc = (e / cs) % npc, tp = e / (cs * npc);
+      const C2<R>* row = A + tp * npp * cs + c;
+      C2<R> a = mk<R>(0, 0);
+      for (int j = phP[uc]; j < phP[uc + 1]; ++j) {
+        const R w = phW[j];
+        const C2<R> v = row[phI[j]];
+        a.x = fma(w, v.x, a.x);
+        a.y = fma(w, v.y, a.y);
+      }
+      B[e] = a;
     }
-    C2<R>& o = out[(int64_t)(tc * npc + uc) * nc + c];
-    o.x += a.x;
-    o.y += a.y;
+    __syncthreads();
+    C2<R>* out = Gc + ((int64_t)ch * 2 + comp) * Kc * ldp + c0;
+    for (int e = threadIdx.x; e < ntc * npc * cs; e += blockDim.x) {
+      const int c = e % cs, uc = (e / cs) % npc, tc = e / (cs * npc);
+      if (c >= cw) continue;
+      const int ucr = (uc + hc) % npc;
+      C2<R> a = mk<R>(0, 0);
+      for (int j = thP[tc]; j < thP[tc + 1]; ++j) {
+        const int code = thI[j];
+        const int tp = code & 0x3fffffff;
+        const R w = thW[j];
+        const C2<R> v = B[(tp * npc + ((code >> 30) ? ucr : uc)) * cs + c];
+        a.x = fma(w, v.x, a.x);
+        a.y = fma(w, v.y, a.y);
+      }
+      C2<R>& o = out[(int64_t)(tc * npc + uc) * ldp + c];
+      o.x += a.x;
+      o.y += a.y;
+    }
   }
 }
 
@@ -511,18 +628,19 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_disagg1(const C2<R>* __restrict__ V, const C2<R>* __restrict__ G,
                                                  const R* __restrict__ qwc, const C2<R>* __restrict__ yi,
                                                  const int32_t* __restrict__ box_of, const int32_t* __restrict__ perm,
-                                                 int K, int64_t N, C2<R>* __restrict__ y, int64_t ld, int conj_out) {
+                                                 int K, int64_t N, int ldp, C2<R>* __restrict__ y, int64_t ld,
+                                                 int conj_out) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= N) return;
   const int b = box_of[i];
   const C2<R>* v = V + i * 2 * K;
-  const C2<R>* g = G + (int64_t)b * 2 * K;
+  const C2<R>* g = G + (int64_t)b * 2 * K * ldp;
   R ax = 0, ay = 0;
   for (int cq = lane; cq < 2 * K; cq += 64) {
     const R w = qwc[cq < K ? cq : cq - K];
     const C2<R> a = v[cq];
-    const C2<R> gg = g[cq];
+    const C2<R> gg = g[(int64_t)cq * ldp];
     ax = fma(w * a.x, gg.x, ax);
     ax = fma(w * a.y, gg.y, ax);
     ay = fma(w * a.x, gg.y, ay);
@@ -537,7 +655,7 @@ __global__ void __launch_bounds__(256) k_disagg1(const C2<R>* __restrict__ V, co
     r.x += ax;
     r.y += ay;
     if (conj_out) r.y = -r.y;
-    y[(int64_t)perm[i] * ld] = r;
+    y[(int64_t)(perm ? perm[i] : i) * ld] = r;
   }
 }
 
@@ -546,12 +664,12 @@ template <typename R, int CG>
 __global__ void __launch_bounds__(256) k_disagg(const C2<R>* __restrict__ V, const C2<R>* __restrict__ G,
                                                 const R* __restrict__ qwc, const C2<R>* __restrict__ yi,
                                                 const int32_t* __restrict__ box_start,
-                                                const int32_t* __restrict__ perm, int K, int nc,
+                                                const int32_t* __restrict__ perm, int K, int nc, int ldp,
                                                 C2<R>* __restrict__ y, int64_t ld, int conj_out) {
   const int b = blockIdx.x;
   const int j0 = box_start[b], nb = box_start[b + 1] - j0;
   const int ncg = nc / CG;
-  const C2<R>* g = G + (int64_t)b * 2 * K * nc;
+  const C2<R>* g = G + (int64_t)b * 2 * K * ldp;
   for (int o = threadIdx.x; o < nb * ncg; o += blockDim.x) {
     const int cg = o % ncg, ii = o / ncg;
     const int64_t i = j0 + ii;
@@ -564,7 +682,7 @@ __global__ void __launch_bounds__(256) k_disagg(const C2<R>* __restrict__ V, con
       C2<R> a = v[cq];
       a.x *= w;
       a.y *= w;
-      const C2<R>* gr = g + (int64_t)cq * nc + cg * CG;
+      const C2<R>* gr = g + (int64_t)cq * ldp + cg * CG;
 #pragma unroll
       for (int u = 0; u < CG; ++u) acc[u] = cfma_conj(acc[u], a, gr[u]);
     }
@@ -574,9 +692,23 @@ __global__ void __launch_bounds__(256) k_disagg(const C2<R>* __restrict__ V, con
       r.x += acc[u].x;
       r.y += acc[u].y;
       if (conj_out) r.y = -r.y;
-      y[(int64_t)perm[i] * ld + cg * CG + u] = r;
+      y[(int64_t)(perm ? perm[i] : i) * ld + cg * CG + u] = r;
     }
   }
+}
+
+// y[:, 0:nc] += alpha x[:, 0:nc] over rows of a pattern buffer with column stride ld
+template <typename R>
+__global__ void __launch_bounds__(256) k_pattern_axpy(const C2<R>* __restrict__ x, C2<R>* __restrict__ y, int64_t rows,
+                                                      int nc, int ld, R alpha) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= rows * nc) return;
+  int64_t r = g / nc;
+  int c = (int)(g % nc);
+  C2<R> a = x[r * ld + c];
+  C2<R>& o = y[r * ld + c];
+  o.x += alpha * a.x;
+  o.y += alpha * a.y;
 }
 
 // ---------------------------------------------------------------- SAI apply
@@ -674,52 +806,37 @@ static void set_lds_limit(const void* f, size_t bytes) {
 }
 
 template <typename R>
-static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* x, void* y, int64_t ld, int nc,
-                       hipStream_t s) {
+struct Stages {
   using CR = C2<R>;
-  const int lf = d.lf;
-  const int64_t N = d.N;
-  CR* xi = (CR*)d.xi;
-  CR* yi = (CR*)d.yi;
-  const int conj = (op == 3);
-  const int kind = (op == 1) ? 1 : (op == 2) ? 2 : 0;   // 0 Z, 1 R, 2 X
-  {
-    int64_t tot = N * nc;
-    stage_begin(d, s, 0);
-    hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
-                       d.perm, xi, N, conj);
-    stage_end(d, s);
-  }
-  const dim3 rows_grid((unsigned)((N + 3) / 4));
-  stage_begin(d, s, 1);
-  hipLaunchKernelGGL(k_near<R>, rows_grid, dim3(256), 0, s, d.row_ptr, d.box_of, d.bcol_ptr, d.bcol, d.self_off,
-                     d.box_start, (const double2*)d.Zn, (const CR*)xi, yi, N, nc, kind);
-  stage_end(d, s);
-  // upward pass
-  {
-    const int K = P.lev[lf].K;
-    stage_begin(d, s, 2);
+  Dev& d;
+  const Plan& P;
+  PrecD<R>& pd;
+  hipStream_t s;
+
+  void aggregate(const void* V, const CR* xi, int ldx, CR* S, int ldS, int nc) {
+    const int K = P.lev[d.lf].K;
     if (nc % 4 == 0) {
       int tot = 2 * K * nc / 4;
       int gy = std::max(1, std::min(16, (tot + 255) / 256));
-      hipLaunchKernelGGL((k_aggregate<R, 4>), dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)pd.V, (const CR*)xi,
-                         (CR*)d.S[lf], d.box_start, K, nc);
+      hipLaunchKernelGGL((k_aggregate<R, 4>), dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)V, xi, ldx, S, ldS,
+                         d.box_start, K, nc);
     } else {
       int tot = 2 * K * nc;
       int gy = std::max(1, std::min(16, (tot + 255) / 256));
-      hipLaunchKernelGGL((k_aggregate<R, 1>), dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)pd.V, (const CR*)xi,
-                         (CR*)d.S[lf], d.box_start, K, nc);
+      hipLaunchKernelGGL((k_aggregate<R, 1>), dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)V, xi, ldx, S, ldS,
+                         d.box_start, K, nc);
     }
-    stage_end(d, s);
   }
-  constexpr int kJ = sizeof(R) == 4 ? 16 : 8;
-  for (int l = lf - 1; l >= 2; --l) {
-    LevelD<R>& Lp = pd.lev[l];
+
+  // child level l+1 -> level l; shift = per-octant phase table (or its k-derivative)
+  void interp(int l, const CR* Sc, CR* Sp, int nc, int ldp, int accum, const void* shift) {
+    constexpr int kJ = sizeof(R) == 4 ? 16 : 8;
+    LevelD<R> Lp = pd.lev[l];
+    Lp.shift = const_cast<void*>(shift);
     const int Kc = P.lev[l + 1].K;
-    const int per_col = (Lp.ntc * Lp.npc + Lp.ntc * Lp.np) * (int)sizeof(CR);   // staged LDS per column
+    const int per_col = (Lp.ntc * Lp.npc + Lp.ntc * Lp.np) * (int)sizeof(CR);
     const int tables = (Lp.np + Lp.nt) * Lp.p * (4 + (int)sizeof(R));
     const dim3 blk(256);
-    stage_begin(d, s, 3 + 10 * l);
     if (per_col + tables <= 96 * 1024 && Lp.np <= kJ * 256) {
       int cs = std::max(1, std::min(nc, (64 * 1024 - tables) / per_col));
       while (cs > 1 && std::min(Lp.nt * Lp.np, kJ * 256) * cs > kJ * 256) --cs;
@@ -727,8 +844,8 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
       const int nchunk = (Lp.nt + tpc - 1) / tpc;
       const size_t sh = (size_t)per_col * cs + tables;
       set_lds_limit((const void*)k_interp_up<R, kJ>, sh);
-      hipLaunchKernelGGL((k_interp_up<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s,
-                         (const CR*)d.S[l + 1], (CR*)d.S[l], Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc);
+      hipLaunchKernelGGL((k_interp_up<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s, Sc, Sp,
+                         Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc, ldp, accum);
     } else {
       const int cs = interp_cs<R>(nc, Lp.ntc, Lp.np, std::min(Lp.nt * Lp.np, kJ * 256), kJ, 256);
       const int tpc = std::max(1, std::min(Lp.nt, kJ * 256 / (Lp.np * cs)));
@@ -737,15 +854,13 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
       if (sh > 160 * 1024 || tpc * Lp.np * cs > kJ * 256)
         throw Error(-7, "angular grid too large for the interpolation kernel");
       set_lds_limit((const void*)k_interp_up_direct<R, kJ>, sh);
-      hipLaunchKernelGGL((k_interp_up_direct<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s,
-                         (const CR*)d.S[l + 1], (CR*)d.S[l], Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc);
+      hipLaunchKernelGGL((k_interp_up_direct<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s, Sc,
+                         Sp, Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc, ldp, accum);
     }
-    stage_end(d, s);
   }
-  // translations
-  for (int l = 2; l <= lf; ++l) {
+
+  void m2l(int l, int kind, const void* T, const CR* S, CR* G, int nc, int ldp, int accum) {
     LevelD<R>& Lv = pd.lev[l];
-    const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
     const int32_t* tptr = (kind == 1) ? Lv.tileR_ptr : Lv.tile_ptr;
     const int32_t* tsrc = (kind == 1) ? Lv.tileR_src : Lv.tile_src;
     const int16_t* toff = (kind == 1) ? Lv.tileR_off : Lv.tile_off;
@@ -755,59 +870,129 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     const size_t sh = (size_t)Lv.n_off * qb * sizeof(CR);
     const bool stage = (cw >= 8) && sh <= 64 * 1024;
     dim3 grid(Lv.ntile, (Lv.K + qb - 1) / qb, (nc + cw - 1) / cw);
-    stage_begin(d, s, 4 + 10 * l);
     if (stage)
-      hipLaunchKernelGGL((k_m2l<R, true>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off,
-                         (const CR*)d.S[l], (CR*)d.G[l], Lv.nbox, Lv.K, nc, cw);
+      hipLaunchKernelGGL((k_m2l<R, true>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S, G,
+                         Lv.nbox, Lv.K, nc, cw, ldp, accum);
     else
-      hipLaunchKernelGGL((k_m2l<R, false>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off,
-                         (const CR*)d.S[l], (CR*)d.G[l], Lv.nbox, Lv.K, nc, cw);
-    stage_end(d, s);
+      hipLaunchKernelGGL((k_m2l<R, false>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
+                         G, Lv.nbox, Lv.K, nc, cw, ldp, accum);
   }
-  // downward pass
-  for (int l = 2; l < lf; ++l) {
-    LevelD<R>& Lp = pd.lev[l];
+
+  // level l -> child level l+1 (accumulates into the child patterns)
+  void anterp(int l, const CR* Gp, CR* Gc, int nc, int ldp, const void* shift) {
+    LevelD<R> Lp = pd.lev[l];
+    Lp.shift = const_cast<void*>(shift);
     const int Kc = P.lev[l + 1].K;
-    const int per_col = (Lp.nt * Lp.np + Lp.nt * Lp.npc) * (int)sizeof(CR);
+    const int per_col = (2 * Lp.nt * Lp.np + Lp.nt * Lp.npc) * (int)sizeof(CR);
     const Interp& Ip = P.ip[l];
     const int tables = (Lp.npc + 1 + Lp.ntc + 1) * 4 +
                        (int)(Ip.pht_idx.size() + Ip.tht_idx.size()) * (4 + (int)sizeof(R)) + 16;
-    stage_begin(d, s, 5 + 10 * (l + 1));
-    if (per_col + tables <= 96 * 1024) {
-      const int cs = std::max(1, std::min(nc, (64 * 1024 - tables) / per_col));
+    if (per_col + tables <= 144 * 1024) {
+      const int cs = std::max(1, std::min(nc, (48 * 1024 - tables) / per_col));   // >= 3 blocks per CU
       const size_t sh = (size_t)per_col * cs + tables;
       set_lds_limit((const void*)k_anterp_down<R>, sh);
-      hipLaunchKernelGGL(k_anterp_down<R>, dim3(pd.lev[l + 1].nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s,
-                         (const CR*)d.G[l], (CR*)d.G[l + 1], pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc,
-                         cs);
+      hipLaunchKernelGGL(k_anterp_down<R>, dim3(Lp.nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s, Gp, Gc,
+                         Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, ldp);
     } else {
       const int cs = interp_cs<R>(nc, Lp.nt, Lp.npc, 0, 1, 1);
       const size_t sh = (size_t)Lp.nt * Lp.npc * cs * sizeof(CR);
       if (sh > 160 * 1024) throw Error(-7, "anterpolation LDS grid exceeds 160 KiB");
       set_lds_limit((const void*)k_anterp_down_direct<R>, sh);
       hipLaunchKernelGGL(k_anterp_down_direct<R>, dim3(pd.lev[l + 1].nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s,
-                         (const CR*)d.G[l], (CR*)d.G[l + 1], pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc,
-                         cs);
+                         Gp, Gc, pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc, cs, ldp);
     }
+  }
+
+  // y = yi + (k^2 eta/4pi) sum_q w_q conj(V) . G; perm == nullptr writes internal order
+  void disagg(const void* V, const CR* G, int ldp, const CR* yi, CR* y, int64_t ld, const int32_t* perm, int nc,
+              int conj) {
+    const int K = P.lev[d.lf].K;
+    if (nc == 1)
+      hipLaunchKernelGGL(k_disagg1<R>, dim3((unsigned)((d.N + 3) / 4)), dim3(256), 0, s, (const CR*)V, G,
+                         (const R*)pd.qwc, yi, d.box_of, perm, K, d.N, ldp, y, ld, conj);
+    else if (nc % 4 == 0)
+      hipLaunchKernelGGL((k_disagg<R, 4>), dim3(d.nleaf), dim3(256), 0, s, (const CR*)V, G, (const R*)pd.qwc, yi,
+                         d.box_start, perm, K, nc, ldp, y, ld, conj);
+    else
+      hipLaunchKernelGGL((k_disagg<R, 1>), dim3(d.nleaf), dim3(256), 0, s, (const CR*)V, G, (const R*)pd.qwc, yi,
+                         d.box_start, perm, K, nc, ldp, y, ld, conj);
+  }
+};
+
+template <typename R>
+static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* x, void* y, int64_t ld, int nc,
+                       hipStream_t s) {
+  using CR = C2<R>;
+  const int lf = d.lf;
+  const int64_t N = d.N;
+  CR* xi = (CR*)d.xi;
+  CR* yi = (CR*)d.yi;
+  const bool dual = (op == 4);                          // dZ/dk: values and k-derivatives side by side
+  const int conj = (op == 3);
+  const int kind = (op == 1) ? 1 : (op == 2) ? 2 : 0;   // 0 Z, 1 R, 2 X
+  const int ldp = dual ? 2 * nc : nc;                   // pattern column stride
+  Stages<R> st{d, P, pd, s};
+  {
+    int64_t tot = N * nc;
+    stage_begin(d, s, 0);
+    hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
+                       d.perm, xi, N, conj);
+    stage_end(d, s);
+  }
+  const dim3 rows_grid((unsigned)((N + 3) / 4));
+  stage_begin(d, s, 1);
+  if (nc % 4 == 0 && nc <= 64)
+    hipLaunchKernelGGL(k_near_box<R>, dim3(d.nleaf), dim3(256), 0, s, d.row_ptr, d.box_start, d.bcol_ptr, d.bcol,
+                       d.self_off, (const double2*)(dual ? d.dZn : d.Zn), (const CR*)xi, yi, nc, kind);
+  else
+    hipLaunchKernelGGL(k_near<R>, rows_grid, dim3(256), 0, s, d.row_ptr, d.box_of, d.bcol_ptr, d.bcol, d.self_off,
+                       d.box_start, (const double2*)(dual ? d.dZn : d.Zn), (const CR*)xi, yi, N, nc, kind);
+  stage_end(d, s);
+  // upward pass
+  stage_begin(d, s, 2);
+  st.aggregate(pd.V, xi, nc, (CR*)d.S[lf], ldp, nc);
+  if (dual) st.aggregate(pd.dV, xi, nc, (CR*)d.S[lf] + nc, ldp, nc);
+  stage_end(d, s);
+  for (int l = lf - 1; l >= 2; --l) {
+    stage_begin(d, s, 3 + 10 * l);
+    st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l], dual ? 2 * nc : nc, ldp, 0, pd.lev[l].shift);
+    if (dual) st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l] + nc, nc, ldp, 1, pd.lev[l].dshift);
+    stage_end(d, s);
+  }
+  // translations
+  for (int l = 2; l <= lf; ++l) {
+    LevelD<R>& Lv = pd.lev[l];
+    const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
+    stage_begin(d, s, 4 + 10 * l);
+    st.m2l(l, kind, T, (const CR*)d.S[l], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, 0);
+    if (dual) st.m2l(l, 0, Lv.dTZ, (const CR*)d.S[l], (CR*)d.G[l] + nc, nc, ldp, 1);
+    stage_end(d, s);
+  }
+  // downward pass
+  for (int l = 2; l < lf; ++l) {
+    stage_begin(d, s, 5 + 10 * (l + 1));
+    st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift);
+    if (dual) st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift);
     stage_end(d, s);
   }
   stage_begin(d, s, 6);
-  if (nc == 1)
-    hipLaunchKernelGGL(k_disagg1<R>, rows_grid, dim3(256), 0, s, (const CR*)pd.V, (const CR*)d.G[lf],
-                       (const R*)pd.qwc, (const CR*)yi, d.box_of, d.perm, P.lev[lf].K, N, (CR*)y, ld, conj);
-  else if (nc % 4 == 0)
-    hipLaunchKernelGGL((k_disagg<R, 4>), dim3(d.nleaf), dim3(256), 0, s, (const CR*)pd.V, (const CR*)d.G[lf],
-                       (const R*)pd.qwc, (const CR*)yi, d.box_start, d.perm, P.lev[lf].K, nc, (CR*)y, ld, conj);
-  else
-    hipLaunchKernelGGL((k_disagg<R, 1>), dim3(d.nleaf), dim3(256), 0, s, (const CR*)pd.V, (const CR*)d.G[lf],
-                       (const R*)pd.qwc, (const CR*)yi, d.box_start, d.perm, P.lev[lf].K, nc, (CR*)y, ld, conj);
+  if (dual) {
+    // d/dk of (k^2 eta/4pi) sum w conj(V).G = (2/k)(...) + conj(dV).G + conj(V).dG
+    const int64_t rows = (int64_t)d.nleaf * 2 * P.lev[lf].K;
+    hipLaunchKernelGGL(k_pattern_axpy<R>, dim3((unsigned)((rows * nc + 255) / 256)), dim3(256), 0, s,
+                       (const CR*)d.G[lf], (CR*)d.G[lf] + nc, rows, nc, ldp, (R)(2.0 / P.k));
+    st.disagg(pd.dV, (const CR*)d.G[lf], ldp, yi, yi, nc, nullptr, nc, 0);
+    st.disagg(pd.V, (const CR*)d.G[lf] + nc, ldp, yi, (CR*)y, ld, d.perm, nc, 0);
+  } else {
+    st.disagg(pd.V, (const CR*)d.G[lf], ldp, yi, (CR*)y, ld, d.perm, nc, conj);
+  }
   stage_end(d, s);
   chk(hipGetLastError(), "apply launch");
 }
 
 void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
                hipStream_t s) {
-  if (op == 4) throw Error(-7, "dZ/dk apply is not available in this build");
+  if (op == 4 && (!d.dZn || !d.f64.dV)) throw Error(-5, "dZ/dk needs CM_FLAG_DERIV at create");
   if (fp64)
     apply_impl<double>(d, P, d.f64, op, x, y, ld, nc, s);
   else

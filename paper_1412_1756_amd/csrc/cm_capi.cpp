@@ -106,6 +106,7 @@ static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<in
       D.pht_idx = upload(d, I.pht_idx, s);
       D.pht_w = upload(d, cast<R>(I.pht_w), s);
       D.shift = upload_complex<R>(d, P.shift[l], s);
+      if (P.opt.flags & CM_FLAG_DERIV) D.dshift = upload_complex<R>(d, P.dshift[l], s);
     }
   }
   for (int l = 2; l <= lf; ++l) pd.lev[l].octant = reinterpret_cast<int8_t*>(lists[8 * (lf + 1) + l]);
@@ -204,8 +205,9 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   // workspace
   d.S.assign(lf + 1, nullptr);
   d.G.assign(lf + 1, nullptr);
+  const int colmul = deriv ? 2 : 1;   // the dZ/dk pass keeps values and derivatives side by side
   for (int l = 2; l <= lf; ++l) {
-    size_t b = (size_t)P.lev[l].nbox * 2 * P.lev[l].K * d.max_cols * sizeof(double2);
+    size_t b = (size_t)P.lev[l].nbox * 2 * P.lev[l].K * d.max_cols * colmul * sizeof(double2);
     d.S[l] = dmalloc(d, b);
     d.G[l] = dmalloc(d, b);
   }

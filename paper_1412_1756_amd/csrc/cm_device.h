@@ -44,6 +44,7 @@ struct LevelD {
   int32_t *tht_ptr = nullptr, *tht_idx = nullptr, *tht_ref = nullptr, *pht_ptr = nullptr, *pht_idx = nullptr;
   R *tht_w = nullptr, *pht_w = nullptr;
   void* shift = nullptr;                    // 8 x K complex<R>: exp(ik khat.(r_child - r_parent))
+  void* dshift = nullptr;                   // its k-derivative (CM_FLAG_DERIV)
 };
 
 template <typename R>

@@ -572,6 +572,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
   // ---- interpolation (child l+1 -> parent l, l = 2..lf-1) and shift phases
   ip.assign(lf + 1, Interp());
   shift.assign(lf + 1, {});
+  dshift.assign(lf + 1, {});
   const int p = o.p;
   for (int l = 2; l < lf; ++l) {
     const Level& C = lev[l + 1];
@@ -652,13 +653,16 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     }
     // shift phases exp(ik khat . (r_child - r_parent)) for the 8 octants
     shift[l].resize(8 * (size_t)P.K);
+    dshift[l].resize(8 * (size_t)P.K);
     for (int oc = 0; oc < 8; ++oc) {
       double dv[3] = {((oc & 1) ? 0.5 : -0.5) * C.a, ((oc & 2) ? 0.5 : -0.5) * C.a,
                       ((oc & 4) ? 0.5 : -0.5) * C.a};
       for (int q = 0; q < P.K; ++q) {
         const double* D = &dirs[l][9 * (size_t)q];
-        double ph = k * (D[0] * dv[0] + D[1] * dv[1] + D[2] * dv[2]);
+        double kd = D[0] * dv[0] + D[1] * dv[1] + D[2] * dv[2];
+        double ph = k * kd;
         shift[l][(size_t)oc * P.K + q] = cplx(std::cos(ph), std::sin(ph));
+        dshift[l][(size_t)oc * P.K + q] = cplx(0.0, kd) * cplx(std::cos(ph), std::sin(ph));
       }
     }
   }

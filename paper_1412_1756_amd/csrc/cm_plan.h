@@ -107,6 +107,7 @@ struct Plan {
   std::vector<std::vector<cplx>> TZ, TR, TX, dTZ;   // [level][n_off_used*K] (compact offset index)
   std::vector<std::vector<uint8_t>> off_used;        // [level][kNoff]
   std::vector<std::vector<cplx>> shift;             // [level l][8*K_l]: child l+1 -> l
+  std::vector<std::vector<cplx>> dshift;            // d shift / dk
   std::vector<std::vector<double>> qw;              // [level][K] quadrature weights
   std::vector<std::vector<double>> dirs;            // [level][9*K]: khat, theta-hat, phi-hat
 
