@@ -314,71 +314,110 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
 // receivers' lists; each source pattern element is loaded once and applied to
 // every receiver of the tile that lists it (register accumulators).  With
 // STAGE the block's translator rows are staged in LDS first.
-template <typename R, bool STAGE>
+template <typename R, bool STAGE, int QPT>
 __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tsrc,
-                                             const int16_t* __restrict__ toff, const C2<R>* __restrict__ T,
+                                             const int32_t* __restrict__ toff, const C2<R>* __restrict__ T,
                                              int n_off, const C2<R>* __restrict__ S, C2<R>* __restrict__ G,
-                                             int nbox, int K, int nc, int cw, int ldp, int accum) {
+                                             int nbox, int ntile, int K, int nc, int cw, int ldp, int accum) {
   extern __shared__ unsigned char smem_raw[];
-  C2<R>* Ts = reinterpret_cast<C2<R>*>(smem_raw);    // [n_off][qb]
-  const int tile = blockIdx.x;
-  const int qb = blockDim.x / cw;                     // directions per block
+  const int qb = blockDim.x / cw;                     // direction rows per block pass
+  const int qspan = qb * QPT;                         // directions per block
+  C2<R>* Ts = reinterpret_cast<C2<R>*>(smem_raw);    // [n_off][qspan]
+  // XCD-aware order: consecutive tiles (which share most sources) go to the
+  // same XCD, i.e. the same L2
+  const int per_xcd = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (tile >= ntile) return;
   const int c = blockIdx.z * cw + (int)(threadIdx.x % cw);
   const int ql = threadIdx.x / cw;
-  const int q = blockIdx.y * qb + ql;
-  const bool act = (ql < qb) && (q < K) && (c < nc);
+  const int qlr = min(ql, qb - 1);
+  int q[QPT];
+  bool act[QPT];
+#pragma unroll
+  for (int u = 0; u < QPT; ++u) {
+    q[u] = blockIdx.y * qspan + u * qb + ql;
+    act[u] = (ql < qb) && (q[u] < K) && (c < nc);
+  }
   if (STAGE) {
-    for (int e = threadIdx.x; e < n_off * qb; e += blockDim.x) {
-      const int f = e / qb, qq = blockIdx.y * qb + e % qb;
+    for (int e = threadIdx.x; e < n_off * qspan; e += blockDim.x) {
+      const int f = e / qspan, qq = blockIdx.y * qspan + e % qspan;
       Ts[e] = (qq < K) ? T[(int64_t)f * K + qq] : mk<R>(0, 0);
     }
     __syncthreads();
   }
-  C2<R> a0[kTile], a1[kTile];
+  C2<R> a0[QPT][kTile], a1[QPT][kTile];
 #pragma unroll
-  for (int r = 0; r < kTile; ++r) a0[r] = a1[r] = mk<R>(0, 0);
+  for (int u = 0; u < QPT; ++u)
+#pragma unroll
+    for (int r = 0; r < kTile; ++r) a0[u][r] = a1[u][r] = mk<R>(0, 0);
   const int e0 = tptr[tile], e1 = tptr[tile + 1];
   // software pipelining: the next source's pattern loads are in flight while
   // the current one is applied to the tile's receivers
-  C2<R> n0 = mk<R>(0, 0), n1 = mk<R>(0, 0);
-  if (act && e0 < e1) {
-    const int sb = tsrc[e0];
-    n0 = S[(((int64_t)sb * 2 + 0) * K + q) * ldp + c];
-    n1 = S[(((int64_t)sb * 2 + 1) * K + q) * ldp + c];
+  C2<R> n0[QPT], n1[QPT];
+#pragma unroll
+  for (int u = 0; u < QPT; ++u) {
+    n0[u] = n1[u] = mk<R>(0, 0);
+    if (act[u] && e0 < e1) {
+      const int sb = tsrc[e0];
+      n0[u] = S[(((int64_t)sb * 2 + 0) * K + q[u]) * ldp + c];
+      n1[u] = S[(((int64_t)sb * 2 + 1) * K + q[u]) * ldp + c];
+    }
   }
   for (int e = e0; e < e1; ++e) {
-    const C2<R> s0 = n0, s1 = n1;
-    if (act && e + 1 < e1) {
-      const int sb = tsrc[e + 1];
-      n0 = S[(((int64_t)sb * 2 + 0) * K + q) * ldp + c];
-      n1 = S[(((int64_t)sb * 2 + 1) * K + q) * ldp + c];
+    C2<R> s0[QPT], s1[QPT];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+      s0[u] = n0[u];
+      s1[u] = n1[u];
+      if (act[u] && e + 1 < e1) {
+        const int sb = tsrc[e + 1];
+        n0[u] = S[(((int64_t)sb * 2 + 0) * K + q[u]) * ldp + c];
+        n1[u] = S[(((int64_t)sb * 2 + 1) * K + q[u]) * ldp + c];
+      }
     }
-    const int16_t* of = toff + (int64_t)e * kTile;
+    // the tile's translator ids for this source: uniform, one batch of scalar loads
+    const int4* of4 = reinterpret_cast<const int4*>(toff + (int64_t)e * kTile);
+    int f[kTile];
+#pragma unroll
+    for (int r4 = 0; r4 < kTile / 4; ++r4) {
+      const int4 v = of4[r4];
+      f[4 * r4 + 0] = v.x;
+      f[4 * r4 + 1] = v.y;
+      f[4 * r4 + 2] = v.z;
+      f[4 * r4 + 3] = v.w;
+    }
 #pragma unroll
     for (int r = 0; r < kTile; ++r) {
-      const int f = of[r];
-      if (f >= 0) {
-        const C2<R> t = STAGE ? (act ? Ts[f * qb + ql] : mk<R>(0, 0)) : (act ? T[(int64_t)f * K + q] : mk<R>(0, 0));
-        a0[r] = cfma(a0[r], t, s0);
-        a1[r] = cfma(a1[r], t, s1);
+      if (f[r] >= 0) {
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+          // staged rows: in range for every thread (ql clamped), zero beyond K
+          const C2<R> t = STAGE ? Ts[f[r] * qspan + u * qb + qlr]
+                                : (act[u] ? T[(int64_t)f[r] * K + q[u]] : mk<R>(0, 0));
+          a0[u][r] = cfma(a0[u][r], t, s0[u]);
+          a1[u][r] = cfma(a1[u][r], t, s1[u]);
+        }
       }
     }
   }
-  if (!act) return;
 #pragma unroll
-  for (int r = 0; r < kTile; ++r) {
-    const int m = tile * kTile + r;
-    if (m < nbox) {
-      C2<R>& g0 = G[(((int64_t)m * 2 + 0) * K + q) * ldp + c];
-      C2<R>& g1 = G[(((int64_t)m * 2 + 1) * K + q) * ldp + c];
-      if (accum) {
-        g0.x += a0[r].x;
-        g0.y += a0[r].y;
-        g1.x += a1[r].x;
-        g1.y += a1[r].y;
-      } else {
-        g0 = a0[r];
-        g1 = a1[r];
+  for (int u = 0; u < QPT; ++u) {
+    if (!act[u]) continue;
+#pragma unroll
+    for (int r = 0; r < kTile; ++r) {
+      const int m = tile * kTile + r;
+      if (m < nbox) {
+        C2<R>& g0 = G[(((int64_t)m * 2 + 0) * K + q[u]) * ldp + c];
+        C2<R>& g1 = G[(((int64_t)m * 2 + 1) * K + q[u]) * ldp + c];
+        if (accum) {
+          g0.x += a0[u][r].x;
+          g0.y += a0[u][r].y;
+          g1.x += a1[u][r].x;
+          g1.y += a1[u][r].y;
+        } else {
+          g0 = a0[u][r];
+          g1 = a1[u][r];
+        }
       }
     }
   }
@@ -711,6 +750,105 @@ __global__ void __launch_bounds__(256) k_pattern_axpy(const C2<R>* __restrict__ 
   o.y += alpha * a.y;
 }
 
+
+// Batched aggregation, one block per leaf box: the box's x rows are staged in
+// LDS; thread = (4 columns, direction-component cq), looping over the box's
+// unknowns with one leaf-pattern load per 4 complex multiply-adds.
+template <typename R>
+__global__ void __launch_bounds__(256) k_aggregate_box(const C2<R>* __restrict__ V, const C2<R>* __restrict__ xi,
+                                                       int ldx, C2<R>* __restrict__ S, int ldS,
+                                                       const int32_t* __restrict__ box_start, int K, int nc) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<R>* xs = reinterpret_cast<C2<R>*>(smem_raw);          // [nb][nc]
+  const int b = blockIdx.x;
+  const int j0 = box_start[b], nb = box_start[b + 1] - j0;
+  for (int e = threadIdx.x; e < nb * nc; e += blockDim.x) xs[e] = xi[(int64_t)(j0 + e / nc) * ldx + e % nc];
+  __syncthreads();
+  const int ncg = nc / 4;
+  const int tot = 2 * K * ncg;
+  for (int o = blockIdx.y * blockDim.x + threadIdx.x; o < tot; o += gridDim.y * blockDim.x) {
+    const int cg = o % ncg, cq = o / ncg;
+    C2<R> a0 = mk<R>(0, 0), a1 = a0, a2 = a0, a3 = a0;
+    const C2<R>* v = V + (int64_t)j0 * 2 * K + cq;
+    const C2<R>* xr = xs + cg * 4;
+    for (int j = 0; j < nb; ++j) {
+      const C2<R> w = v[(int64_t)j * 2 * K];
+      a0 = cfma(a0, w, xr[0]);
+      a1 = cfma(a1, w, xr[1]);
+      a2 = cfma(a2, w, xr[2]);
+      a3 = cfma(a3, w, xr[3]);
+      xr += nc;
+    }
+    C2<R>* out = S + ((int64_t)b * 2 * K + cq) * ldS + cg * 4;
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
+    out[3] = a3;
+  }
+}
+
+// Batched disaggregation, one block per leaf box: chunks of 64 direction-
+// components of the box's incoming pattern G and of the box's leaf patterns
+// (weighted and conjugated) are staged in LDS; thread = (unknown, 4 columns).
+template <typename R>
+__global__ void __launch_bounds__(256) k_disagg_box(const C2<R>* __restrict__ V, const C2<R>* __restrict__ G,
+                                                    const R* __restrict__ qwc, const C2<R>* __restrict__ yi,
+                                                    const int32_t* __restrict__ box_start,
+                                                    const int32_t* __restrict__ perm, int K, int nc, int ldp,
+                                                    C2<R>* __restrict__ y, int64_t ld, int conj_out) {
+  constexpr int CH = 64;
+  extern __shared__ unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int j0 = box_start[b], nb = box_start[b + 1] - j0;
+  C2<R>* gs = reinterpret_cast<C2<R>*>(smem_raw);          // [CH][nc]
+  C2<R>* vs = gs + CH * nc;                                // [nb][CH]
+  const int ncg = nc / 4;
+  const int nout = nb * ncg;
+  const C2<R>* g = G + (int64_t)b * 2 * K * ldp;
+  for (int base = 0; base < nout; base += blockDim.x) {
+    const int o = base + threadIdx.x;
+    const int cg = o % ncg, ii = o / ncg;
+    C2<R> a0 = mk<R>(0, 0), a1 = a0, a2 = a0, a3 = a0;
+    for (int q0 = 0; q0 < 2 * K; q0 += CH) {
+      const int qn = min(CH, 2 * K - q0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < qn * nc; e += blockDim.x) gs[e] = g[(int64_t)(q0 + e / nc) * ldp + e % nc];
+      for (int e = threadIdx.x; e < nb * qn; e += blockDim.x) {
+        const int jj = e / qn, qq = e % qn;
+        const int cq = q0 + qq;
+        C2<R> v = V[(int64_t)(j0 + jj) * 2 * K + cq];
+        const R w = qwc[cq < K ? cq : cq - K];
+        vs[jj * CH + qq] = mk<R>(w * v.x, -w * v.y);       // w conj(V)
+      }
+      __syncthreads();
+      if (o < nout) {
+        const C2<R>* vr = vs + ii * CH;
+        const C2<R>* gr = gs + cg * 4;
+        for (int qq = 0; qq < qn; ++qq) {
+          const C2<R> w = vr[qq];
+          a0 = cfma(a0, w, gr[0]);
+          a1 = cfma(a1, w, gr[1]);
+          a2 = cfma(a2, w, gr[2]);
+          a3 = cfma(a3, w, gr[3]);
+          gr += nc;
+        }
+      }
+    }
+    if (o < nout) {
+      const int64_t i = j0 + ii;
+      C2<R> acc[4] = {a0, a1, a2, a3};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        C2<R> r = yi[i * nc + cg * 4 + u];
+        r.x += acc[u].x;
+        r.y += acc[u].y;
+        if (conj_out) r.y = -r.y;
+        y[(int64_t)(perm ? perm[i] : i) * ld + cg * 4 + u] = r;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- SAI apply
 // y_pub[perm[i]] = sum_t P[i, t] x_int[col[t]]  (FP64 products), one wavefront per row
 template <typename R>
@@ -815,7 +953,12 @@ struct Stages {
 
   void aggregate(const void* V, const CR* xi, int ldx, CR* S, int ldS, int nc) {
     const int K = P.lev[d.lf].K;
-    if (nc % 4 == 0) {
+    if (nc % 4 == 0 && (size_t)d.max_box * nc * sizeof(CR) <= 48 * 1024) {
+      int tot = 2 * K * nc / 4;
+      int gy = std::max(1, std::min(4, (tot + 1023) / 1024));
+      hipLaunchKernelGGL(k_aggregate_box<R>, dim3(d.nleaf, gy), dim3(256), (size_t)d.max_box * nc * sizeof(CR), s,
+                         (const CR*)V, xi, ldx, S, ldS, d.box_start, K, nc);
+    } else if (nc % 4 == 0) {
       int tot = 2 * K * nc / 4;
       int gy = std::max(1, std::min(16, (tot + 255) / 256));
       hipLaunchKernelGGL((k_aggregate<R, 4>), dim3(d.nleaf, gy), dim3(256), 0, s, (const CR*)V, xi, ldx, S, ldS,
@@ -863,19 +1006,27 @@ struct Stages {
     LevelD<R>& Lv = pd.lev[l];
     const int32_t* tptr = (kind == 1) ? Lv.tileR_ptr : Lv.tile_ptr;
     const int32_t* tsrc = (kind == 1) ? Lv.tileR_src : Lv.tile_src;
-    const int16_t* toff = (kind == 1) ? Lv.tileR_off : Lv.tile_off;
+    const int32_t* toff = (kind == 1) ? Lv.tileR_off : Lv.tile_off;
     const int cw = std::min(nc, 32);
     const int threads = (nc == 1) ? 64 : 256;           // single vector: more, smaller blocks
     const int qb = threads / cw;
+    const int gx = (Lv.ntile + 7) / 8 * 8;              // multiple of 8 for the XCD-aware tile order
+    const size_t sh2 = (size_t)Lv.n_off * qb * 2 * sizeof(CR);
+    if (sizeof(R) == 4 && cw >= 8 && sh2 <= 64 * 1024) {
+      dim3 grid(gx, (Lv.K + 2 * qb - 1) / (2 * qb), (nc + cw - 1) / cw);
+      hipLaunchKernelGGL((k_m2l<R, true, 2>), grid, dim3(threads), sh2, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off,
+                         S, G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
+      return;
+    }
     const size_t sh = (size_t)Lv.n_off * qb * sizeof(CR);
     const bool stage = (cw >= 8) && sh <= 64 * 1024;
-    dim3 grid(Lv.ntile, (Lv.K + qb - 1) / qb, (nc + cw - 1) / cw);
+    dim3 grid(gx, (Lv.K + qb - 1) / qb, (nc + cw - 1) / cw);
     if (stage)
-      hipLaunchKernelGGL((k_m2l<R, true>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S, G,
-                         Lv.nbox, Lv.K, nc, cw, ldp, accum);
+      hipLaunchKernelGGL((k_m2l<R, true, 1>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
+                         G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
     else
-      hipLaunchKernelGGL((k_m2l<R, false>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
-                         G, Lv.nbox, Lv.K, nc, cw, ldp, accum);
+      hipLaunchKernelGGL((k_m2l<R, false, 1>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
+                         G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
   }
 
   // level l -> child level l+1 (accumulates into the child patterns)
@@ -910,6 +1061,9 @@ struct Stages {
     if (nc == 1)
       hipLaunchKernelGGL(k_disagg1<R>, dim3((unsigned)((d.N + 3) / 4)), dim3(256), 0, s, (const CR*)V, G,
                          (const R*)pd.qwc, yi, d.box_of, perm, K, d.N, ldp, y, ld, conj);
+    else if (nc % 4 == 0 && (size_t)(64 * nc + 64 * d.max_box) * sizeof(CR) <= 64 * 1024)
+      hipLaunchKernelGGL(k_disagg_box<R>, dim3(d.nleaf), dim3(256), (size_t)(64 * nc + 64 * d.max_box) * sizeof(CR), s,
+                         (const CR*)V, G, (const R*)pd.qwc, yi, d.box_start, perm, K, nc, ldp, y, ld, conj);
     else if (nc % 4 == 0)
       hipLaunchKernelGGL((k_disagg<R, 4>), dim3(d.nleaf), dim3(256), 0, s, (const CR*)V, G, (const R*)pd.qwc, yi,
                          d.box_start, perm, K, nc, ldp, y, ld, conj);

@@ -80,10 +80,10 @@ static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<in
     D.ntile = (Lv.nbox + kTile - 1) / kTile;
     D.tile_ptr = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 0];
     D.tile_src = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 1];
-    D.tile_off = reinterpret_cast<int16_t*>(lists[8 * (lf + 1) + (lf + 1) + 6 * l + 2]);
+    D.tile_off = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 2];
     D.tileR_ptr = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 3];
     D.tileR_src = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 4];
-    D.tileR_off = reinterpret_cast<int16_t*>(lists[8 * (lf + 1) + (lf + 1) + 6 * l + 5]);
+    D.tileR_off = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 5];
     D.TZ = upload_complex<R>(d, P.TZ[l], s);
     D.TR = upload_complex<R>(d, P.TR[l], s);
     D.TX = upload_complex<R>(d, P.TX[l], s);
@@ -129,6 +129,7 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   d.nleaf = P.lev[P.lf].nbox;
   d.Kleaf = P.lev[P.lf].K;
   d.max_cols = P.opt.max_cols;
+  for (int b = 0; b < P.lev[P.lf].nbox; ++b) d.max_box = std::max(d.max_box, P.box_start[b + 1] - P.box_start[b]);
   const int lf = P.lf;
   // triangles
   std::vector<TriD> tri(P.nt);
@@ -186,10 +187,10 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
     const int tb = 8 * (lf + 1) + (lf + 1) + 6 * l;
     lists[tb + 0] = upload(d, Lv.tile_ptr, s);
     lists[tb + 1] = upload(d, Lv.tile_src, s);
-    lists[tb + 2] = reinterpret_cast<int32_t*>(upload(d, Lv.tile_off, s));
+    lists[tb + 2] = upload(d, Lv.tile_off, s);
     lists[tb + 3] = upload(d, Lv.tileR_ptr, s);
     lists[tb + 4] = upload(d, Lv.tileR_src, s);
-    lists[tb + 5] = reinterpret_cast<int32_t*>(upload(d, Lv.tileR_off, s));
+    lists[tb + 5] = upload(d, Lv.tileR_off, s);
   }
   std::vector<int32_t> dummy;
   build_prec<float>(d, P, d.f32, dummy, lists, s);

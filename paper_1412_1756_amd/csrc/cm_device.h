@@ -36,7 +36,7 @@ struct LevelD {
   void *TZ = nullptr, *TR = nullptr, *TX = nullptr, *dTZ = nullptr;  // n_off x K complex<R>
   int ntile = 0;
   int32_t *tile_ptr = nullptr, *tile_src = nullptr, *tileR_ptr = nullptr, *tileR_src = nullptr;
-  int16_t *tile_off = nullptr, *tileR_off = nullptr;
+  int32_t *tile_off = nullptr, *tileR_off = nullptr;
   // interpolation from level l+1 into this level (l = 2..lf-1)
   int p = 0, ntc = 0, npc = 0;
   int32_t *th_idx = nullptr, *th_ref = nullptr, *ph_idx = nullptr;
@@ -58,7 +58,7 @@ struct PrecD {
 struct Dev {
   int device = 0;
   int64_t N = 0, nnz = 0;
-  int lf = 0, nleaf = 0, Kleaf = 0, max_cols = 0;
+  int lf = 0, nleaf = 0, Kleaf = 0, max_cols = 0, max_box = 0;   // max_box: most unknowns in a leaf box
   TriD* tri = nullptr;
   RwgD* rwg = nullptr;
   int32_t *perm = nullptr, *box_of = nullptr, *box_start = nullptr;

@@ -540,7 +540,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     Level& Lv = lev[l];
     auto make = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& src,
                     const std::vector<int32_t>& off, std::vector<int32_t>& tptr, std::vector<int32_t>& tsrc,
-                    std::vector<int16_t>& toff) {
+                    std::vector<int32_t>& toff) {
       const int ntile = (Lv.nbox + kTile - 1) / kTile;
       tptr.assign(ntile + 1, 0);
       for (int t = 0; t < ntile; ++t) {
@@ -556,9 +556,9 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
           int sbox = ent[i].first;
           tsrc.push_back(sbox);
           size_t base = toff.size();
-          toff.resize(base + kTile, (int16_t)-1);
+          toff.resize(base + kTile, -1);
           while (i < ent.size() && ent[i].first == sbox) {
-            toff[base + ent[i].second.first] = (int16_t)ent[i].second.second;
+            toff[base + ent[i].second.first] = ent[i].second.second;
             ++i;
           }
         }

@@ -44,9 +44,9 @@ struct Level {
   // receiver tiles of kTile consecutive boxes: union of their sources and, per
   // (tile, source), the compact translator index for each receiver (-1: none)
   std::vector<int32_t> tile_ptr, tile_src;
-  std::vector<int16_t> tile_off;
+  std::vector<int32_t> tile_off;            // int32: read with scalar loads in the kernel
   std::vector<int32_t> tileR_ptr, tileR_src;
-  std::vector<int16_t> tileR_off;
+  std::vector<int32_t> tileR_off;
   std::vector<int32_t> off_compact;                   // kNoff -> compact id (-1 unused)
   int n_off_used = 0;
 };
