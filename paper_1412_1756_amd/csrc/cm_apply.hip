@@ -97,6 +97,7 @@ __global__ void __launch_bounds__(256) k_near(const int64_t* __restrict__ row_pt
   const double2* z = Zn + row_ptr[i];
   double ax = 0.0, ay = 0.0;
   if (c < nc) {
+#pragma unroll 4
     for (int t = t0 + s; t < t1; t += S) {
       double2 v = z[t];
       if (mode == 1) v.y = 0.0;
@@ -153,6 +154,7 @@ __global__ void __launch_bounds__(256) k_near_box(const int64_t* __restrict__ ro
     for (int tc0 = t0; tc0 < t1; tc0 += TC) {
       const int tn = min(TC, t1 - tc0);
       __syncthreads();
+#pragma unroll 4
       for (int e = threadIdx.x; e < tn * nc; e += blockDim.x) {
         const int tt = e / nc, c = e % nc;
         xs[tt * nc + c] = xi[(int64_t)cols[tc0 + tt] * nc + c];
@@ -164,6 +166,7 @@ __global__ void __launch_bounds__(256) k_near_box(const int64_t* __restrict__ ro
         if (o >= nout) continue;
         const int ii = o / ncg, cg = o % ncg;
         const double2* z = Zn + row_ptr[r0 + ii] + tc0;
+#pragma unroll 8
         for (int tt = 0; tt < tn; ++tt) {
           double2 v = z[tt];
           if (mode == 1) v.y = 0.0;
@@ -212,6 +215,7 @@ __global__ void __launch_bounds__(256) k_aggregate(const C2<R>* __restrict__ V, 
     C2<R> acc[CG];
 #pragma unroll
     for (int u = 0; u < CG; ++u) acc[u] = mk<R>(0, 0);
+#pragma unroll 8
     for (int j = j0; j < j1; ++j) {
       const C2<R> v = V[(int64_t)j * 2 * K + cq];
       const C2<R>* xr = xi + (int64_t)j * ldx + cg * CG;
@@ -520,6 +524,7 @@ __global__ void __launch_bounds__(256) k_interp_up(const C2<R>* __restrict__ Sc,
     const C2<R>* src = Sc + ((int64_t)ch * 2 + comp) * Kc * ldp + c0;
     const int oc = octant[ch];
     __syncthreads();
+#pragma unroll 4
     for (int e = threadIdx.x; e < Kc * cs; e += blockDim.x) {
       const int c = e % cs, q = e / cs;
       A[e] = (c < cw) ? src[(int64_t)q * ldp + c] : mk<R>(0, 0);
@@ -613,6 +618,7 @@ __global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ G
   const int cw = min(cs, nc - c0);
   const int hc = npc / 2;
   const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * ldp + c0;
+#pragma unroll 4
   for (int e = threadIdx.x; e < Kp * cs; e += blockDim.x) {
     const int c = e % cs, q = e / cs;
     P0[e] = (c < cw) ? g[(int64_t)q * ldp + c] : mk<R>(0, 0);
@@ -676,6 +682,7 @@ __global__ void __launch_bounds__(256) k_disagg1(const C2<R>* __restrict__ V, co
   const C2<R>* v = V + i * 2 * K;
   const C2<R>* g = G + (int64_t)b * 2 * K * ldp;
   R ax = 0, ay = 0;
+#pragma unroll 4
   for (int cq = lane; cq < 2 * K; cq += 64) {
     const R w = qwc[cq < K ? cq : cq - K];
     const C2<R> a = v[cq];
@@ -771,6 +778,7 @@ __global__ void __launch_bounds__(256) k_aggregate_box(const C2<R>* __restrict__
     C2<R> a0 = mk<R>(0, 0), a1 = a0, a2 = a0, a3 = a0;
     const C2<R>* v = V + (int64_t)j0 * 2 * K + cq;
     const C2<R>* xr = xs + cg * 4;
+#pragma unroll 8
     for (int j = 0; j < nb; ++j) {
       const C2<R> w = v[(int64_t)j * 2 * K];
       a0 = cfma(a0, w, xr[0]);
@@ -812,7 +820,9 @@ __global__ void __launch_bounds__(256) k_disagg_box(const C2<R>* __restrict__ V,
     for (int q0 = 0; q0 < 2 * K; q0 += CH) {
       const int qn = min(CH, 2 * K - q0);
       __syncthreads();
+#pragma unroll 4
       for (int e = threadIdx.x; e < qn * nc; e += blockDim.x) gs[e] = g[(int64_t)(q0 + e / nc) * ldp + e % nc];
+#pragma unroll 4
       for (int e = threadIdx.x; e < nb * qn; e += blockDim.x) {
         const int jj = e / qn, qq = e % qn;
         const int cq = q0 + qq;
@@ -864,6 +874,7 @@ __global__ void __launch_bounds__(256) k_sai_apply(const int64_t* __restrict__ p
   const int c = lane % NC, s = lane / NC;
   double ax = 0.0, ay = 0.0;
   if (c < nc) {
+#pragma unroll 4
     for (int64_t t = ptr[i] + s; t < ptr[i + 1]; t += S) {
       double2 v = val[t];
       C2<R> xv = xi[(int64_t)col[t] * nc + c];
