@@ -984,6 +984,12 @@ struct Stages {
 
   // child level l+1 -> level l; shift = per-octant phase table (or its k-derivative)
   void interp(int l, const CR* Sc, CR* Sp, int nc, int ldp, int accum, const void* shift) {
+    if constexpr (sizeof(R) == 4) {
+      const void* sT = (shift == pd.lev[l].dshift) ? pd.lev[l].dshiftT : pd.lev[l].shiftT;
+      if (!(P.opt.flags & CM_FLAG_VALU_INTERP) &&
+          mf_interp(pd.lev[l], pd.lev[l + 1], (const float2*)Sc, (float2*)Sp, nc, ldp, accum, sT, s))
+        return;
+    }
     constexpr int kJ = sizeof(R) == 4 ? 16 : 8;
     LevelD<R> Lp = pd.lev[l];
     Lp.shift = const_cast<void*>(shift);
@@ -1041,6 +1047,16 @@ struct Stages {
   }
 
   // level l -> child level l+1 (accumulates into the child patterns)
+  // matrix-core anterpolation: stores into the child patterns (add: adds onto them)
+  void anterp_mf(int l, const CR* Gp, CR* Gc, int nc, int ldp, const void* shift, int add) {
+    if constexpr (sizeof(R) == 4) {
+      const void* zg = (shift == pd.lev[l].dshift) ? pd.lev[l].dzg : pd.lev[l].zg;
+      if (mf_anterp(pd.lev[l], pd.lev[l + 1], (const float2*)Gp, (float2*)Gc, nc, ldp, add, zg, s)) return;
+    }
+    throw Error(-7, "matrix-core anterpolation does not cover this level");
+  }
+
+  // vector-ALU anterpolation: adds onto the child patterns
   void anterp(int l, const CR* Gp, CR* Gc, int nc, int ldp, const void* shift) {
     LevelD<R> Lp = pd.lev[l];
     Lp.shift = const_cast<void*>(shift);
@@ -1124,21 +1140,40 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     if (dual) st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l] + nc, nc, ldp, 1, pd.lev[l].dshift);
     stage_end(d, s);
   }
-  // translations
-  for (int l = 2; l <= lf; ++l) {
+  // translations and downward pass.  With the matrix-core anterpolation the
+  // parent's contribution is stored first and the translations of the level
+  // are added onto it; otherwise the translations are stored first and the
+  // anterpolation adds onto them.
+  bool mf_down = false;
+  if constexpr (sizeof(R) == 4) {
+    mf_down = !(P.opt.flags & CM_FLAG_VALU_INTERP) && nc % 8 == 0;
+    for (int l = 2; l < lf && mf_down; ++l) mf_down = mf_covers(pd.lev[l], nc);
+  }
+  auto m2l_level = [&](int l, int accum) {
     LevelD<R>& Lv = pd.lev[l];
     const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
     stage_begin(d, s, 4 + 10 * l);
-    st.m2l(l, kind, T, (const CR*)d.S[l], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, 0);
+    st.m2l(l, kind, T, (const CR*)d.S[l], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, accum);
     if (dual) st.m2l(l, 0, Lv.dTZ, (const CR*)d.S[l], (CR*)d.G[l] + nc, nc, ldp, 1);
     stage_end(d, s);
-  }
-  // downward pass
-  for (int l = 2; l < lf; ++l) {
-    stage_begin(d, s, 5 + 10 * (l + 1));
-    st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift);
-    if (dual) st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift);
-    stage_end(d, s);
+  };
+  if (mf_down) {
+    m2l_level(2, 0);
+    for (int l = 3; l <= lf; ++l) {
+      stage_begin(d, s, 5 + 10 * l);
+      st.anterp_mf(l - 1, (const CR*)d.G[l - 1], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, pd.lev[l - 1].shift, 0);
+      if (dual) st.anterp_mf(l - 1, (const CR*)d.G[l - 1], (CR*)d.G[l] + nc, nc, ldp, pd.lev[l - 1].dshift, 1);
+      stage_end(d, s);
+      m2l_level(l, 1);
+    }
+  } else {
+    for (int l = 2; l <= lf; ++l) m2l_level(l, 0);
+    for (int l = 2; l < lf; ++l) {
+      stage_begin(d, s, 5 + 10 * (l + 1));
+      st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift);
+      if (dual) st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift);
+      stage_end(d, s);
+    }
   }
   stage_begin(d, s, 6);
   if (dual) {

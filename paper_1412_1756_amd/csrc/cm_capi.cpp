@@ -54,6 +54,49 @@ static std::vector<R> cast(const std::vector<double>& v) {
   return std::vector<R>(v.begin(), v.end());
 }
 
+static MfD upload_mf(Dev& d, const MfTab& T, hipStream_t s) {
+  MfD m;
+  if (!T.ok) return m;
+  m.ok = 1;
+  m.NT = T.NT;
+  m.S2 = T.S2;
+  m.half = T.half;
+  m.nchunk = T.nchunk;
+  m.kmax = T.kmax;
+  m.ktmax = T.ktmax;
+  m.chunk = upload(d, T.chunk, s);
+  m.nk = upload(d, T.nk, s);
+  m.kidx = upload(d, T.kidx, s);
+  m.kA = upload(d, cast<float>(T.kA), s);
+  m.nkt = upload(d, T.nkt, s);
+  m.tidx = upload(d, T.tidx, s);
+  m.tA = upload(d, cast<float>(T.tA), s);
+  return m;
+}
+
+// phase table [8][K] (q = t*np + u) re-laid as [8][np][16 NT] with theta fastest
+static void* upload_shiftT(Dev& d, const std::vector<cplx>& sh, int nt, int np, int NT, hipStream_t s) {
+  const int tp = 16 * NT;
+  std::vector<cplx> v((size_t)8 * np * tp, cplx(0, 0));
+  for (int oc = 0; oc < 8; ++oc)
+    for (int t = 0; t < nt; ++t)
+      for (int u = 0; u < np; ++u) v[((size_t)oc * np + u) * tp + t] = sh[(size_t)oc * nt * np + (size_t)t * np + u];
+  return upload_complex<float>(d, v, s);
+}
+
+// phase values of the anterpolation K steps: [chunk][octant][t][4 kmax]
+static void* upload_zg(Dev& d, const std::vector<cplx>& sh, const MfTab& T, int nt, int np, hipStream_t s) {
+  const int kz = 4 * T.kmax;
+  std::vector<cplx> v((size_t)T.nchunk * 8 * nt * kz, cplx(0, 0));
+  for (int c = 0; c < T.nchunk; ++c)
+    for (int oc = 0; oc < 8; ++oc)
+      for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 4 * T.nk[c]; ++k)
+          v[(((size_t)c * 8 + oc) * nt + t) * kz + k] =
+              sh[(size_t)oc * nt * np + (size_t)t * np + T.kidx[((size_t)c * T.kmax) * 4 + k]];
+  return upload_complex<float>(d, v, s);
+}
+
 template <typename R>
 static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<int32_t>& octant_dummy,
                        std::vector<int32_t*>& lists, hipStream_t s) {
@@ -107,6 +150,18 @@ static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<in
       D.pht_w = upload(d, cast<R>(I.pht_w), s);
       D.shift = upload_complex<R>(d, P.shift[l], s);
       if (P.opt.flags & CM_FLAG_DERIV) D.dshift = upload_complex<R>(d, P.dshift[l], s);
+      if constexpr (sizeof(R) == 4) {
+        D.mip = upload_mf(d, P.mf_ip[l], s);
+        D.mat = upload_mf(d, P.mf_at[l], s);
+        if (D.mip.ok) {
+          D.shiftT = upload_shiftT(d, P.shift[l], Lv.nt, Lv.np, D.mip.NT, s);
+          if (P.opt.flags & CM_FLAG_DERIV) D.dshiftT = upload_shiftT(d, P.dshift[l], Lv.nt, Lv.np, D.mip.NT, s);
+        }
+        if (D.mat.ok) {
+          D.zg = upload_zg(d, P.shift[l], P.mf_at[l], Lv.nt, Lv.np, s);
+          if (P.opt.flags & CM_FLAG_DERIV) D.dzg = upload_zg(d, P.dshift[l], P.mf_at[l], Lv.nt, Lv.np, s);
+        }
+      }
     }
   }
   for (int l = 2; l <= lf; ++l) pd.lev[l].octant = reinterpret_cast<int8_t*>(lists[8 * (lf + 1) + l]);

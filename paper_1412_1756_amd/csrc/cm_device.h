@@ -25,6 +25,13 @@ struct RwgD {
   double len;
 };
 
+// Matrix-core interpolation tables of one level pair (FP32 path), see MfTab.
+struct MfD {
+  int ok = 0, NT = 0, S2 = 0, half = 0, nchunk = 0, kmax = 0, ktmax = 0;
+  int32_t *chunk = nullptr, *nk = nullptr, *kidx = nullptr, *nkt = nullptr, *tidx = nullptr;
+  float *kA = nullptr, *tA = nullptr;
+};
+
 template <typename R>
 struct LevelD {
   int nbox = 0, K = 0, nt = 0, np = 0;
@@ -45,6 +52,12 @@ struct LevelD {
   R *tht_w = nullptr, *pht_w = nullptr;
   void* shift = nullptr;                    // 8 x K complex<R>: exp(ik khat.(r_child - r_parent))
   void* dshift = nullptr;                   // its k-derivative (CM_FLAG_DERIV)
+  // FP32 matrix-core path: tables and the phase tables as [8][np][16 NT] (theta fastest, zero padded)
+  MfD mip, mat;
+  void *shiftT = nullptr, *dshiftT = nullptr;
+  // anterpolation: phase values per slot chunk and octant in K-step key order,
+  // [nchunk][8][nt][4 kmax] complex (and the k-derivative)
+  void *zg = nullptr, *dzg = nullptr;
 };
 
 template <typename R>
@@ -96,6 +109,17 @@ struct Dev {
 void stage_begin(Dev& d, hipStream_t s, int stage);
 void stage_end(Dev& d, hipStream_t s);
 void collect_stage_times(Dev& d);
+
+// Matrix-core interpolation (level l+1 -> l) and anterpolation (l -> l+1) for
+// complex-float patterns with nc % 8 == 0; false when the level is not covered.
+// Lp: the parent level, Lc: the child level.  shiftT: Lp.shiftT or
+// Lp.dshiftT; zg: Lp.zg or Lp.dzg.
+bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc, int ldp,
+               int accum, const void* shiftT, hipStream_t s);
+bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc, int ldp,
+               int add, const void* zg, hipStream_t s);
+// whether mf_anterp takes the anterpolation from level Lp for nc columns
+bool mf_covers(const LevelD<float>& Lp, int nc);
 
 void dev_build(Dev& d, const Plan& P, hipStream_t s);
 void dev_free(Dev& d);

@@ -1,0 +1,474 @@
+// Matrix-core interpolation and anterpolation between adjacent MLFMA levels
+// (section III: local Lagrange interpolation of the radiation patterns in
+// theta and phi, with the shift to the parent centre; the anterpolation is the
+// weighted transpose).  FP32 patterns, columns in multiples of 8.
+//
+// Layout of the work: one wave owns 16 real columns (8 complex columns of one
+// polarisation component) of one parent box and one slot chunk.  The separable
+// stencils become small dense products on v_mfma_f32_16x16x4_f32:
+//   phi step   M = 16 slots (a set U of phi indices and its pole partners
+//              U + np/2), K = the inputs those slots need, N = 16 columns;
+//   theta step M = 16 theta rows, K = the (row, reflected) inputs of the tile,
+//              N = 16 columns, once per slot; a reflected input reads the
+//              partner slot of the same LDS row (sign folded into the weight).
+// The phi-step result of every theta row of the box goes through LDS (one
+// region per wave, rows padded by 16 floats so the four lane groups of a
+// K step fall into different banks).  The K-step tables hold the weights as
+// the per-lane A operand (lane 16 g + r: output row r, input key 4 k + g).
+#include <hip/hip_runtime.h>
+
+#include "cm_device.h"
+
+namespace cm {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// value held by lane ^ 1 (the other half of the complex column)
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+// LDS written by some lanes of a wave and then read by others
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// kRG rows of phi-step inputs for K steps [0, nk): rows r0 .. r0+kRG-1 of
+// base (clamped to nrows-1), each row at off[k] from its start.
+template <int kRG, int kMK>
+__device__ __forceinline__ void load_rows(float (&v)[kRG][kMK], const float* base, int r0, int nrows,
+                                          int64_t rstride, const unsigned (&off)[kMK], int nk) {
+#pragma unroll
+  for (int r = 0; r < kRG; ++r) {
+    const float* row = base + (int64_t)min(r0 + r, nrows - 1) * rstride;
+#pragma unroll
+    for (int k4 = 0; k4 < kMK; k4 += 4)
+      if (k4 < nk) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[r][k4 + i] = row[off[k4 + i]];
+      }
+  }
+}
+
+// theta-step tables of all row tiles into LDS (ktmax steps each: 4 keys, 64 A values)
+__device__ __forceinline__ void stage_theta_tables(const MfD& T, int NT, int* tcode, float* tA) {
+  for (int e = threadIdx.x; e < NT * T.ktmax * 4; e += blockDim.x) tcode[e] = T.tidx[e];
+  for (int e = threadIdx.x; e < NT * T.ktmax * 64; e += blockDim.x) tA[e] = T.tA[e];
+}
+
+// Interpolation child level -> parent level, summed over the children of a
+// parent with the shift phase of each child's octant; parent rows are written
+// (or accumulated onto, accum != 0).  Grid: x = parent boxes x slot chunks
+// (padded to a multiple of 8, XCD-major order), y = groups of four column
+// tiles; 256 threads, one column tile per wave.  The phi-step loads of a
+// child are double-buffered in groups of kRG rows and the first group of the
+// next child is loaded during the theta step, which touches only LDS.
+template <int NT, int S2, int kMK, int kRG>
+__global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc, float* __restrict__ Sp,
+                                                   const int32_t* __restrict__ child_ptr,
+                                                   const int8_t* __restrict__ octant, MfD T,
+                                                   const float2* __restrict__ shiftT, int ntc, int npc, int ntp,
+                                                   int npp, int nbox, int nc, int ldp, int accum) {
+  constexpr int S = 2 * S2, RS = 16 * S + 16, SB = S < 8 ? S : 8, SH = S * 16 * NT;   // SH: shift entries
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (b >= nbox * T.nchunk) return;   // whole block
+  int* tcode = reinterpret_cast<int*>(lds);
+  float* tAl = lds + NT * T.ktmax * 4;
+  stage_theta_tables(T, NT, tcode, tAl);
+  __syncthreads();
+  const int cpt = nc >> 3;
+  const int tile = blockIdx.y * 4 + w;
+  if (tile >= 2 * cpt) return;
+  float* O = tAl + NT * T.ktmax * 64 + w * (ntc * RS + 2 * SH);
+  float2* ShL = reinterpret_cast<float2*>(O + ntc * RS);   // [slot][16 NT] shift of the current child
+  const int m = b / T.nchunk, c = b - m * T.nchunk;
+  const int comp = tile / cpt, col = 16 * (tile - comp * cpt);
+  const int g = lane >> 4, n = lane & 15;
+  const int ld2 = 2 * ldp;
+  const int64_t Kc = (int64_t)ntc * npc, Kp = (int64_t)ntp * npp;
+  const int u0 = T.chunk[2 * c], h = T.chunk[2 * c + 1];
+  const int nk = T.nk[c];
+  unsigned uoff[kMK];
+  float pa[kMK];
+#pragma unroll
+  for (int kk = 0; kk < kMK; ++kk) {
+    uoff[kk] = 0;
+    pa[kk] = 0.f;
+    if (kk < nk) {
+      uoff[kk] = (unsigned)T.kidx[(c * T.kmax + kk) * 4 + g] * (unsigned)ld2 + (unsigned)(col + n);
+      pa[kk] = T.kA[(c * T.kmax + kk) * 64 + lane];
+    }
+  }
+  f4 acc[NT][S];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[t][s] = f4{0.f, 0.f, 0.f, 0.f};
+  const float sg = (n & 1) ? 1.f : -1.f;   // (sx + i sy)(re + i im): re lane -sy*im, im lane +sy*re
+  const int64_t rstride = (int64_t)npc * ld2;
+  auto child_src = [&](int ch) { return Sc + ((int64_t)ch * 2 + comp) * Kc * ld2; };
+  // phi step of kRG rows from v into LDS rows r0 ..
+  auto phi_rows = [&](const float (&v)[kRG][kMK], int r0) {
+    f4 d[kRG];
+#pragma unroll
+    for (int r = 0; r < kRG; ++r) d[r] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k4 = 0; k4 < kMK; k4 += 4)
+      if (k4 < nk) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int r = 0; r < kRG; ++r) d[r] = mma(pa[k4 + i], v[r][k4 + i], d[r]);
+      }
+#pragma unroll
+    for (int r = 0; r < kRG; ++r)
+      if (r0 + r < ntc) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * g + j < S) O[(r0 + r) * RS + (4 * g + j) * 16 + n] = d[r][j];
+      }
+  };
+  const int ch0 = child_ptr[m], ch1 = child_ptr[m + 1];
+  float va[kRG][kMK], vb[kRG][kMK];
+  if (ch0 < ch1) load_rows(va, child_src(ch0), 0, ntc, rstride, uoff, nk);
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const float* src = child_src(ch);
+    // this child's shift rows of the chunk's slots (written to LDS after the phi step)
+    const float4* shg = reinterpret_cast<const float4*>(shiftT + (size_t)octant[ch] * npp * (16 * NT));
+    float4 shv[(SH / 2 + 63) / 64];
+#pragma unroll
+    for (int i = 0; i < (SH / 2 + 63) / 64; ++i) {
+      const int e = lane + 64 * i;                  // float4 index: slot e / (8 NT), pair e % (8 NT)
+      const int sl = e / (8 * NT), q = e - sl * (8 * NT);
+      const int up = (sl % S2) < h ? u0 + (sl % S2) + (sl / S2) * T.half : u0;
+      if (e < SH / 2) shv[i] = shg[up * (8 * NT) + q];
+    }
+    // phi step, double-buffered row groups
+    for (int tc0 = 0; tc0 < ntc; tc0 += 2 * kRG) {
+      const bool more = tc0 + kRG < ntc;
+      if (more) load_rows(vb, src, tc0 + kRG, ntc, rstride, uoff, nk);
+      phi_rows(va, tc0);
+      if (more) {
+        if (tc0 + 2 * kRG < ntc) load_rows(va, src, tc0 + 2 * kRG, ntc, rstride, uoff, nk);
+        phi_rows(vb, tc0 + kRG);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < (SH / 2 + 63) / 64; ++i) {
+      const int e = lane + 64 * i;
+      if (e < SH / 2) reinterpret_cast<float4*>(ShL)[e] = shv[i];
+    }
+    wave_lds_sync();
+    if (ch + 1 < ch1) load_rows(va, child_src(ch + 1), 0, ntc, rstride, uoff, nk);
+    // theta step per row tile and slot batch, then shift and accumulate
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int nkt = T.nkt[t];
+#pragma unroll
+      for (int s0 = 0; s0 < S; s0 += SB) {
+        f4 d2[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) d2[i] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < nkt; ++kk) {
+          const int code = tcode[(t * T.ktmax + kk) * 4 + g];
+          const float a = tAl[(t * T.ktmax + kk) * 64 + lane];
+          // reflected inputs read the partner slot s ^ S2 of the same row
+          const int rfo = (code >> 16) ? 16 * S2 : 0;
+          const float* lo = O + (code & 0xffff) * RS + n + rfo;
+          const float* hi = O + (code & 0xffff) * RS + n - rfo;
+#pragma unroll
+          for (int i = 0; i < SB; ++i) {
+            const int s = s0 + i;
+            d2[i] = mma(a, (s < S2 ? lo : hi)[s * 16], d2[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+          const int s = s0 + i;
+          if ((s % S2) < h) {
+            const float4* sp = reinterpret_cast<const float4*>(ShL + s * (16 * NT) + 16 * t + 4 * g);
+            const float4 s01 = sp[0], s23 = sp[1];
+            const float sx[4] = {s01.x, s01.z, s23.x, s23.z};
+            const float sy[4] = {s01.y, s01.w, s23.y, s23.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const float v = d2[i][j], vp = pair_swap(v);
+              acc[t][s][j] = fmaf(sx[j], v, fmaf(sg * sy[j], vp, acc[t][s][j]));
+            }
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+  float* dst = Sp + ((int64_t)m * 2 + comp) * Kp * ld2 + col + n;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if ((s % S2) >= h) continue;
+      const int up = u0 + (s % S2) + (s / S2) * T.half;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int tp = 16 * t + 4 * g + j;
+        if (tp < ntp) {
+          float* o = dst + ((int64_t)tp * npp + up) * ld2;
+          if (accum)
+            unsafeAtomicAdd(o, acc[t][s][j]);   // single writer per element: a plain read-add-write
+          else
+            *o = acc[t][s][j];
+        }
+      }
+    }
+}
+
+// Anterpolation parent level -> child level, one child box (and slot chunk
+// over the child phi grid) per block: conj(shift) times the parent pattern,
+// the transposed phi step (parent phi -> child slots) into LDS, the
+// transposed theta step with the child-grid reflection, stored into the child
+// rows (add != 0: added onto them).  The block stages the chunk's shift
+// values for the child's octant (zg: [chunk][octant][parent theta row][4
+// kmax], in K-step key order) and the theta tables in LDS; the parent-row
+// loads are double-buffered in groups of kRG rows.
+template <int NT, int S2, int kMK, int kRG>
+__global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp, float* __restrict__ Gc,
+                                                   const int32_t* __restrict__ parent,
+                                                   const int8_t* __restrict__ octant, MfD T,
+                                                   const float2* __restrict__ zg, int ntc, int npc, int ntp,
+                                                   int npp, int nchild, int nc, int ldp, int add) {
+  constexpr int S = 2 * S2, RS = 16 * S + 16;
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (b >= nchild * T.nchunk) return;   // whole block
+  const int ch = b / T.nchunk, c = b - ch * T.nchunk;
+  const int kz = 4 * T.kmax;
+  int* tcode = reinterpret_cast<int*>(lds);
+  float* tAl = lds + NT * T.ktmax * 4;
+  float2* Z = reinterpret_cast<float2*>(tAl + NT * T.ktmax * 64);
+  stage_theta_tables(T, NT, tcode, tAl);
+  {
+    const float4* zs = reinterpret_cast<const float4*>(zg + ((size_t)c * 8 + octant[ch]) * ntp * kz);
+    float4* zd = reinterpret_cast<float4*>(Z);
+    for (int e = threadIdx.x; e < ntp * kz / 2; e += blockDim.x) zd[e] = zs[e];
+  }
+  __syncthreads();
+  const int cpt = nc >> 3;
+  const int tile = blockIdx.y * 4 + w;
+  if (tile >= 2 * cpt) return;
+  float* O = reinterpret_cast<float*>(Z + ntp * kz) + w * ntp * RS;
+  const int m = parent[ch];
+  const int comp = tile / cpt, col = 16 * (tile - comp * cpt);
+  const int g = lane >> 4, n = lane & 15;
+  const int ld2 = 2 * ldp;
+  const int64_t Kc = (int64_t)ntc * npc, Kp = (int64_t)ntp * npp;
+  const int u0 = T.chunk[2 * c], h = T.chunk[2 * c + 1];
+  const int nk = T.nk[c];
+  unsigned poff[kMK];
+  float pa[kMK];
+#pragma unroll
+  for (int kk = 0; kk < kMK; ++kk) {
+    poff[kk] = 0;
+    pa[kk] = 0.f;
+    if (kk < nk) {
+      poff[kk] = (unsigned)T.kidx[(c * T.kmax + kk) * 4 + g] * (unsigned)ld2 + (unsigned)(col + n);
+      pa[kk] = T.kA[(c * T.kmax + kk) * 64 + lane];
+    }
+  }
+  const float* par = Gp + ((int64_t)m * 2 + comp) * Kp * ld2;
+  const int64_t rstride = (int64_t)npp * ld2;
+  const float sg = (n & 1) ? -1.f : 1.f;   // (sx - i sy)(re + i im): re lane +sy*im, im lane -sy*re
+  auto phiT_rows = [&](const float (&v)[kRG][kMK], int r0) {
+    f4 d[kRG];
+#pragma unroll
+    for (int r = 0; r < kRG; ++r) d[r] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k4 = 0; k4 < kMK; k4 += 4)
+      if (k4 < nk) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int r = 0; r < kRG; ++r) {
+            const float2 z = Z[min(r0 + r, ntp - 1) * kz + (k4 + i) * 4 + g];
+            const float x = v[r][k4 + i];
+            d[r] = mma(pa[k4 + i], fmaf(z.x, x, sg * z.y * pair_swap(x)), d[r]);
+          }
+      }
+#pragma unroll
+    for (int r = 0; r < kRG; ++r)
+      if (r0 + r < ntp) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * g + j < S) O[(r0 + r) * RS + (4 * g + j) * 16 + n] = d[r][j];
+      }
+  };
+  // transposed phi step over the parent rows, double-buffered row groups
+  float va[kRG][kMK], vb[kRG][kMK];
+  load_rows(va, par, 0, ntp, rstride, poff, nk);
+  for (int tp0 = 0; tp0 < ntp; tp0 += 2 * kRG) {
+    const bool more = tp0 + kRG < ntp;
+    if (more) load_rows(vb, par, tp0 + kRG, ntp, rstride, poff, nk);
+    phiT_rows(va, tp0);
+    if (more) {
+      if (tp0 + 2 * kRG < ntp) load_rows(va, par, tp0 + 2 * kRG, ntp, rstride, poff, nk);
+      phiT_rows(vb, tp0 + kRG);
+    }
+  }
+  wave_lds_sync();
+  // transposed theta step
+  f4 acc[NT][S];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[t][s] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int nkt = T.nkt[t];
+    for (int kk = 0; kk < nkt; ++kk) {
+      const int code = tcode[(t * T.ktmax + kk) * 4 + g];
+      const float a = tAl[(t * T.ktmax + kk) * 64 + lane];
+      const int rfo = (code >> 16) ? 16 * S2 : 0;
+      const float* lo = O + (code & 0xffff) * RS + n + rfo;
+      const float* hi = O + (code & 0xffff) * RS + n - rfo;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[t][s] = mma(a, (s < S2 ? lo : hi)[s * 16], acc[t][s]);
+    }
+  }
+  float* dst = Gc + ((int64_t)ch * 2 + comp) * Kc * ld2;
+  const unsigned rstep = (unsigned)npc * (unsigned)ld2;
+  const unsigned loff = 4u * g * rstep + (unsigned)(col + n);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (16 * t + 4 * g + j >= ntc) continue;
+      const unsigned ro = loff + (unsigned)(16 * t + j) * rstep;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if ((s % S2) >= h) continue;
+        const unsigned o = ro + (unsigned)(u0 + (s % S2) + (s / S2) * T.half) * (unsigned)ld2;
+        if (add)
+          unsafeAtomicAdd(dst + o, acc[t][s][j]);   // single writer per element: a plain read-add-write
+        else
+          dst[o] = acc[t][s][j];
+      }
+    }
+}
+
+static void lds_limit(const void* f, size_t bytes) {
+  if (bytes > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) throw Error(-4, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  }
+}
+
+static bool lds_fits(size_t bytes) { return bytes <= 160 * 1024; }
+
+static size_t interp_lds(const MfD& T, int ntc) {
+  const int S = 2 * T.S2, RS = 16 * S + 16, SH = S * 16 * T.NT;
+  return (size_t)T.NT * T.ktmax * 68 * 4 + (size_t)4 * (ntc * RS + 2 * SH) * 4;
+}
+static size_t anterp_lds(const MfD& T, int ntp) {
+  const int S = 2 * T.S2, RS = 16 * S + 16;
+  return (size_t)T.NT * T.ktmax * 68 * 4 + (size_t)ntp * 4 * T.kmax * 8 + (size_t)4 * ntp * RS * 4;
+}
+
+// rows per double-buffered load group (by the K-step register budget)
+#ifndef CM_RG_I8
+#define CM_RG_I8 2
+#endif
+#ifndef CM_RG_I16
+#define CM_RG_I16 1
+#endif
+#ifndef CM_RG_A8
+#define CM_RG_A8 2
+#endif
+#ifndef CM_RG_A16
+#define CM_RG_A16 1
+#endif
+template <int NT, int S2, int MK>
+static void launch_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
+                          int ldp, int accum, const void* shiftT, hipStream_t s) {
+  constexpr int RG = MK <= 8 ? CM_RG_I8 : CM_RG_I16;
+  const MfD& T = Lp.mip;
+  const int nb = (Lp.nbox * T.nchunk + 7) / 8 * 8;
+  const int ntiles = nc / 4;   // 2 components x nc/8
+  const size_t sh = interp_lds(T, Lc.nt);
+  lds_limit((const void*)k_interp_mf<NT, S2, MK, RG>, sh);
+  hipLaunchKernelGGL((k_interp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + 3) / 4), dim3(256), sh, s, (const float*)Sc,
+                     (float*)Sp, Lp.child_ptr, Lc.octant, T, (const float2*)shiftT, Lc.nt, Lc.np, Lp.nt, Lp.np,
+                     Lp.nbox, nc, ldp, accum);
+}
+
+template <int NT, int S2, int MK>
+static void launch_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
+                          int ldp, int add, const void* zg, hipStream_t s) {
+  constexpr int RG = MK <= 8 ? CM_RG_A8 : CM_RG_A16;
+  const MfD& T = Lp.mat;
+  const int nb = (Lc.nbox * T.nchunk + 7) / 8 * 8;
+  const int ntiles = nc / 4;
+  const size_t sh = anterp_lds(T, Lp.nt);
+  lds_limit((const void*)k_anterp_mf<NT, S2, MK, RG>, sh);
+  hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + 3) / 4), dim3(256), sh, s, (const float*)Gp,
+                     (float*)Gc, Lc.parent, Lc.octant, T, (const float2*)zg, Lc.nt, Lc.np, Lp.nt, Lp.np, Lc.nbox, nc,
+                     ldp, add);
+}
+
+#define CM_MF_CASES(X)                                                    \
+  X(1, 8, 4) X(1, 8, 8) X(1, 8, 16) X(1, 4, 4) X(1, 4, 8) X(1, 4, 16) \
+  X(2, 8, 4) X(2, 8, 8) X(2, 8, 16) X(2, 4, 4) X(2, 4, 8) X(2, 4, 16) \
+  X(3, 4, 4) X(3, 4, 8) X(3, 4, 16) X(4, 4, 4) X(4, 4, 8) X(4, 4, 16)
+
+static int mk_of(const MfD& T) { return T.kmax <= 4 ? 4 : T.kmax <= 8 ? 8 : 16; }
+
+static bool has_case(const MfD& T) {
+  const int mk = mk_of(T);
+#define X(a, b, c) \
+  if (T.NT == a && T.S2 == b && mk == c) return true;
+  CM_MF_CASES(X)
+#undef X
+  return false;
+}
+
+bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc, int ldp,
+               int accum, const void* shiftT, hipStream_t s) {
+  const MfD& T = Lp.mip;
+  if (!T.ok || nc % 8 != 0 || !shiftT || !lds_fits(interp_lds(T, Lc.nt)) || !has_case(T)) return false;
+  const int mk = mk_of(T);
+#define X(a, b, c)                                                           \
+  if (T.NT == a && T.S2 == b && mk == c) {                                   \
+    launch_interp<a, b, c>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);       \
+    return true;                                                             \
+  }
+  CM_MF_CASES(X)
+#undef X
+  return false;
+}
+
+bool mf_covers(const LevelD<float>& Lp, int nc) {
+  const MfD& T = Lp.mat;
+  return T.ok && nc % 8 == 0 && Lp.zg && lds_fits(anterp_lds(T, Lp.nt)) && has_case(T);
+}
+
+bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc, int ldp,
+               int add, const void* zg, hipStream_t s) {
+  const MfD& T = Lp.mat;
+  if (!mf_covers(Lp, nc) || !zg) return false;
+  const int mk = mk_of(T);
+#define X(a, b, c)                                                       \
+  if (T.NT == a && T.S2 == b && mk == c) {                               \
+    launch_anterp<a, b, c>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);         \
+    return true;                                                         \
+  }
+  CM_MF_CASES(X)
+#undef X
+  return false;
+}
+
+}  // namespace cm

@@ -127,6 +127,133 @@ static void parallel_for(int64_t n, F fn) {
 }
 
 // ---------------------------------------------------------------- build
+
+// ---- operand tables of the matrix-core interpolation kernels
+namespace {
+using RowList = std::vector<std::vector<std::pair<int32_t, double>>>;   // 16 output rows: (input key, weight)
+
+// Union of the inputs of 16 output rows, four per K step (by4: the step count
+// rounded up to a multiple of four); A[k][16 g + r] is the weight of input
+// key[4k + g] in row r (unused lanes point at a valid input with weight 0).
+int gather_steps(const RowList& rows, std::vector<int32_t>& key, std::vector<double>& A, bool by4) {
+  std::vector<int32_t> u;
+  for (auto& r : rows)
+    for (auto& e : r) u.push_back(e.first);
+  std::sort(u.begin(), u.end());
+  u.erase(std::unique(u.begin(), u.end()), u.end());
+  const int nk = by4 ? (int)(u.size() + 15) / 16 * 4 : (int)(u.size() + 3) / 4;
+  key.assign((size_t)nk * 4, u.empty() ? 0 : u[0]);
+  for (size_t i = 0; i < u.size(); ++i) key[i] = u[i];
+  A.assign((size_t)nk * 64, 0.0);
+  for (int r = 0; r < (int)rows.size(); ++r)
+    for (auto& e : rows[r]) {
+      const int i = (int)(std::lower_bound(u.begin(), u.end(), e.first) - u.begin());
+      A[(size_t)(i / 4) * 64 + (i % 4) * 16 + r] += e.second;
+    }
+  return nk;
+}
+
+// phi_rows(idx) lists the phi-step inputs of slotted index idx; theta_rows(t)
+// the theta-step inputs of theta row t.
+// lds_rows: theta rows each wave keeps in LDS (32 S2 + 16 floats per row);
+// the half slot count drops to 4 where S2 = 8 would take more than 80 KiB
+// for a block of four waves (two blocks per CU), or more than 128
+// accumulator registers.
+template <typename PhiRows, typename ThetaRows>
+void build_tab(MfTab& T, int nth, int nph, int lds_rows, PhiRows phi_rows, ThetaRows theta_rows) {
+  T.NT = (nth + 15) / 16;
+  T.S2 = (T.NT <= 2 && (size_t)lds_rows * (16 * 16 + 16) * 4 * 4 <= 80 * 1024) ? 8 : 4;
+  T.half = nph / 2;
+  T.nchunk = (T.half + T.S2 - 1) / T.S2;
+  std::vector<std::vector<int32_t>> keys(T.nchunk);
+  std::vector<std::vector<double>> As(T.nchunk);
+  T.chunk.assign(2 * (size_t)T.nchunk, 0);
+  T.nk.assign(T.nchunk, 0);
+  int u0 = 0;
+  for (int c = 0; c < T.nchunk; ++c) {
+    const int h = T.half / T.nchunk + (c < T.half % T.nchunk ? 1 : 0);
+    T.chunk[2 * c] = u0;
+    T.chunk[2 * c + 1] = h;
+    RowList rows(16);
+    for (int s = 0; s < 2 * T.S2; ++s) {
+      const int i = s % T.S2, hf = s / T.S2;
+      if (i < h) rows[s] = phi_rows(u0 + i + hf * T.half);
+    }
+    T.nk[c] = gather_steps(rows, keys[c], As[c], true);
+    T.kmax = std::max(T.kmax, T.nk[c]);
+    u0 += h;
+  }
+  std::vector<std::vector<int32_t>> tkeys(T.NT);
+  std::vector<std::vector<double>> tAs(T.NT);
+  T.nkt.assign(T.NT, 0);
+  for (int t = 0; t < T.NT; ++t) {
+    RowList rows(16);
+    for (int r = 0; r < 16 && 16 * t + r < nth; ++r) rows[r] = theta_rows(16 * t + r);
+    T.nkt[t] = gather_steps(rows, tkeys[t], tAs[t], false);
+    T.ktmax = std::max(T.ktmax, T.nkt[t]);
+  }
+  const int km = std::max(1, T.kmax), ktm = std::max(1, T.ktmax);
+  T.kidx.assign((size_t)T.nchunk * km * 4, 0);
+  T.kA.assign((size_t)T.nchunk * km * 64, 0.0);
+  for (int c = 0; c < T.nchunk; ++c) {
+    std::copy(keys[c].begin(), keys[c].end(), T.kidx.begin() + (size_t)c * km * 4);
+    std::copy(As[c].begin(), As[c].end(), T.kA.begin() + (size_t)c * km * 64);
+  }
+  T.tidx.assign((size_t)T.NT * ktm * 4, 0);
+  T.tA.assign((size_t)T.NT * ktm * 64, 0.0);
+  for (int t = 0; t < T.NT; ++t) {
+    std::copy(tkeys[t].begin(), tkeys[t].end(), T.tidx.begin() + (size_t)t * ktm * 4);
+    std::copy(tAs[t].begin(), tAs[t].end(), T.tA.begin() + (size_t)t * ktm * 64);
+  }
+  T.kmax = km;
+  T.ktmax = ktm;
+  T.ok = T.NT <= 4 && T.kmax <= 16;
+}
+}  // namespace
+
+static void build_mf_tables(Plan& P) {
+  P.mf_ip.assign(P.lf + 1, MfTab());
+  P.mf_at.assign(P.lf + 1, MfTab());
+  for (int l = 2; l < P.lf; ++l) {
+    const Interp& I = P.ip[l];
+    const int p = I.p;
+    // interpolation child l+1 -> l: phi first (child phi -> parent phi), then
+    // theta over child rows, reflected entries read the partner phi column
+    build_tab(
+        P.mf_ip[l], I.ntp, I.npp, I.ntc,
+        [&](int up) {
+          std::vector<std::pair<int32_t, double>> e;
+          for (int j = 0; j < p; ++j) e.push_back({I.ph_idx[up * p + j], I.ph_w[up * p + j]});
+          return e;
+        },
+        [&](int tp) {
+          std::vector<std::pair<int32_t, double>> e;
+          for (int j = 0; j < p; ++j) {
+            const int ref = I.th_ref[tp * p + j];
+            e.push_back({I.th_idx[tp * p + j] | (ref << 16), ref ? -I.th_w[tp * p + j] : I.th_w[tp * p + j]});
+          }
+          return e;
+        });
+    // anterpolation l -> l+1: weighted transposes, phi first (parent phi ->
+    // child phi), then theta over parent rows with reflection in child phi
+    build_tab(
+        P.mf_at[l], I.ntc, I.npc, I.ntp,
+        [&](int uc) {
+          std::vector<std::pair<int32_t, double>> e;
+          for (int q = I.pht_ptr[uc]; q < I.pht_ptr[uc + 1]; ++q) e.push_back({I.pht_idx[q], I.pht_w[q]});
+          return e;
+        },
+        [&](int tc) {
+          std::vector<std::pair<int32_t, double>> e;
+          for (int q = I.tht_ptr[tc]; q < I.tht_ptr[tc + 1]; ++q) {
+            const int ref = I.tht_ref[q];
+            e.push_back({I.tht_idx[q] | (ref << 16), ref ? -I.tht_w[q] : I.tht_w[q]});
+          }
+          return e;
+        });
+  }
+}
+
 void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri, double kk,
                  const Opts& o) {
   opt = o;
@@ -666,6 +793,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
       }
     }
   }
+  build_mf_tables(*this);
   if (o.flags & 4u) check_coverage();
 }
 
@@ -718,7 +846,17 @@ std::string Plan::stats_json() const {
     s << "{\"l\": " << l << ", \"a\": " << Lv.a << ", \"nbox\": " << Lv.nbox << ", \"L\": " << Lv.L
       << ", \"nt\": " << Lv.nt << ", \"np\": " << Lv.np << ", \"K\": " << Lv.K
       << ", \"far_pairs\": " << (Lv.far_src.size()) << ", \"farR_pairs\": " << (Lv.farR_src.size())
-      << ", \"tile_sources\": " << Lv.tile_src.size() << ", \"n_off_used\": " << Lv.n_off_used << "}";
+      << ", \"tile_sources\": " << Lv.tile_src.size() << ", \"n_off_used\": " << Lv.n_off_used;
+    // matrix-core interpolation tables (into level l, and anterpolation from it)
+    auto mf = [&](const char* key, const std::vector<MfTab>& v) {
+      if (l >= (int)v.size() || !v[l].nchunk) return;
+      const MfTab& T = v[l];
+      s << ", \"" << key << "\": {\"ok\": " << (T.ok ? 1 : 0) << ", \"NT\": " << T.NT << ", \"S2\": " << T.S2
+        << ", \"nchunk\": " << T.nchunk << ", \"kmax\": " << T.kmax << ", \"ktmax\": " << T.ktmax << "}";
+    };
+    mf("mf_interp", mf_ip);
+    mf("mf_anterp", mf_at);
+    s << "}";
   }
   s << "]}";
   return s.str();

@@ -65,6 +65,26 @@ struct Interp {
   std::vector<int32_t> pht_ptr, pht_idx; std::vector<double> pht_w;
 };
 
+// Operand tables of the matrix-core (16x16x4 MFMA) interpolation kernels for
+// one level pair.  A block of S = 2*S2 "slots" holds a set U of phi indices
+// and U + np/2 (its pole-reflection partners); the slots are the M rows of
+// the phi step.  K steps gather the inputs a row block actually needs, four
+// per step (lane group g = lane/16 holds input key[k*4+g]); the A operand of
+// step k for lane l = 16 g + r is the weight of input key[k*4+g] in output row r.
+struct MfTab {
+  bool ok = false;
+  int NT = 0, S2 = 0;           // theta row tiles of 16; half slot count
+  int half = 0;                 // np/2 of the slotted grid
+  int nchunk = 0, kmax = 0, ktmax = 0;
+  std::vector<int32_t> chunk;   // nchunk x 2: first phi index, slots used per half
+  std::vector<int32_t> nk;      // nchunk: phi K steps
+  std::vector<int32_t> kidx;    // nchunk x kmax x 4: phi input index
+  std::vector<double> kA;       // nchunk x kmax x 64
+  std::vector<int32_t> nkt;     // NT: theta K steps per row tile
+  std::vector<int32_t> tidx;    // NT x ktmax x 4: theta input row | reflected << 16
+  std::vector<double> tA;       // NT x ktmax x 64
+};
+
 struct Opts {
   int nlv = 0;
   double d0 = 3.0;
@@ -93,6 +113,7 @@ struct Plan {
   int nlv = 0, lf = 0;          // leaf level = nlv - 1
   std::vector<Level> lev;       // 0..lf
   std::vector<Interp> ip;       // ip[l] maps level l+1 -> l, for l = 2..lf-1
+  std::vector<MfTab> mf_ip, mf_at;  // matrix-core tables: interpolation into l, anterpolation from l
   std::vector<int32_t> perm;    // internal index -> public RWG index
   std::vector<int32_t> iperm;   // public -> internal
   std::vector<int32_t> box_start;  // leaf box -> first internal unknown (nleaf+1)
