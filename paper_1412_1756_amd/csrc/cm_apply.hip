@@ -964,6 +964,11 @@ struct Stages {
 
   void aggregate(const void* V, const CR* xi, int ldx, CR* S, int ldS, int nc) {
     const int K = P.lev[d.lf].K;
+    if constexpr (sizeof(R) == 4) {
+      if (!(P.opt.flags & CM_FLAG_VALU_INTERP) &&
+          mf_aggregate(V, (const float2*)xi, ldx, (float2*)S, ldS, d.box_start, d.nleaf, K, nc, s))
+        return;
+    }
     if (nc % 4 == 0 && (size_t)d.max_box * nc * sizeof(CR) <= 48 * 1024) {
       int tot = 2 * K * nc / 4;
       int gy = std::max(1, std::min(4, (tot + 1023) / 1024));
@@ -1085,6 +1090,12 @@ struct Stages {
   void disagg(const void* V, const CR* G, int ldp, const CR* yi, CR* y, int64_t ld, const int32_t* perm, int nc,
               int conj) {
     const int K = P.lev[d.lf].K;
+    if constexpr (sizeof(R) == 4) {
+      if (!(P.opt.flags & CM_FLAG_VALU_INTERP) &&
+          mf_disagg(V, (const float2*)G, ldp, (const float*)pd.qwc, (const float2*)yi, d.box_start, d.nleaf,
+                    d.max_box, perm, K, nc, (float2*)y, ld, conj, s))
+        return;
+    }
     if (nc == 1)
       hipLaunchKernelGGL(k_disagg1<R>, dim3((unsigned)((d.N + 3) / 4)), dim3(256), 0, s, (const CR*)V, G,
                          (const R*)pd.qwc, yi, d.box_of, perm, K, d.N, ldp, y, ld, conj);

@@ -118,6 +118,13 @@ bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* S
                int accum, const void* shiftT, hipStream_t s);
 bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc, int ldp,
                int add, const void* zg, hipStream_t s);
+// Matrix-core leaf aggregation / disaggregation (complex float, nc % 8 == 0);
+// false when not covered (disaggregation: boxes of more than 64 unknowns).
+bool mf_aggregate(const void* V, const float2* xi, int ldx, float2* S, int ldS, const int32_t* box_start, int nbox,
+                  int K, int nc, hipStream_t s);
+bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const float2* yi, const int32_t* box_start,
+               int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
+               hipStream_t s);
 // whether mf_anterp takes the anterpolation from level Lp for nc columns
 bool mf_covers(const LevelD<float>& Lp, int nc);
 

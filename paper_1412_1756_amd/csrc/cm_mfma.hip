@@ -361,6 +361,179 @@ __global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp,
     }
 }
 
+// Leaf aggregation S_box[row][c] = sum_i V_i[row] x_i[c] over the unknowns i
+// of a leaf box (rows: component x direction, 2K of them): a complex product
+// on the matrix cores as two real MFMAs, C += Re(A) B + Im(A) B~, where B~ is
+// B with each (re, im) column pair swapped and the new re negated.  One wave
+// owns MTW row tiles of 16 and NTL column tiles of 16 reals; K runs over the
+// box's unknowns four at a time.  Grid: waves box-major, 256 threads.
+template <int MTW, int NTL>
+__global__ void __launch_bounds__(256) k_aggregate_mf(const float2* __restrict__ V, const float* __restrict__ xi,
+                                                      int ldx, float* __restrict__ S, int ldS,
+                                                      const int32_t* __restrict__ box_start, int nbox, int K2, int nc,
+                                                      int wpb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int wid = blockIdx.x * 4 + w;
+  const int box = wid / wpb, m0 = (wid - box * wpb) * MTW * 16;
+  if (box >= nbox || m0 >= K2) return;
+  const int i0 = box_start[box], i1 = box_start[box + 1];
+  const int ntiles = nc >> 3;
+  const float sg = (r & 1) ? 1.f : -1.f;
+  for (int nt0 = 0; nt0 < ntiles; nt0 += NTL) {
+    f4 acc[MTW][NTL];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int i = i0; i < i1; i += 4) {
+      const int ii = i + g;
+      const bool ok = ii < i1;
+      float2 a[MTW];
+      float bq[NTL];
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt) {
+        const int row = m0 + 16 * mt + r;
+        a[mt] = (ok && row < K2) ? V[(int64_t)ii * K2 + row] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt)
+        bq[nt] = (ok && nt0 + nt < ntiles) ? xi[(int64_t)ii * 2 * ldx + 16 * (nt0 + nt) + r] : 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) {
+        const float bs = sg * pair_swap(bq[nt]);
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+          acc[mt][nt] = mma(a[mt].x, bq[nt], acc[mt][nt]);
+          acc[mt][nt] = mma(a[mt].y, bs, acc[mt][nt]);
+        }
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) {
+        if (nt0 + nt >= ntiles) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = m0 + 16 * mt + 4 * g + j;
+          if (row < K2) S[((int64_t)box * K2 + row) * 2 * ldS + 16 * (nt0 + nt) + r] = acc[mt][nt][j];
+        }
+      }
+  }
+}
+
+// Leaf disaggregation y_i = yi_i + sum_row w_q conj(V_i[row]) G_box[row] (the
+// far-field part of every unknown of a box), optionally conjugated, written
+// at perm[i] (internal position i without perm).  One block per leaf box: its
+// four waves split the 2K rows, each accumulating all the box's unknowns (MTU
+// tiles of 16) times NTL column tiles on the matrix cores; the partial sums
+// meet in LDS.
+template <int MTU, int NTL>
+__global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V, const float* __restrict__ G, int ldp,
+                                                   const float* __restrict__ qwc, const float* __restrict__ yi,
+                                                   const int32_t* __restrict__ box_start,
+                                                   const int32_t* __restrict__ perm, int K, int nc,
+                                                   float* __restrict__ y, int64_t ld, int conj_out) {
+  constexpr int NV = MTU * NTL * 4;   // accumulator floats per lane
+  extern __shared__ float red[];      // [4 waves][NV][64]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int box = blockIdx.x;
+  const int i0 = box_start[box], i1 = box_start[box + 1];
+  const int K2 = 2 * K, nks = (K2 + 3) / 4;
+  const int ks0 = w * nks / 4, ks1 = (w + 1) * nks / 4;
+  const int ntiles = nc >> 3;
+  const float sg = (r & 1) ? 1.f : -1.f;
+  const float* gb = G + (int64_t)box * K2 * 2 * ldp;
+  for (int nt0 = 0; nt0 < ntiles; nt0 += NTL) {
+    f4 acc[MTU][NTL];
+#pragma unroll
+    for (int mt = 0; mt < MTU; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int ks = ks0; ks < ks1; ++ks) {
+      const int row = 4 * ks + g;
+      const bool rok = row < K2;
+      const float wq = rok ? qwc[row < K ? row : row - K] : 0.f;
+      float2 a[MTU];
+      float bq[NTL];
+#pragma unroll
+      for (int mt = 0; mt < MTU; ++mt) {
+        const int i = i0 + 16 * mt + r;
+        const float2 v = (rok && i < i1) ? V[(int64_t)i * K2 + row] : make_float2(0.f, 0.f);
+        a[mt] = make_float2(wq * v.x, -wq * v.y);   // w_q conj(V)
+      }
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt)
+        bq[nt] = (rok && nt0 + nt < ntiles) ? gb[(int64_t)row * 2 * ldp + 16 * (nt0 + nt) + r] : 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) {
+        const float bs = sg * pair_swap(bq[nt]);
+#pragma unroll
+        for (int mt = 0; mt < MTU; ++mt) {
+          acc[mt][nt] = mma(a[mt].x, bq[nt], acc[mt][nt]);
+          acc[mt][nt] = mma(a[mt].y, bs, acc[mt][nt]);
+        }
+      }
+    }
+    __syncthreads();   // the previous column group's reads of red are done
+#pragma unroll
+    for (int mt = 0; mt < MTU; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[(w * NV + (mt * NTL + nt) * 4 + j) * 64 + lane] = acc[mt][nt][j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NV * 64; e += 256) {
+      const int v = e >> 6, l = e & 63;
+      const int j = v & 3, nt = (v >> 2) % NTL, mt = (v >> 2) / NTL;
+      const int i = i0 + 16 * mt + 4 * (l >> 4) + j;
+      const int colf = 16 * (nt0 + nt) + (l & 15);
+      if (i >= i1 || nt0 + nt >= ntiles) continue;
+      float sum = red[e] + red[NV * 64 + e] + red[2 * NV * 64 + e] + red[3 * NV * 64 + e];
+      sum += yi[(int64_t)i * 2 * nc + colf];
+      if (conj_out && (colf & 1)) sum = -sum;
+      y[(int64_t)(perm ? perm[i] : i) * 2 * ld + colf] = sum;
+    }
+  }
+}
+
+bool mf_aggregate(const void* V, const float2* xi, int ldx, float2* S, int ldS, const int32_t* box_start, int nbox,
+                  int K, int nc, hipStream_t s) {
+  if (nc % 8 != 0) return false;
+  constexpr int MTW = 3, NTL = 4;
+  const int K2 = 2 * K;
+  const int wpb = (K2 + 16 * MTW - 1) / (16 * MTW);
+  const int64_t waves = (int64_t)nbox * wpb;
+  hipLaunchKernelGGL((k_aggregate_mf<MTW, NTL>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                     (const float2*)V, (const float*)xi, ldx, (float*)S, ldS, box_start, nbox, K2, nc, wpb);
+  return true;
+}
+
+bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const float2* yi, const int32_t* box_start,
+               int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
+               hipStream_t s) {
+  if (nc % 8 != 0 || max_box > 64) return false;
+  constexpr int NTL = 4;
+#define CM_DIS(MTU)                                                                                            \
+  hipLaunchKernelGGL((k_disagg_mf<MTU, NTL>), dim3(nbox), dim3(256), (size_t)4 * MTU * NTL * 4 * 64 * 4, s,   \
+                     (const float2*)V, (const float*)G, ldp, qwc, (const float*)yi, box_start, perm, K, nc,   \
+                     (float*)y, ld, conj)
+  if (max_box <= 16)
+    CM_DIS(1);
+  else if (max_box <= 32)
+    CM_DIS(2);
+  else if (max_box <= 48)
+    CM_DIS(3);
+  else
+    CM_DIS(4);
+#undef CM_DIS
+  return true;
+}
+
 static void lds_limit(const void* f, size_t bytes) {
   if (bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

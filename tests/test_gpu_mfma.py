@@ -1,13 +1,16 @@
 """Matrix-core (MFMA) interpolation/anterpolation against the vector-ALU
 kernels and the CPU FP64 oracle, through the C ABI.
 
-Both FP32 paths compute the same sums (section III's separable Lagrange
-interpolation and its weighted transpose) in a different order, so they must
-agree to FP32 rounding: a relative 2-norm difference of 5e-5 per column, the
-spread that reordering alone produces in the FP32 product (the batched and
-single-column FP32 applies, which share every kernel but the accumulation
-order, differ by up to 3e-5 on the same inputs).  Against the oracle the FP32 bound of the method's product, 5e-4,
-applies.  Column counts 8, 24 (a partly filled block of column tiles) and 32
+Both FP32 paths compute the same sums (the leaf aggregation and
+disaggregation, and section III's separable Lagrange interpolation and its
+weighted transpose) in a different order, so they differ by FP32 rounding
+only: each is measured against the FP64 apply with the same truncation and
+interpolation, and the matrix-core path must be about as accurate as the
+vector-ALU one (within 50%: the leaf products add four terms per matrix-core
+step, and the X part of Z amplifies rounding through near/far cancellation,
+4.5e-5 relative to FP64 on this sphere); their mutual difference stays below
+1e-4.  Against
+the oracle the FP32 bound of the method's product, 5e-4, applies.  Column counts 8, 24 (a partly filled block of column tiles) and 32
 with a row stride larger than the column count; the dZ/dk pass exercises the
 accumulating (second-term) variants.
 """
@@ -20,7 +23,7 @@ pytestmark = pytest.mark.gpu
 
 K0 = 2 * np.pi
 ACC32 = dict(d0=5.0, interp_p=10)
-TOL_PATH, TOL32 = 5e-5, 5e-4
+TOL_PATH, TOL32 = 1e-4, 5e-4
 
 
 def colerr(a, b):
@@ -57,17 +60,19 @@ def test_mfma_matches_valu(torch_cuda, ops, ncols, ld, opname):
     mf, va = ops
     N = mf.N
     print(f"mfma vs valu op={opname} ncols={ncols} ld={ld} N={N}", flush=True)
-    X = torch.tensor(workloads.cn01_block(N, ncols, 300 + ncols), dtype=torch.complex64, device="cuda")
+    Xh = workloads.cn01_block(N, ncols, 300 + ncols)
     buf = torch.zeros((N, ld), dtype=torch.complex64, device="cuda")
     xin = buf[:, :ncols]
-    xin.copy_(X)
+    xin.copy_(torch.tensor(Xh, dtype=torch.complex64, device="cuda"))
     o1 = torch.zeros((N, ld), dtype=torch.complex64, device="cuda")[:, :ncols]
     o2 = torch.zeros((N, ld), dtype=torch.complex64, device="cuda")[:, :ncols]
     y1 = mf.apply(xin, op=opname, out=o1).cpu().numpy()
     y2 = va.apply(xin, op=opname, out=o2).cpu().numpy()
-    e = colerr(y1, y2)
-    print(f"  max column rel diff {e:.2e}", flush=True)
+    y3 = mf.apply(torch.tensor(Xh, dtype=torch.complex128, device="cuda"), op=opname).cpu().numpy()
+    e, e1, e2 = colerr(y1, y2), colerr(y1, y3), colerr(y2, y3)
+    print(f"  max column rel diff {e:.2e}; vs fp64: mfma {e1:.2e} valu {e2:.2e}", flush=True)
     assert e < TOL_PATH
+    assert e1 <= 1.5 * e2 + 2e-6
 
 
 def test_mfma_sampled_rows_match_oracle(torch_cuda, sphere2, ops):
