@@ -78,10 +78,11 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
 #define CM_FLAG_DERIV     2u   /* also build dZ_near/dk and derivative tables */
 #define CM_FLAG_CHECK     4u   /* brute-force check that every leaf-box pair is
                                   covered exactly once (O(boxes^2))          */
-#define CM_FLAG_VALU_INTERP 8u /* FP32 applies: use the vector-ALU
-                                  interpolation/anterpolation kernels instead
-                                  of the matrix-core ones (same arithmetic up
-                                  to rounding order)                         */
+#define CM_FLAG_NO_MATRIX_CORES 8u /* applies use the vector-ALU kernels
+                                  only: no MFMA for the near field, the leaf
+                                  aggregation/disaggregation and the
+                                  interpolation (FP32 applies then keep the
+                                  near-field product in FP64)                */
 
 typedef struct {
   int32_t nlv;       /* number of octree levels including level 0 (>= 3)        */

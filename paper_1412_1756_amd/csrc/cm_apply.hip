@@ -965,7 +965,7 @@ struct Stages {
   void aggregate(const void* V, const CR* xi, int ldx, CR* S, int ldS, int nc) {
     const int K = P.lev[d.lf].K;
     if constexpr (sizeof(R) == 4) {
-      if (!(P.opt.flags & CM_FLAG_VALU_INTERP) &&
+      if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) &&
           mf_aggregate(V, (const float2*)xi, ldx, (float2*)S, ldS, d.box_start, d.nleaf, K, nc, s))
         return;
     }
@@ -991,7 +991,7 @@ struct Stages {
   void interp(int l, const CR* Sc, CR* Sp, int nc, int ldp, int accum, const void* shift) {
     if constexpr (sizeof(R) == 4) {
       const void* sT = (shift == pd.lev[l].dshift) ? pd.lev[l].dshiftT : pd.lev[l].shiftT;
-      if (!(P.opt.flags & CM_FLAG_VALU_INTERP) &&
+      if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) &&
           mf_interp(pd.lev[l], pd.lev[l + 1], (const float2*)Sc, (float2*)Sp, nc, ldp, accum, sT, s))
         return;
     }
@@ -1091,7 +1091,7 @@ struct Stages {
               int conj) {
     const int K = P.lev[d.lf].K;
     if constexpr (sizeof(R) == 4) {
-      if (!(P.opt.flags & CM_FLAG_VALU_INTERP) &&
+      if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) &&
           mf_disagg(V, (const float2*)G, ldp, (const float*)pd.qwc, (const float2*)yi, d.box_start, d.nleaf,
                     d.max_box, perm, K, nc, (float2*)y, ld, conj, s))
         return;
@@ -1133,7 +1133,18 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   }
   const dim3 rows_grid((unsigned)((N + 3) / 4));
   stage_begin(d, s, 1);
-  if (nc % 4 == 0 && nc <= 64)
+  bool near_done = false;
+  if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES)) {
+    if constexpr (sizeof(R) == 4)
+      near_done = mf_near32(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off, dual ? d.dZn32 : d.Zn32,
+                            (const float2*)xi, (float2*)yi, d.nleaf, d.max_near_cols, nc, kind, s);
+    else
+      near_done = mf_near<R>(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off,
+                             (const double2*)(dual ? d.dZn : d.Zn), xi, yi, d.nleaf, d.max_box, d.max_near_cols, nc,
+                             kind, s);
+  }
+  if (near_done) {
+  } else if (nc % 4 == 0 && nc <= 64)
     hipLaunchKernelGGL(k_near_box<R>, dim3(d.nleaf), dim3(256), 0, s, d.row_ptr, d.box_start, d.bcol_ptr, d.bcol,
                        d.self_off, (const double2*)(dual ? d.dZn : d.Zn), (const CR*)xi, yi, nc, kind);
   else
@@ -1157,7 +1168,7 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   // anterpolation adds onto them.
   bool mf_down = false;
   if constexpr (sizeof(R) == 4) {
-    mf_down = !(P.opt.flags & CM_FLAG_VALU_INTERP) && nc % 8 == 0;
+    mf_down = !(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) && nc % 8 == 0;
     for (int l = 2; l < lf && mf_down; ++l) mf_down = mf_covers(pd.lev[l], nc);
   }
   auto m2l_level = [&](int l, int accum) {

@@ -184,7 +184,10 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   d.nleaf = P.lev[P.lf].nbox;
   d.Kleaf = P.lev[P.lf].K;
   d.max_cols = P.opt.max_cols;
-  for (int b = 0; b < P.lev[P.lf].nbox; ++b) d.max_box = std::max(d.max_box, P.box_start[b + 1] - P.box_start[b]);
+  for (int b = 0; b < P.lev[P.lf].nbox; ++b) {
+    d.max_box = std::max(d.max_box, P.box_start[b + 1] - P.box_start[b]);
+    d.max_near_cols = std::max(d.max_near_cols, P.bcol_ptr[b + 1] - P.bcol_ptr[b]);
+  }
   const int lf = P.lf;
   // triangles
   std::vector<TriD> tri(P.nt);
@@ -258,6 +261,13 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   chk(hipGetLastError(), "leaf pattern launch");
   launch_near_fill(P.k, P.opt.eta, d, d.nleaf, s);
   chk(hipGetLastError(), "near fill launch");
+  // FP32 copies for the FP32 matrix-core near field
+  d.Zn32 = (float2*)dmalloc(d, (size_t)std::max<int64_t>(1, d.nnz) * sizeof(float2));
+  blas_to_c64(d.Zn, d.Zn32, d.nnz, s);
+  if (deriv) {
+    d.dZn32 = (float2*)dmalloc(d, (size_t)std::max<int64_t>(1, d.nnz) * sizeof(float2));
+    blas_to_c64(d.dZn, d.dZn32, d.nnz, s);
+  }
   // workspace
   d.S.assign(lf + 1, nullptr);
   d.G.assign(lf + 1, nullptr);

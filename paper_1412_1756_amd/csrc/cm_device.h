@@ -72,6 +72,7 @@ struct Dev {
   int device = 0;
   int64_t N = 0, nnz = 0;
   int lf = 0, nleaf = 0, Kleaf = 0, max_cols = 0, max_box = 0;   // max_box: most unknowns in a leaf box
+  int max_near_cols = 0;                    // most near-field columns of a leaf box
   TriD* tri = nullptr;
   RwgD* rwg = nullptr;
   int32_t *perm = nullptr, *box_of = nullptr, *box_start = nullptr;
@@ -81,6 +82,7 @@ struct Dev {
   double* leaf_dirs = nullptr;              // 9 x K_leaf
   double2* Zn = nullptr;                    // near-field values (nnz)
   double2* dZn = nullptr;                   // dZ_near/dk values (nnz)
+  float2 *Zn32 = nullptr, *dZn32 = nullptr; // their FP32 copies (FP32 matrix-core near field)
   PrecD<float> f32;
   PrecD<double> f64;
   // workspace (sized for max_cols, complex double; reused as complex float)
@@ -125,9 +127,20 @@ bool mf_aggregate(const void* V, const float2* xi, int ldx, float2* S, int ldS, 
 bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const float2* yi, const int32_t* box_start,
                int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
                hipStream_t s);
+// Near-field product on the FP64 matrix cores (x, y complex R; nc % 8 == 0,
+// nc <= 64, leaf boxes of at most 64 unknowns); mode 0 Z, 1 Re Z self box, 2 Im Z.
+template <typename R>
+bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
+             const int32_t* self_off, const double2* Zn, const void* xi, void* yi, int nleaf, int max_box,
+             int max_cols_box, int nc, int mode, hipStream_t s);
+// the same on FP32 near-field values and FP32 matrix cores (complex float x, y)
+bool mf_near32(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
+               const int32_t* self_off, const float2* Zn, const float2* xi, float2* yi, int nleaf,
+               int max_cols_box, int nc, int mode, hipStream_t s);
 // whether mf_anterp takes the anterpolation from level Lp for nc columns
 bool mf_covers(const LevelD<float>& Lp, int nc);
 
+void blas_to_c64(const double2* x, float2* y, int64_t N, hipStream_t s);   // complex double -> float
 void dev_build(Dev& d, const Plan& P, hipStream_t s);
 void dev_free(Dev& d);
 // op: 0 Z, 1 R, 2 X, 3 Z^H, 4 dZ/dk

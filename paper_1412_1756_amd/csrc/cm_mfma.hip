@@ -534,6 +534,266 @@ bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const 
   return true;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: A and B lanes as in the FP32 form (lane 16 k + m,
+// lane 16 k + n); result register j of lane 16 g + n holds row 4 j + g.
+__device__ __forceinline__ d4 mma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ double pair_swap64(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffll), 0xB1, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0xB1, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Near-field product y_i = sum_t Z_near[i, t] x[col_t] (mode 1: Re Z_near on
+// the box's own columns, mode 2: Im Z_near) on the FP64 matrix cores.  One
+// wave per leaf box: two row tiles of 16 at a time times every column tile
+// of 16 reals (x rows gathered from memory and converted to FP64), so each
+// near-field value is loaded once.  Complex steps as in the leaf
+// aggregation: C += Re(A) B + Im(A) B~.  nc <= 32.
+template <typename R, int MODE>
+__global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row_ptr,
+                                                 const int32_t* __restrict__ box_start,
+                                                 const int32_t* __restrict__ bcol_ptr,
+                                                 const int32_t* __restrict__ bcol,
+                                                 const int32_t* __restrict__ self_off, const double2* __restrict__ Zn,
+                                                 const R* __restrict__ xi, R* __restrict__ yi, int nleaf, int nc,
+                                                 int xcap) {
+  extern __shared__ int32_t xoff_all[];   // per wave: the box's column rows as offsets into x (floats)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int b = blockIdx.x * 4 + w;
+  if (b >= nleaf) return;
+  int32_t* xoff = xoff_all + w * xcap;
+  const int r0 = box_start[b], nb = box_start[b + 1] - r0;
+  const int32_t* cols = bcol + bcol_ptr[b];
+  int t0 = 0, t1 = bcol_ptr[b + 1] - bcol_ptr[b];
+  if (MODE == 1) {
+    t0 = self_off[b];
+    t1 = t0 + nb;
+  }
+  const int nc2 = 2 * nc, ntiles = nc >> 3;
+  // K steps of four columns in groups of two, the same count on every lane
+  const int ngrp = (t1 - t0 + 7) / 8;
+  for (int e = lane; e < 8 * ngrp; e += 64) xoff[e] = (t0 + e < t1) ? cols[t0 + e] * nc2 : -1;
+  wave_lds_sync();
+  const int tlast = t1 - t0 - 1;
+  const double sg = (r & 1) ? 1.0 : -1.0;
+  for (int m0 = 0; m0 < nb; m0 += 32) {
+    // this lane's A-operand rows (one per row tile); every load is in bounds
+    // (padding reads a valid entry and is zeroed afterwards)
+    bool iok[2];
+    const double2* zrow[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      iok[mt] = m0 + 16 * mt + r < nb;
+      zrow[mt] = Zn + row_ptr[r0 + (iok[mt] ? m0 + 16 * mt + r : 0)] + t0;
+    }
+    d4 acc[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int gi, double2 (&z)[2][2], R (&xv)[2][4]) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int tt = 8 * gi + 4 * u + g;
+        const int xo = xoff[tt];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) z[u][mt] = zrow[mt][min(tt, tlast)];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) xv[u][nt] = (nt < ntiles) ? xi[(xo >= 0 ? xo : 0) + 16 * nt + r] : (R)0;
+      }
+    };
+    auto step = [&](int gi, double2 (&z)[2][2], R (&xv)[2][4]) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool ok = xoff[8 * gi + 4 * u + g] >= 0;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          if (nt >= ntiles) continue;
+          const double bv = ok ? (double)xv[u][nt] : 0.0;
+          const double bs = sg * pair_swap64(bv);
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const double2 zz = (iok[mt] && ok) ? z[u][mt] : make_double2(0.0, 0.0);
+            acc[mt][nt] = mma64((MODE == 2) ? zz.y : zz.x, bv, acc[mt][nt]);
+            if (MODE == 0) acc[mt][nt] = mma64(zz.y, bs, acc[mt][nt]);
+          }
+        }
+      }
+    };
+    double2 za[2][2], zb[2][2];
+    R xa[2][4], xb[2][4];
+    load(0, za, xa);
+    for (int gi = 0; gi < ngrp; gi += 2) {
+      if (gi + 1 < ngrp) load(gi + 1, zb, xb);
+      step(gi, za, xa);
+      if (gi + 1 < ngrp) {
+        if (gi + 2 < ngrp) load(gi + 2, za, xa);
+        step(gi + 1, zb, xb);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        if (nt >= ntiles) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ii = m0 + 16 * mt + 4 * j + g;   // FP64 16x16x4 result: row 4 j + lane / 16
+          if (ii < nb) yi[(int64_t)(r0 + ii) * nc2 + 16 * nt + r] = (R)acc[mt][nt][j];
+        }
+      }
+  }
+}
+
+// FP32 form of the near-field product for the FP32 applies: near-field values
+// rounded to FP32 once at set-up, FP32 matrix-core steps (v_mfma_f32_16x16x4:
+// about three times the FP64 rate), same work layout as k_near_mf.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_near_mf32(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ box_start,
+                                                   const int32_t* __restrict__ bcol_ptr,
+                                                   const int32_t* __restrict__ bcol,
+                                                   const int32_t* __restrict__ self_off,
+                                                   const float2* __restrict__ Zn, const float* __restrict__ xi,
+                                                   float* __restrict__ yi, int nleaf, int nc, int xcap) {
+  extern __shared__ int32_t xoff_all[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int b = blockIdx.x * 4 + w;
+  if (b >= nleaf) return;
+  int32_t* xoff = xoff_all + w * xcap;
+  const int r0 = box_start[b], nb = box_start[b + 1] - r0;
+  const int32_t* cols = bcol + bcol_ptr[b];
+  int t0 = 0, t1 = bcol_ptr[b + 1] - bcol_ptr[b];
+  if (MODE == 1) {
+    t0 = self_off[b];
+    t1 = t0 + nb;
+  }
+  const int nc2 = 2 * nc, ntiles = nc >> 3;
+  const int ngrp = (t1 - t0 + 7) / 8;
+  for (int e = lane; e < 8 * ngrp; e += 64) xoff[e] = (t0 + e < t1) ? cols[t0 + e] * nc2 : -1;
+  wave_lds_sync();
+  const int tlast = t1 - t0 - 1;
+  const float sg = (r & 1) ? 1.f : -1.f;
+  for (int m0 = 0; m0 < nb; m0 += 32) {
+    bool iok[2];
+    const float2* zrow[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      iok[mt] = m0 + 16 * mt + r < nb;
+      zrow[mt] = Zn + row_ptr[r0 + (iok[mt] ? m0 + 16 * mt + r : 0)] + t0;
+    }
+    f4 acc[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    auto load = [&](int gi, float2 (&z)[2][2], float (&xv)[2][4]) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int tt = 8 * gi + 4 * u + g;
+        const int xo = xoff[tt];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) z[u][mt] = zrow[mt][min(tt, tlast)];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) xv[u][nt] = (nt < ntiles) ? xi[(xo >= 0 ? xo : 0) + 16 * nt + r] : 0.f;
+      }
+    };
+    auto step = [&](int gi, float2 (&z)[2][2], float (&xv)[2][4]) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool ok = xoff[8 * gi + 4 * u + g] >= 0;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          if (nt >= ntiles) continue;
+          const float bv = ok ? xv[u][nt] : 0.f;
+          const float bs = sg * pair_swap(bv);
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const float2 zz = (iok[mt] && ok) ? z[u][mt] : make_float2(0.f, 0.f);
+            acc[mt][nt] = mma((MODE == 2) ? zz.y : zz.x, bv, acc[mt][nt]);
+            if (MODE == 0) acc[mt][nt] = mma(zz.y, bs, acc[mt][nt]);
+          }
+        }
+      }
+    };
+    float2 za[2][2], zb[2][2];
+    float xa[2][4], xb[2][4];
+    load(0, za, xa);
+    for (int gi = 0; gi < ngrp; gi += 2) {
+      if (gi + 1 < ngrp) load(gi + 1, zb, xb);
+      step(gi, za, xa);
+      if (gi + 1 < ngrp) {
+        if (gi + 2 < ngrp) load(gi + 2, za, xa);
+        step(gi + 1, zb, xb);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        if (nt >= ntiles) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ii = m0 + 16 * mt + 4 * g + j;
+          if (ii < nb) yi[(int64_t)(r0 + ii) * nc2 + 16 * nt + r] = acc[mt][nt][j];
+        }
+      }
+  }
+}
+
+bool mf_near32(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
+               const int32_t* self_off, const float2* Zn, const float2* xi, float2* yi, int nleaf,
+               int max_cols_box, int nc, int mode, hipStream_t s) {
+  if (!Zn || nc % 8 != 0 || nc > 32 || max_cols_box > 4096) return false;
+  const int xcap = (max_cols_box + 8 + 7) / 8 * 8;
+  const size_t sh = (size_t)4 * xcap * sizeof(int32_t);
+  const dim3 grid((unsigned)((nleaf + 3) / 4));
+#define CM_NEAR(M)                                                                                                   \
+  hipLaunchKernelGGL((k_near_mf32<M>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol, self_off, Zn,    \
+                     (const float*)xi, (float*)yi, nleaf, nc, xcap)
+  if (mode == 0)
+    CM_NEAR(0);
+  else if (mode == 1)
+    CM_NEAR(1);
+  else
+    CM_NEAR(2);
+#undef CM_NEAR
+  return true;
+}
+
+template <typename R>
+bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
+             const int32_t* self_off, const double2* Zn, const void* xi, void* yi, int nleaf, int max_box,
+             int max_cols_box, int nc, int mode, hipStream_t s) {
+  if (nc % 8 != 0 || nc > 32 || max_cols_box > 4096) return false;
+  const int xcap = (max_cols_box + 8 + 7) / 8 * 8;
+  const size_t sh = (size_t)4 * xcap * sizeof(int32_t);
+  const dim3 grid((unsigned)((nleaf + 3) / 4));
+  (void)max_box;
+#define CM_NEAR(M)                                                                                                 \
+  hipLaunchKernelGGL((k_near_mf<R, M>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol, self_off, Zn, \
+                     (const R*)xi, (R*)yi, nleaf, nc, xcap)
+  if (mode == 0)
+    CM_NEAR(0);
+  else if (mode == 1)
+    CM_NEAR(1);
+  else
+    CM_NEAR(2);
+#undef CM_NEAR
+  return true;
+}
+template bool mf_near<float>(const int64_t*, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                             const double2*, const void*, void*, int, int, int, int, int, hipStream_t);
+template bool mf_near<double>(const int64_t*, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                              const double2*, const void*, void*, int, int, int, int, int, hipStream_t);
+
 static void lds_limit(const void* f, size_t bytes) {
   if (bytes > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

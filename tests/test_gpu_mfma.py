@@ -49,7 +49,7 @@ def ops(sphere2):
     from paper_1412_1756_amd import Operator
     V, F = sphere2
     mf = Operator(V, F, K0, nlv=5, max_cols=32, **ACC32)
-    va = Operator(V, F, K0, nlv=5, max_cols=32, valu_interp=True, **ACC32)
+    va = Operator(V, F, K0, nlv=5, max_cols=32, matrix_cores=False, **ACC32)
     return mf, va
 
 
@@ -102,7 +102,7 @@ def test_mfma_dzdk_matches_valu(torch_cuda, sphere2):
     from paper_1412_1756_amd import Operator
     V, F = sphere2
     mf = Operator(V, F, K0, nlv=5, max_cols=8, deriv=True, **ACC32)
-    va = Operator(V, F, K0, nlv=5, max_cols=8, deriv=True, valu_interp=True, **ACC32)
+    va = Operator(V, F, K0, nlv=5, max_cols=8, deriv=True, matrix_cores=False, **ACC32)
     X = workloads.cn01_block(mf.N, 8, 700)
     y1 = mf.apply(torch.tensor(X, dtype=torch.complex64, device="cuda"), op="DZDK").cpu().numpy()
     y2 = va.apply(torch.tensor(X, dtype=torch.complex64, device="cuda"), op="DZDK").cpu().numpy()
