@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
 // receivers' lists; each source pattern element is loaded once and applied to
 // every receiver of the tile that lists it (register accumulators).  With
 // STAGE the block's translator rows are staged in LDS first.
-template <typename R, bool STAGE, int QPT>
+template <typename R, bool STAGE, int QPT, int RT>
 __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tsrc,
                                              const int32_t* __restrict__ toff, const C2<R>* __restrict__ T,
                                              int n_off, const C2<R>* __restrict__ S, C2<R>* __restrict__ G,
@@ -349,78 +349,83 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
     }
     __syncthreads();
   }
-  C2<R> a0[QPT][kTile], a1[QPT][kTile];
-#pragma unroll
-  for (int u = 0; u < QPT; ++u)
-#pragma unroll
-    for (int r = 0; r < kTile; ++r) a0[u][r] = a1[u][r] = mk<R>(0, 0);
   const int e0 = tptr[tile], e1 = tptr[tile + 1];
-  // software pipelining: the next source's pattern loads are in flight while
-  // the current one is applied to the tile's receivers
-  C2<R> n0[QPT], n1[QPT];
+  // the tile's kTile receivers, RT at a time in registers (each pass walks the
+  // tile's source list once)
+  for (int h = 0; h < kTile; h += RT) {
+    C2<R> a0[QPT][RT], a1[QPT][RT];
 #pragma unroll
-  for (int u = 0; u < QPT; ++u) {
-    n0[u] = n1[u] = mk<R>(0, 0);
-    if (act[u] && e0 < e1) {
-      const int sb = tsrc[e0];
-      n0[u] = S[(((int64_t)sb * 2 + 0) * K + q[u]) * ldp + c];
-      n1[u] = S[(((int64_t)sb * 2 + 1) * K + q[u]) * ldp + c];
-    }
-  }
-  for (int e = e0; e < e1; ++e) {
-    C2<R> s0[QPT], s1[QPT];
+    for (int u = 0; u < QPT; ++u)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) a0[u][r] = a1[u][r] = mk<R>(0, 0);
+    // software pipelining: the next source's pattern loads are in flight while
+    // the current one is applied to the tile's receivers
+    C2<R> n0[QPT], n1[QPT];
 #pragma unroll
     for (int u = 0; u < QPT; ++u) {
-      s0[u] = n0[u];
-      s1[u] = n1[u];
-      if (act[u] && e + 1 < e1) {
-        const int sb = tsrc[e + 1];
+      n0[u] = n1[u] = mk<R>(0, 0);
+      if (act[u] && e0 < e1) {
+        const int sb = tsrc[e0];
         n0[u] = S[(((int64_t)sb * 2 + 0) * K + q[u]) * ldp + c];
         n1[u] = S[(((int64_t)sb * 2 + 1) * K + q[u]) * ldp + c];
       }
     }
-    // the tile's translator ids for this source: uniform, one batch of scalar loads
-    const int4* of4 = reinterpret_cast<const int4*>(toff + (int64_t)e * kTile);
-    int f[kTile];
+    for (int e = e0; e < e1; ++e) {
+      C2<R> s0[QPT], s1[QPT];
 #pragma unroll
-    for (int r4 = 0; r4 < kTile / 4; ++r4) {
-      const int4 v = of4[r4];
-      f[4 * r4 + 0] = v.x;
-      f[4 * r4 + 1] = v.y;
-      f[4 * r4 + 2] = v.z;
-      f[4 * r4 + 3] = v.w;
-    }
+      for (int u = 0; u < QPT; ++u) {
+        s0[u] = n0[u];
+        s1[u] = n1[u];
+        if (act[u] && e + 1 < e1) {
+          const int sb = tsrc[e + 1];
+          n0[u] = S[(((int64_t)sb * 2 + 0) * K + q[u]) * ldp + c];
+          n1[u] = S[(((int64_t)sb * 2 + 1) * K + q[u]) * ldp + c];
+        }
+      }
+      // the translator ids of this pass's receivers for this source: uniform,
+      // one batch of scalar loads
+      const int4* of4 = reinterpret_cast<const int4*>(toff + (int64_t)e * kTile + h);
+      int f[RT];
 #pragma unroll
-    for (int r = 0; r < kTile; ++r) {
-      if (f[r] >= 0) {
+      for (int r4 = 0; r4 < RT / 4; ++r4) {
+        const int4 v = of4[r4];
+        f[4 * r4 + 0] = v.x;
+        f[4 * r4 + 1] = v.y;
+        f[4 * r4 + 2] = v.z;
+        f[4 * r4 + 3] = v.w;
+      }
 #pragma unroll
-        for (int u = 0; u < QPT; ++u) {
-          // staged rows: in range for every thread (ql clamped), zero beyond K
-          const C2<R> t = STAGE ? Ts[f[r] * qspan + u * qb + qlr]
-                                : (act[u] ? T[(int64_t)f[r] * K + q[u]] : mk<R>(0, 0));
-          a0[u][r] = cfma(a0[u][r], t, s0[u]);
-          a1[u][r] = cfma(a1[u][r], t, s1[u]);
+      for (int r = 0; r < RT; ++r) {
+        if (f[r] >= 0) {
+#pragma unroll
+          for (int u = 0; u < QPT; ++u) {
+            // staged rows: in range for every thread (ql clamped), zero beyond K
+            const C2<R> t = STAGE ? Ts[f[r] * qspan + u * qb + qlr]
+                                  : (act[u] ? T[(int64_t)f[r] * K + q[u]] : mk<R>(0, 0));
+            a0[u][r] = cfma(a0[u][r], t, s0[u]);
+            a1[u][r] = cfma(a1[u][r], t, s1[u]);
+          }
         }
       }
     }
-  }
 #pragma unroll
-  for (int u = 0; u < QPT; ++u) {
-    if (!act[u]) continue;
+    for (int u = 0; u < QPT; ++u) {
+      if (!act[u]) continue;
 #pragma unroll
-    for (int r = 0; r < kTile; ++r) {
-      const int m = tile * kTile + r;
-      if (m < nbox) {
-        C2<R>& g0 = G[(((int64_t)m * 2 + 0) * K + q[u]) * ldp + c];
-        C2<R>& g1 = G[(((int64_t)m * 2 + 1) * K + q[u]) * ldp + c];
-        if (accum) {
-          g0.x += a0[u][r].x;
-          g0.y += a0[u][r].y;
-          g1.x += a1[u][r].x;
-          g1.y += a1[u][r].y;
-        } else {
-          g0 = a0[u][r];
-          g1 = a1[u][r];
+      for (int r = 0; r < RT; ++r) {
+        const int m = tile * kTile + h + r;
+        if (m < nbox) {
+          C2<R>& g0 = G[(((int64_t)m * 2 + 0) * K + q[u]) * ldp + c];
+          C2<R>& g1 = G[(((int64_t)m * 2 + 1) * K + q[u]) * ldp + c];
+          if (accum) {
+            g0.x += a0[u][r].x;
+            g0.y += a0[u][r].y;
+            g1.x += a1[u][r].x;
+            g1.y += a1[u][r].y;
+          } else {
+            g0 = a0[u][r];
+            g1 = a1[u][r];
+          }
         }
       }
     }
@@ -1034,20 +1039,22 @@ struct Stages {
     const int qb = threads / cw;
     const int gx = (Lv.ntile + 7) / 8 * 8;              // multiple of 8 for the XCD-aware tile order
     const size_t sh2 = (size_t)Lv.n_off * qb * 2 * sizeof(CR);
-    if (sizeof(R) == 4 && cw >= 8 && sh2 <= 64 * 1024) {
-      dim3 grid(gx, (Lv.K + 2 * qb - 1) / (2 * qb), (nc + cw - 1) / cw);
-      hipLaunchKernelGGL((k_m2l<R, true, 2>), grid, dim3(threads), sh2, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off,
-                         S, G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
-      return;
-    }
+    if constexpr (sizeof(R) == 4)
+      if (cw >= 8 && sh2 <= 64 * 1024) {
+        // FP32 batched: two directions per thread share the translator ids
+        dim3 grid(gx, (Lv.K + 2 * qb - 1) / (2 * qb), (nc + cw - 1) / cw);
+        hipLaunchKernelGGL((k_m2l<R, true, 2, kTile>), grid, dim3(threads), sh2, s, tptr, tsrc, toff, (const CR*)T,
+                           Lv.n_off, S, G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
+        return;
+      }
     const size_t sh = (size_t)Lv.n_off * qb * sizeof(CR);
     const bool stage = (cw >= 8) && sh <= 64 * 1024;
     dim3 grid(gx, (Lv.K + qb - 1) / qb, (nc + cw - 1) / cw);
     if (stage)
-      hipLaunchKernelGGL((k_m2l<R, true, 1>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
+      hipLaunchKernelGGL((k_m2l<R, true, 1, kTile>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
                          G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
     else
-      hipLaunchKernelGGL((k_m2l<R, false, 1>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
+      hipLaunchKernelGGL((k_m2l<R, false, 1, kTile>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
                          G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
   }
 
