@@ -360,14 +360,19 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
       for (int r = 0; r < RT; ++r) a0[u][r] = a1[u][r] = mk<R>(0, 0);
     // software pipelining: the next source's pattern loads are in flight while
     // the current one is applied to the tile's receivers
-    C2<R> n0[QPT], n1[QPT];
+    // source patterns: a uniform per-box base plus a loop-invariant lane
+    // offset (inactive lanes read direction 0, which is always in range)
+    const int64_t bstride = (int64_t)2 * K * ldp, cstride = (int64_t)K * ldp;
+    int lo[QPT];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) {
-      n0[u] = n1[u] = mk<R>(0, 0);
-      if (act[u] && e0 < e1) {
-        const int sb = tsrc[e0];
-        n0[u] = S[(((int64_t)sb * 2 + 0) * K + q[u]) * ldp + c];
-        n1[u] = S[(((int64_t)sb * 2 + 1) * K + q[u]) * ldp + c];
+    for (int u = 0; u < QPT; ++u) lo[u] = (act[u] ? q[u] * ldp : 0) + (c < nc ? c : 0);
+    C2<R> n0[QPT], n1[QPT];
+    if (e0 < e1) {
+      const C2<R>* sp = S + tsrc[e0] * bstride;
+#pragma unroll
+      for (int u = 0; u < QPT; ++u) {
+        n0[u] = sp[lo[u]];
+        n1[u] = sp[cstride + lo[u]];
       }
     }
     for (int e = e0; e < e1; ++e) {
@@ -376,10 +381,13 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
       for (int u = 0; u < QPT; ++u) {
         s0[u] = n0[u];
         s1[u] = n1[u];
-        if (act[u] && e + 1 < e1) {
-          const int sb = tsrc[e + 1];
-          n0[u] = S[(((int64_t)sb * 2 + 0) * K + q[u]) * ldp + c];
-          n1[u] = S[(((int64_t)sb * 2 + 1) * K + q[u]) * ldp + c];
+      }
+      if (e + 1 < e1) {
+        const C2<R>* sp = S + tsrc[e + 1] * bstride;
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+          n0[u] = sp[lo[u]];
+          n1[u] = sp[cstride + lo[u]];
         }
       }
       // the translator ids of this pass's receivers for this source: uniform,
@@ -415,8 +423,9 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
       for (int r = 0; r < RT; ++r) {
         const int m = tile * kTile + h + r;
         if (m < nbox) {
-          C2<R>& g0 = G[(((int64_t)m * 2 + 0) * K + q[u]) * ldp + c];
-          C2<R>& g1 = G[(((int64_t)m * 2 + 1) * K + q[u]) * ldp + c];
+          C2<R>* gp = G + m * bstride + lo[u];
+          C2<R>& g0 = gp[0];
+          C2<R>& g1 = gp[cstride];
           if (accum) {
             g0.x += a0[u][r].x;
             g0.y += a0[u][r].y;
