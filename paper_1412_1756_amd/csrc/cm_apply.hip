@@ -1178,10 +1178,10 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     if (dual) st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l] + nc, nc, ldp, 1, pd.lev[l].dshift);
     stage_end(d, s);
   }
-  // translations and downward pass.  With the matrix-core anterpolation the
-  // parent's contribution is stored first and the translations of the level
-  // are added onto it; otherwise the translations are stored first and the
-  // anterpolation adds onto them.
+  // translations and downward pass: the translations of a level are stored,
+  // then the parent's anterpolated pattern is added onto them (the
+  // matrix-core kernel adds with one atomic per element, so the sum is still
+  // formed in a fixed order).
   bool mf_down = false;
   if constexpr (sizeof(R) == 4) {
     mf_down = !(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) && nc % 8 == 0;
@@ -1195,23 +1195,17 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     if (dual) st.m2l(l, 0, Lv.dTZ, (const CR*)d.S[l], (CR*)d.G[l] + nc, nc, ldp, 1);
     stage_end(d, s);
   };
-  if (mf_down) {
-    m2l_level(2, 0);
-    for (int l = 3; l <= lf; ++l) {
-      stage_begin(d, s, 5 + 10 * l);
-      st.anterp_mf(l - 1, (const CR*)d.G[l - 1], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, pd.lev[l - 1].shift, 0);
-      if (dual) st.anterp_mf(l - 1, (const CR*)d.G[l - 1], (CR*)d.G[l] + nc, nc, ldp, pd.lev[l - 1].dshift, 1);
-      stage_end(d, s);
-      m2l_level(l, 1);
-    }
-  } else {
-    for (int l = 2; l <= lf; ++l) m2l_level(l, 0);
-    for (int l = 2; l < lf; ++l) {
-      stage_begin(d, s, 5 + 10 * (l + 1));
+  for (int l = 2; l <= lf; ++l) m2l_level(l, 0);
+  for (int l = 2; l < lf; ++l) {
+    stage_begin(d, s, 5 + 10 * (l + 1));
+    if (mf_down) {
+      st.anterp_mf(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift, 1);
+      if (dual) st.anterp_mf(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift, 1);
+    } else {
       st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift);
       if (dual) st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift);
-      stage_end(d, s);
     }
+    stage_end(d, s);
   }
   stage_begin(d, s, 6);
   if (dual) {

@@ -46,10 +46,10 @@ __device__ __forceinline__ void load_rows(float (&v)[kRG][kMK], const float* bas
   for (int r = 0; r < kRG; ++r) {
     const float* row = base + (int64_t)min(r0 + r, nrows - 1) * rstride;
 #pragma unroll
-    for (int k4 = 0; k4 < kMK; k4 += 4)
-      if (k4 < nk) {
+    for (int k2 = 0; k2 < kMK; k2 += 2)
+      if (k2 < nk) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[r][k4 + i] = row[off[k4 + i]];
+        for (int i = 0; i < 2; ++i) v[r][k2 + i] = row[off[k2 + i]];
       }
   }
 }
@@ -119,12 +119,12 @@ __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc,
 #pragma unroll
     for (int r = 0; r < kRG; ++r) d[r] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k4 = 0; k4 < kMK; k4 += 4)
-      if (k4 < nk) {
+    for (int k2 = 0; k2 < kMK; k2 += 2)
+      if (k2 < nk) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int r = 0; r < kRG; ++r) d[r] = mma(pa[k4 + i], v[r][k4 + i], d[r]);
+          for (int r = 0; r < kRG; ++r) d[r] = mma(pa[k2 + i], v[r][k2 + i], d[r]);
       }
 #pragma unroll
     for (int r = 0; r < kRG; ++r)
@@ -289,15 +289,15 @@ __global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp,
 #pragma unroll
     for (int r = 0; r < kRG; ++r) d[r] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k4 = 0; k4 < kMK; k4 += 4)
-      if (k4 < nk) {
+    for (int k2 = 0; k2 < kMK; k2 += 2)
+      if (k2 < nk) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int r = 0; r < kRG; ++r) {
-            const float2 z = Z[min(r0 + r, ntp - 1) * kz + (k4 + i) * 4 + g];
-            const float x = v[r][k4 + i];
-            d[r] = mma(pa[k4 + i], fmaf(z.x, x, sg * z.y * pair_swap(x)), d[r]);
+            const float2 z = Z[min(r0 + r, ntp - 1) * kz + (k2 + i) * 4 + g];
+            const float x = v[r][k2 + i];
+            d[r] = mma(pa[k2 + i], fmaf(z.x, x, sg * z.y * pair_swap(x)), d[r]);
           }
       }
 #pragma unroll

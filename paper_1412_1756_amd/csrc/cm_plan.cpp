@@ -132,16 +132,16 @@ static void parallel_for(int64_t n, F fn) {
 namespace {
 using RowList = std::vector<std::vector<std::pair<int32_t, double>>>;   // 16 output rows: (input key, weight)
 
-// Union of the inputs of 16 output rows, four per K step (by4: the step count
-// rounded up to a multiple of four); A[k][16 g + r] is the weight of input
+// Union of the inputs of 16 output rows, four per K step (by2: the step count
+// rounded up to an even number); A[k][16 g + r] is the weight of input
 // key[4k + g] in row r (unused lanes point at a valid input with weight 0).
-int gather_steps(const RowList& rows, std::vector<int32_t>& key, std::vector<double>& A, bool by4) {
+int gather_steps(const RowList& rows, std::vector<int32_t>& key, std::vector<double>& A, bool by2) {
   std::vector<int32_t> u;
   for (auto& r : rows)
     for (auto& e : r) u.push_back(e.first);
   std::sort(u.begin(), u.end());
   u.erase(std::unique(u.begin(), u.end()), u.end());
-  const int nk = by4 ? (int)(u.size() + 15) / 16 * 4 : (int)(u.size() + 3) / 4;
+  const int nk = by2 ? (int)(u.size() + 7) / 8 * 2 : (int)(u.size() + 3) / 4;
   key.assign((size_t)nk * 4, u.empty() ? 0 : u[0]);
   for (size_t i = 0; i < u.size(); ++i) key[i] = u[i];
   A.assign((size_t)nk * 64, 0.0);
