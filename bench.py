@@ -1,7 +1,9 @@
 """Benchmark: MLFMA Z.x matvecs/s at N = 122,880 (PEC sphere, radius 4
-wavelengths, 6-level tree) on one MI355X -- FP32 batched (far field in complex
-FP32, near field FP64) against FP64 single-vector, each with its relative
-2-norm error against the CPU FP64 oracle on sampled rows.
+wavelengths, 6-level tree) on one MI355X -- FP32 batched (complex FP32
+throughout: near field from an FP32 copy of the FP64-filled near-field values,
+leaf and interpolation products on the matrix cores) against FP64
+single-vector, each with its relative 2-norm error against the CPU FP64
+oracle on sampled rows.
 
 One "step" is one apply of Z to a block of `--ncols` right-hand sides (the
 whole hot path: near-field product, aggregation, interpolation, translation,
@@ -54,8 +56,9 @@ def stage_model(st, nc, cb):
     nleaf = lev[lf]["nbox"]
     p = st["interp_p"]
     m = {}
-    m["near"] = dict(bytes=st["nnz_near"] * 16 + st["near_cols_total"] * 4 + 2 * N * nc * cb,
-                     flops=8.0 * st["nnz_near"] * nc, fp="f64")
+    # near-field values: FP32 copies on the FP32 path, FP64 otherwise
+    m["near"] = dict(bytes=st["nnz_near"] * cb + st["near_cols_total"] * 4 + 2 * N * nc * cb,
+                     flops=8.0 * st["nnz_near"] * nc, fp="f32" if cb == 8 else "f64")
     m["aggregate"] = dict(bytes=N * 2 * Kf * cb + N * nc * cb + nleaf * 2 * Kf * nc * cb,
                           flops=8.0 * N * 2 * Kf * nc, fp="f32" if cb == 8 else "f64")
     m["disagg"] = dict(bytes=N * 2 * Kf * cb + nleaf * 2 * Kf * nc * cb + 2 * N * nc * cb,
@@ -100,8 +103,10 @@ def measured_traffic(stage, path_tag, cfg):
     rec = json.load(open(f)).get(f"{stage}/{path_tag}")
     if not rec or rec.get("config") != cfg:
         return None
-    src = open(os.path.join(ROOT, "paper_1412_1756_amd", "csrc", "cm_apply.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    h = hashlib.sha256()
+    for f in ("cm_apply.hip", "cm_mfma.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1412_1756_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
         return None
     return rec["read_bytes"] + rec["write_bytes"]
 
@@ -181,7 +186,7 @@ def main():
         "unit": "matvecs/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms32,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 far field / c128 near field",
+        "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": name, "N": N, "nlv": a.nlv, "d0": a.d0, "interp_p": a.p, "ncols": a.ncols,
                    "k": k, "mesh": "icosphere nsub 6, radius 4 wavelengths"},

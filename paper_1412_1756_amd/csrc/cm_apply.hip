@@ -1151,7 +1151,7 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   stage_begin(d, s, 1);
   bool near_done = false;
   if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES)) {
-    if constexpr (sizeof(R) == 4)
+    if (sizeof(R) == 4 && (P.opt.flags & CM_FLAG_NEAR_FP32))
       near_done = mf_near32(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off, dual ? d.dZn32 : d.Zn32,
                             (const float2*)xi, (float2*)yi, d.nleaf, d.max_near_cols, nc, kind, s);
     else

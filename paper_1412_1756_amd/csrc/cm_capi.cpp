@@ -261,10 +261,12 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   chk(hipGetLastError(), "leaf pattern launch");
   launch_near_fill(P.k, P.opt.eta, d, d.nleaf, s);
   chk(hipGetLastError(), "near fill launch");
-  // FP32 copies for the FP32 matrix-core near field
-  d.Zn32 = (float2*)dmalloc(d, (size_t)std::max<int64_t>(1, d.nnz) * sizeof(float2));
-  blas_to_c64(d.Zn, d.Zn32, d.nnz, s);
-  if (deriv) {
+  // FP32 copies for the FP32 near-field product (CM_FLAG_NEAR_FP32)
+  if (P.opt.flags & CM_FLAG_NEAR_FP32) {
+    d.Zn32 = (float2*)dmalloc(d, (size_t)std::max<int64_t>(1, d.nnz) * sizeof(float2));
+    blas_to_c64(d.Zn, d.Zn32, d.nnz, s);
+  }
+  if (deriv && (P.opt.flags & CM_FLAG_NEAR_FP32)) {
     d.dZn32 = (float2*)dmalloc(d, (size_t)std::max<int64_t>(1, d.nnz) * sizeof(float2));
     blas_to_c64(d.dZn, d.dZn32, d.nnz, s);
   }

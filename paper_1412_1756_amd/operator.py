@@ -18,7 +18,7 @@ class Operator:
     """
 
     def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
-                 deriv=False, check_coverage=False, matrix_cores=True, stream=None):
+                 deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, stream=None):
         L = lib()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -32,7 +32,8 @@ class Operator:
         o.max_cols = int(max_cols)
         o.flags = ((_lib.CM_FLAG_HOST_ONLY if host_only else 0) | (_lib.CM_FLAG_DERIV if deriv else 0)
                    | (_lib.CM_FLAG_CHECK if check_coverage else 0)
-                   | (0 if matrix_cores else _lib.CM_FLAG_NO_MATRIX_CORES))
+                   | (0 if matrix_cores else _lib.CM_FLAG_NO_MATRIX_CORES)
+                   | (_lib.CM_FLAG_NEAR_FP32 if near_fp32 else 0))
         kk = np.array([float(k)], dtype=np.float64)
         h = C.c_void_p()
         s = self._stream_ptr(stream) if not host_only else None

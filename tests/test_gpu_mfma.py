@@ -113,6 +113,28 @@ def test_mfma_dzdk_matches_valu(torch_cuda, sphere2):
     assert e1 < 1e-3
 
 
+def test_near_fp32_option(torch_cuda, sphere2, ops):
+    """CM_FLAG_NEAR_FP32: the near-field product from an FP32 copy of the
+    values with FP32 accumulation; it may move the FP32 apply by about the
+    FP32 rounding of the near part (bound 1e-5 relative), and must keep the
+    FP32 accuracy against FP64 (within 25%)."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = sphere2
+    mf, _ = ops
+    nf = Operator(V, F, K0, nlv=5, max_cols=32, near_fp32=True, **ACC32)
+    Xh = workloads.cn01_block(mf.N, 16, 77)
+    X = torch.tensor(Xh, dtype=torch.complex64, device="cuda")
+    for opname in ("Z", "R", "X"):
+        y1 = mf.apply(X, op=opname).cpu().numpy()
+        y2 = nf.apply(X, op=opname).cpu().numpy()
+        y3 = mf.apply(torch.tensor(Xh, dtype=torch.complex128, device="cuda"), op=opname).cpu().numpy()
+        e, e1, e2 = colerr(y2, y1), colerr(y1, y3), colerr(y2, y3)
+        print(f"near fp32 op={opname}: vs c128 near {e:.2e}; vs fp64 {e2:.2e} (c128 near {e1:.2e})", flush=True)
+        assert e < 1e-5
+        assert e2 <= 1.25 * e1 + 2e-6
+
+
 def test_mfma_repeat_is_deterministic(torch_cuda, ops):
     torch = torch_cuda
     mf, _ = ops
