@@ -1,9 +1,8 @@
 """Benchmark: MLFMA Z.x matvecs/s at N = 122,880 (PEC sphere, radius 4
-wavelengths, 6-level tree) on one MI355X -- FP32 batched (complex FP32
-throughout: near field from an FP32 copy of the FP64-filled near-field values,
-leaf and interpolation products on the matrix cores) against FP64
-single-vector, each with its relative 2-norm error against the CPU FP64
-oracle on sampled rows.
+wavelengths, 6-level tree) on one MI355X -- FP32 batched (complex64 far
+field, complex128 near field; leaf, near-field and interpolation products on
+the matrix cores) against FP64 single-vector, each with its relative 2-norm
+error against the CPU FP64 oracle on sampled rows.
 
 One "step" is one apply of Z to a block of `--ncols` right-hand sides (the
 whole hot path: near-field product, aggregation, interpolation, translation,
@@ -56,9 +55,9 @@ def stage_model(st, nc, cb):
     nleaf = lev[lf]["nbox"]
     p = st["interp_p"]
     m = {}
-    # near-field values: FP32 copies on the FP32 path, FP64 otherwise
-    m["near"] = dict(bytes=st["nnz_near"] * cb + st["near_cols_total"] * 4 + 2 * N * nc * cb,
-                     flops=8.0 * st["nnz_near"] * nc, fp="f32" if cb == 8 else "f64")
+    # near-field values in complex128 on both paths (FP64 accumulation)
+    m["near"] = dict(bytes=st["nnz_near"] * 16 + st["near_cols_total"] * 4 + 2 * N * nc * cb,
+                     flops=8.0 * st["nnz_near"] * nc, fp="f64")
     m["aggregate"] = dict(bytes=N * 2 * Kf * cb + N * nc * cb + nleaf * 2 * Kf * nc * cb,
                           flops=8.0 * N * 2 * Kf * nc, fp="f32" if cb == 8 else "f64")
     m["disagg"] = dict(bytes=N * 2 * Kf * cb + nleaf * 2 * Kf * nc * cb + 2 * N * nc * cb,
@@ -186,7 +185,7 @@ def main():
         "unit": "matvecs/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms32,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": "c64 far field / c128 near field",
         "data": "synthetic",
         "config": {"workload": name, "N": N, "nlv": a.nlv, "d0": a.d0, "interp_p": a.p, "ncols": a.ncols,
                    "k": k, "mesh": "icosphere nsub 6, radius 4 wavelengths"},
