@@ -88,6 +88,20 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
                                   complex128 values with FP64 accumulation:
                                   faster, about 1e-6 relative on the near
                                   part; costs 8 B per near-field entry       */
+#define CM_FLAG_WIDE_NEAR 32u  /* two-box buffer at the two finest levels: the
+                                  near field takes leaf boxes up to Chebyshev
+                                  distance 2, and the translation lists of the
+                                  leaf level and the level above start at
+                                  distance 3.  RWG supports reach past their
+                                  leaf box, so at distance 2 the addition
+                                  theorem of eq. (9) is at or past its
+                                  convergence limit there and the truncated
+                                  translator grows fast with L; this flag
+                                  removes both (about 10x smaller error at the
+                                  same d0, p) for about 2.8x the near-field
+                                  entries and more leaf translations.  The
+                                  SAI candidate pattern is the stored near
+                                  field, so it widens with it.              */
 
 typedef struct {
   int32_t nlv;       /* number of octree levels including level 0 (>= 3)        */
@@ -105,10 +119,14 @@ void cm_default_opts(cm_opts* o);
 
 /* Build a handle.  xyz: host, n_vert x 3 float64 (wavelength units are the
    caller's; k is in the same units).  tri: host, n_tri x 3 int32 vertex
-   indices.  k: host array of n_k wavenumbers (n_k = 1 in this version).
-   Blocks until all device set-up (near-field fill with singularity
-   extraction, leaf radiation patterns, translators) is complete.  The caller
-   keeps ownership of xyz/tri/k (copied).  On failure *out is NULL. */
+   indices.  k: host array of n_k >= 1 wavenumbers (a sweep): the same tree
+   and lists for all, and per wavenumber its own truncation (eq. (30)),
+   sampling, translators, leaf patterns, shift phases and near field, so the
+   set-up work and device memory grow n_k-fold.  cm_apply picks a wavenumber
+   per column (k_index); every other entry point works at k[0].  Blocks until
+   all device set-up (near-field fill with singularity extraction, leaf
+   radiation patterns, translators) is complete.  The caller keeps ownership
+   of xyz/tri/k (copied).  On failure *out is NULL. */
 cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
                     const double* k, int32_t n_k, const cm_opts* o, void* hip_stream,
                     cm_handle** out);
@@ -123,8 +141,12 @@ cm_status cm_num_unknowns(const cm_handle* h, int64_t* n);
    vertex), tri_pm (N x 2: T+, T-).  Host arrays, caller-allocated. */
 cm_status cm_rwg_table(const cm_handle* h, int32_t* edge_v, int32_t* tri_pm);
 
-/* y = op(x) on ncols columns (1 <= ncols <= max_cols).  k_index must be NULL
-   (all columns at k[0]).  Asynchronous on hip_stream. */
+/* y = op(x) on ncols columns (1 <= ncols <= max_cols).  k_index: NULL (all
+   columns at k[0]) or a host array of ncols indices into the handle's k
+   array, column j being applied at k[k_index[j]] (columns sharing a
+   wavenumber are gathered into one batched apply; a batch at a single
+   wavenumber runs in place).  Asynchronous on hip_stream; CM_E_BADARG for an
+   index outside [0, n_k). */
 cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols,
                    const int32_t* k_index, cm_dtype dt, void* hip_stream);
 

@@ -91,7 +91,44 @@ __global__ void __launch_bounds__(256) k_to_c128(const float2* __restrict__ x, d
   if (i < N) y[i] = make_double2((double)x[i].x, (double)x[i].y);
 }
 
+// xs[i][j] = x[i][cols[j]] (xs dense, ld = cols.n); ys -> y the other way
+template <typename C>
+__global__ void __launch_bounds__(256) k_gather_cols(const C* __restrict__ x, int64_t ld, ColList cols,
+                                                     C* __restrict__ xs, int64_t N) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * cols.n) return;
+  const int64_t i = e / cols.n;
+  const int j = (int)(e - i * cols.n);
+  xs[e] = x[i * ld + cols.c[j]];
+}
+template <typename C>
+__global__ void __launch_bounds__(256) k_scatter_cols(const C* __restrict__ ys, ColList cols, C* __restrict__ y,
+                                                      int64_t ld, int64_t N) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * cols.n) return;
+  const int64_t i = e / cols.n;
+  const int j = (int)(e - i * cols.n);
+  y[i * ld + cols.c[j]] = ys[e];
+}
+
 static inline dim3 g1(int64_t N) { return dim3((unsigned)((N + 255) / 256)); }
+
+void blas_gather_cols(const void* x, int64_t ld, ColList cols, void* xs, int64_t N, bool fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_gather_cols<double2>, g1(N * cols.n), dim3(256), 0, s, (const double2*)x, ld, cols,
+                       (double2*)xs, N);
+  else
+    hipLaunchKernelGGL(k_gather_cols<float2>, g1(N * cols.n), dim3(256), 0, s, (const float2*)x, ld, cols,
+                       (float2*)xs, N);
+}
+void blas_scatter_cols(const void* ys, ColList cols, void* y, int64_t ld, int64_t N, bool fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_scatter_cols<double2>, g1(N * cols.n), dim3(256), 0, s, (const double2*)ys, cols,
+                       (double2*)y, ld, N);
+  else
+    hipLaunchKernelGGL(k_scatter_cols<float2>, g1(N * cols.n), dim3(256), 0, s, (const float2*)ys, cols,
+                       (float2*)y, ld, N);
+}
 
 void blas_multidot(const double2* V, int64_t ldv, const double2* w, int64_t N, int nk, double2* h, hipStream_t s) {
   if (nk > 0) hipLaunchKernelGGL(k_multidot, dim3(nk), dim3(256), 0, s, V, ldv, w, N, h);

@@ -340,16 +340,41 @@ void cm_default_opts(cm_opts* o) {
   o->max_cols = 32;
 }
 
+static void destroy_handle(cm_handle* h) {
+  if (!h) return;
+  for (cm_handle* t : h->sub) destroy_handle(t);
+  h->sub.clear();
+  if (h->xs) (void)hipFree(h->xs);
+  if (h->ys) (void)hipFree(h->ys);
+  cm::dev_free(h->dev);
+  delete h;
+}
+
+static cm_handle* build_handle(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri, double k,
+                               const cm::Opts& op, uint32_t flags, hipStream_t s) {
+  std::unique_ptr<cm_handle> h(new cm_handle());
+  h->plan.build(xyz, n_vert, tri, n_tri, k, op);
+  if (!(flags & CM_FLAG_HOST_ONLY)) {
+    try {
+      cm::dev_build(h->dev, h->plan, s);
+    } catch (...) {
+      cm::dev_free(h->dev);
+      throw;
+    }
+    h->has_dev = true;
+  }
+  return h.release();
+}
+
 cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri, const double* k,
                     int32_t n_k, const cm_opts* o, void* hip_stream, cm_handle** out) {
   g_err.clear();
   if (out) *out = nullptr;
   if (!xyz || !tri || !k || !o || !out) return fail(CM_E_BADARG, "null argument");
-  if (n_k != 1) return fail(CM_E_UNSUPPORTED, "exactly one wavenumber per handle is supported");
+  if (n_k < 1 || n_k > 64) return fail(CM_E_BADARG, "n_k out of range [1, 64]");
   if (n_vert < 3 || n_tri < 2 || n_vert > (1LL << 31) - 1 || n_tri > (1LL << 31) - 1)
     return fail(CM_E_BADARG, "mesh size out of range");
   CM_TRY({
-    std::unique_ptr<cm_handle> h(new cm_handle());
     cm::Opts op;
     op.nlv = o->nlv;
     op.d0 = o->d0;
@@ -357,26 +382,25 @@ cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64
     op.eta = (o->eta > 0) ? o->eta : 376.730313668;
     op.flags = o->flags;
     op.max_cols = o->max_cols;
-    h->plan.build(xyz, n_vert, tri, n_tri, k[0], op);
-    if (!(o->flags & CM_FLAG_HOST_ONLY)) {
-      try {
-        cm::dev_build(h->dev, h->plan, (hipStream_t)hip_stream);
-      } catch (...) {
-        cm::dev_free(h->dev);
-        throw;
+    cm_handle* h = build_handle(xyz, n_vert, tri, n_tri, k[0], op, o->flags, (hipStream_t)hip_stream);
+    try {
+      for (int i = 1; i < n_k; ++i)
+        h->sub.push_back(build_handle(xyz, n_vert, tri, n_tri, k[i], op, o->flags, (hipStream_t)hip_stream));
+      if (n_k > 1 && h->has_dev) {
+        const size_t b = (size_t)h->dev.N * h->dev.max_cols * 16;
+        if (hipMalloc(&h->xs, b) != hipSuccess || hipMalloc(&h->ys, b) != hipSuccess)
+          throw cm::Error(CM_E_OOM, "sweep staging buffers");
       }
-      h->has_dev = true;
+    } catch (...) {
+      destroy_handle(h);
+      throw;
     }
-    *out = h.release();
+    *out = h;
     return CM_OK;
   })
 }
 
-void cm_destroy(cm_handle* h) {
-  if (!h) return;
-  cm::dev_free(h->dev);
-  delete h;
-}
+void cm_destroy(cm_handle* h) { destroy_handle(h); }
 
 cm_status cm_num_unknowns(const cm_handle* h, int64_t* n) {
   if (!h || !n) return fail(CM_E_BADARG, "null argument");
@@ -409,11 +433,39 @@ cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, i
   cm_status st = check_vec_args(h, x, y, ld, ncols, dt);
   if (st != CM_OK) return st;
   if ((int)op < 0 || (int)op > 4) return fail(CM_E_BADARG, "bad op");
-  if (k_index) return fail(CM_E_UNSUPPORTED, "per-column wavenumbers are not supported by this build");
   if (op == CM_OP_DZDK && !(h->plan.opt.flags & CM_FLAG_DERIV))
     return fail(CM_E_NOT_BUILT, "dZ/dk needs CM_FLAG_DERIV at create");
+  const int nk = 1 + (int)h->sub.size();
+  if (k_index)
+    for (int j = 0; j < ncols; ++j)
+      if (k_index[j] < 0 || k_index[j] >= nk) return fail(CM_E_BADARG, "k_index out of range [0, n_k)");
+  const bool fp64 = dt == CM_C128;
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto at = [&](int kk) { return kk == 0 ? h : h->sub[kk - 1]; };
   CM_TRY({
-    cm::dev_apply(h->dev, h->plan, (int)op, x, y, ld, ncols, dt == CM_C128, (hipStream_t)hip_stream);
+    bool one = true;   // every column at the same wavenumber: in place
+    for (int j = 1; k_index && j < ncols; ++j) one = one && k_index[j] == k_index[0];
+    if (one) {
+      cm_handle* t = at(k_index ? k_index[0] : 0);
+      cm::dev_apply(t->dev, t->plan, (int)op, x, y, ld, ncols, fp64, s);
+      return CM_OK;
+    }
+    // gather the columns of each wavenumber, apply, scatter back
+    for (int kk = 0; kk < nk; ++kk) {
+      cm::ColList cl;
+      cl.n = 0;
+      for (int j = 0; j <= ncols; ++j) {
+        if (j < ncols && k_index[j] == kk) cl.c[cl.n++] = j;
+        if (cl.n == 64 || (j == ncols && cl.n > 0)) {
+          cm_handle* t = at(kk);
+          cm::blas_gather_cols(x, ld, cl, h->xs, h->dev.N, fp64, s);
+          cm::dev_apply(t->dev, t->plan, (int)op, h->xs, h->ys, cl.n, cl.n, fp64, s);
+          cm::blas_scatter_cols(h->ys, cl, y, ld, h->dev.N, fp64, s);
+          cl.n = 0;
+        }
+      }
+    }
+    if (hipGetLastError() != hipSuccess) throw cm::Error(CM_E_HIP, "sweep gather/scatter launch");
     return CM_OK;
   })
 }

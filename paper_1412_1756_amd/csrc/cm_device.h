@@ -152,9 +152,22 @@ void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, in
 
 }  // namespace cm
 
-// the opaque handle of the C ABI
+// gather / scatter of up to 64 columns (by index) of an N x ld complex array
+namespace cm {
+struct ColList {
+  int n;
+  int c[64];
+};
+void blas_gather_cols(const void* x, int64_t ld, ColList cols, void* xs, int64_t N, bool fp64, hipStream_t s);
+void blas_scatter_cols(const void* ys, ColList cols, void* y, int64_t ld, int64_t N, bool fp64, hipStream_t s);
+}  // namespace cm
+
+// the opaque handle of the C ABI; a wavenumber sweep keeps one handle per
+// further wavenumber in `sub` (sub[i] at k[i + 1]) and column staging buffers
 struct cm_handle {
   cm::Plan plan;
   cm::Dev dev;
   bool has_dev = false;
+  std::vector<cm_handle*> sub;
+  void *xs = nullptr, *ys = nullptr;   // N x max_cols complex128 each (sweeps only)
 };

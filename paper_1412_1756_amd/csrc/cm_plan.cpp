@@ -423,6 +423,10 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
       Lv.child_ptr[Lv.nbox] = lev[l + 1].nbox;
     }
   }
+  // Near radius (Chebyshev distance, in boxes) per level: 1, or 2 at the two
+  // finest levels with the wide-near option (flag 32).
+  const bool wide = (o.flags & 32u) != 0;
+  auto near_radius = [&](int l) { return (wide && l >= lf - 1) ? 2 : 1; };
   auto box_lookup = [&](int l, int x, int y, int z) -> int {
     int ns = 1 << l;
     if (x < 0 || y < 0 || z < 0 || x >= ns || y >= ns || z >= ns) return -1;
@@ -433,11 +437,12 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
   {
     const Level& Lf = lev[lf];
     near_ptr.assign(Lf.nbox + 1, 0);
+    const int nr = near_radius(lf);
     for (int b = 0; b < Lf.nbox; ++b) {
       std::vector<int> nb;
-      for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dz = -1; dz <= 1; ++dz) {
+      for (int dx = -nr; dx <= nr; ++dx)
+        for (int dy = -nr; dy <= nr; ++dy)
+          for (int dz = -nr; dz <= nr; ++dz) {
             int q = box_lookup(lf, Lf.ijk[3 * b] + dx, Lf.ijk[3 * b + 1] + dy, Lf.ijk[3 * b + 2] + dz);
             if (q >= 0) nb.push_back(q);
           }
@@ -521,19 +526,22 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     for (int m = 0; m < Lv.nbox; ++m) {
       std::vector<std::pair<int, int>> lst, lstR;
       int P = Lv.parent[m];
-      for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dz = -1; dz <= 1; ++dz) {
+      // parents within the near radius of the level above; children beyond
+      // this level's near radius are translated here
+      const int pr = near_radius(l - 1), dfar = near_radius(l) + 1;
+      for (int dx = -pr; dx <= pr; ++dx)
+        for (int dy = -pr; dy <= pr; ++dy)
+          for (int dz = -pr; dz <= pr; ++dz) {
             int Q = box_lookup(l - 1, Pl.ijk[3 * P] + dx, Pl.ijk[3 * P + 1] + dy, Pl.ijk[3 * P + 2] + dz);
             if (Q < 0) continue;
             for (int c = Pl.child_ptr[Q]; c < Pl.child_ptr[Q + 1]; ++c) {
               int dd = cheb(&Lv.ijk[3 * m], &Lv.ijk[3 * c]);
               int off = off_id(Lv.ijk[3 * m] - Lv.ijk[3 * c], Lv.ijk[3 * m + 1] - Lv.ijk[3 * c + 1],
                                Lv.ijk[3 * m + 2] - Lv.ijk[3 * c + 2]);
-              if (dd >= 2) {
+              if (dd >= dfar) {
                 lst.push_back({c, off});
                 lstR.push_back({c, off});
-              } else if (l == lf && dd == 1) {
+              } else if (l == lf && dd >= 1) {
                 lstR.push_back({c, off});   // R translates neighbouring leaf boxes too
               }
             }
@@ -612,7 +620,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     if (want_d) dTZ[l].assign(nu * K, cplx(0));
     parallel_for((int64_t)offs.size(), [&](int64_t oi) {
       int f = offs[oi];
-      int dx = f / 49 - 3, dy = (f / 7) % 7 - 3, dz = f % 7 - 3;
+      int dx = f / (kOffW * kOffW) - kOffH, dy = (f / kOffW) % kOffW - kOffH, dz = f % kOffW - kOffH;
       double X[3] = {dx * Lv.a, dy * Lv.a, dz * Lv.a};
       double r = std::sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
       std::vector<double> jl, yl;
@@ -837,7 +845,7 @@ std::string Plan::stats_json() const {
   std::ostringstream s;
   s.precision(17);
   s << "{\"N\": " << rwg.N << ", \"n_tri\": " << nt << ", \"k\": " << k << ", \"nlv\": " << nlv
-    << ", \"d0\": " << opt.d0 << ", \"interp_p\": " << opt.p << ", \"root_side\": " << side
+    << ", \"d0\": " << opt.d0 << ", \"interp_p\": " << opt.p << ", \"wide_near\": " << ((opt.flags & 32u) ? 1 : 0) << ", \"root_side\": " << side
     << ", \"nnz_near\": " << nnz << ", \"near_cols_total\": " << bcol.size()
     << ", \"n_leaf\": " << lev[lf].nbox << ", \"levels\": [";
   for (int l = 0; l <= lf; ++l) {

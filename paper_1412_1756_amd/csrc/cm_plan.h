@@ -94,9 +94,11 @@ struct Opts {
   int max_cols = 32;
 };
 
-// Offsets between boxes at one level are coded as (dx+3)*49 + (dy+3)*7 + (dz+3).
-constexpr int kNoff = 343;
-inline int off_id(int dx, int dy, int dz) { return (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3); }
+// Offsets between boxes at one level (each component in -5..5, enough for
+// parents within two boxes of each other) are coded as
+// (dx+5)*121 + (dy+5)*11 + (dz+5).
+constexpr int kOffH = 5, kOffW = 2 * kOffH + 1, kNoff = kOffW * kOffW * kOffW;
+inline int off_id(int dx, int dy, int dz) { return ((dx + kOffH) * kOffW + (dy + kOffH)) * kOffW + (dz + kOffH); }
 
 struct Plan {
   Opts opt;

@@ -14,11 +14,15 @@ class Operator:
     Parameters mirror ``cm_opts``: nlv (levels including level 0), d0 (digits
     of the truncation rule, eq. (30)), interp_p (local Lagrange points),
     max_cols (largest batch).  host_only=True builds only the host plan (no
-    GPU needed); deriv=True also builds dZ/dk tables.
+    GPU needed); deriv=True also builds dZ/dk tables; wide_near=True selects
+    the two-box buffer at the two finest levels (CM_FLAG_WIDE_NEAR).  k may
+    be a sequence of wavenumbers (a sweep; apply's k_index picks one per
+    column).
     """
 
     def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
-                 deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, stream=None):
+                 deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, wide_near=False,
+                 stream=None):
         L = lib()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -33,15 +37,17 @@ class Operator:
         o.flags = ((_lib.CM_FLAG_HOST_ONLY if host_only else 0) | (_lib.CM_FLAG_DERIV if deriv else 0)
                    | (_lib.CM_FLAG_CHECK if check_coverage else 0)
                    | (0 if matrix_cores else _lib.CM_FLAG_NO_MATRIX_CORES)
-                   | (_lib.CM_FLAG_NEAR_FP32 if near_fp32 else 0))
-        kk = np.array([float(k)], dtype=np.float64)
+                   | (_lib.CM_FLAG_NEAR_FP32 if near_fp32 else 0)
+                   | (_lib.CM_FLAG_WIDE_NEAR if wide_near else 0))
+        kk = np.atleast_1d(np.asarray(k, dtype=np.float64)).copy()
         h = C.c_void_p()
         s = self._stream_ptr(stream) if not host_only else None
-        st = L.cm_create(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], kk.ctypes.data, 1, C.byref(o), s,
+        st = L.cm_create(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], kk.ctypes.data, len(kk), C.byref(o), s,
                          C.byref(h))
         check(st)
         self._h = h
-        self.k = float(k)
+        self.ks = [float(v) for v in kk]   # the sweep's wavenumbers (k_index selects one per column)
+        self.k = self.ks[0]
         self.host_only = host_only
         self.max_cols = int(max_cols)
         n = C.c_int64()
@@ -127,11 +133,18 @@ class Operator:
         dt = _lib.CM_C128 if X.dtype == torch.complex128 else _lib.CM_C64
         return X, out, dt, squeeze
 
-    def apply(self, x, op="Z", out=None, stream=None):
-        """y = op(x) for x of shape (N,) or (N, ncols) on the GPU."""
+    def apply(self, x, op="Z", out=None, stream=None, k_index=None):
+        """y = op(x) for x of shape (N,) or (N, ncols) on the GPU; k_index: one
+        index into the handle's wavenumbers per column (None: all at k[0])."""
         X, Y, dt, squeeze = self._vec_args(x, out)
+        ki = None
+        if k_index is not None:
+            ki = np.ascontiguousarray(np.asarray(k_index, dtype=np.int32).reshape(-1))
+            if ki.size != X.shape[1]:
+                raise ValueError("k_index needs one entry per column")
         st = lib().cm_apply(self._h, _lib.OPS[op], C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
-                            X.stride(0), X.shape[1], None, dt, self._stream_ptr(stream))
+                            X.stride(0), X.shape[1], None if ki is None else C.c_void_p(ki.ctypes.data),
+                            dt, self._stream_ptr(stream))
         check(st)
         return Y.reshape(-1) if squeeze else Y
 

@@ -157,8 +157,10 @@ def test_plate_small_leaf_error_is_bounded(torch_cuda):
     assert e < 1e-3
 
 
-def test_sphere_r1_sampled_rows(torch_cuda):
-    """7,680 unknowns, 4 levels: sampled oracle rows."""
+@pytest.mark.parametrize("wide", [False, True])
+def test_sphere_r1_sampled_rows(torch_cuda, wide):
+    """7,680 unknowns, 4 levels: sampled oracle rows; with and without the
+    two-box buffer at the two finest levels."""
     torch = torch_cuda
     from oracle import efie
     V, F = workloads.icosphere(4, 1.0)
@@ -167,33 +169,37 @@ def test_sphere_r1_sampled_rows(torch_cuda):
     Zr = efie.rows_Z(V, F, K0, rows)
     x = workloads.cn01(N, 0)
     for acc, dt, tol in ((ACC64, torch.complex128, TOL64), (ACC32, torch.complex64, TOL32)):
-        op = _op(V, F, 4, acc, max_cols=1)
+        op = _op(V, F, 4, acc, max_cols=1, wide_near=wide)
         y = op.apply(torch.tensor(x, dtype=dt, device="cuda")).cpu().numpy()
         e = relerr(y[rows], Zr @ x)
-        print(f"r1 nlv4 {dt}: {e:.3e}", flush=True)
+        print(f"r1 nlv4 wide={wide} {dt}: {e:.3e}", flush=True)
         assert e < tol
 
 
 def test_config2_sampled_rows(torch_cuda):
-    """N = 122,880, 6 levels, at the benchmark's launch configuration
-    (32-column FP32 batch and FP64 single vector), on sampled oracle rows."""
+    """N = 122,880, 6 levels, at the benchmark's launch configurations: the
+    FP64 single vector (d0 4, p 10, two-box buffer at the two finest levels)
+    and the 32-column FP32 batch (d0 4.5, p 10), on 12 sampled oracle rows
+    (FP32: four of the batch's columns)."""
     torch = torch_cuda
     from oracle import efie
     V, F = workloads.icosphere(6, 4.0)
     N = 122880
-    rows = np.sort(np.random.default_rng(2).choice(N, 6, replace=False))
+    rows = np.sort(np.random.default_rng(2).choice(N, 12, replace=False))
     Zr = efie.rows_Z(V, F, K0, rows)
     x = workloads.cn01(N, 0)
     ref = Zr @ x
-    op = _op(V, F, 6, ACC64, max_cols=1)
+    op = _op(V, F, 6, dict(d0=4.0, interp_p=10), max_cols=1, wide_near=True)
     y = op.apply(torch.tensor(x, dtype=torch.complex128, device="cuda")).cpu().numpy()
     e64 = relerr(y[rows], ref)
     del op
-    op = _op(V, F, 6, ACC32, max_cols=32)
-    X = torch.tensor(workloads.cn01_block(N, 32, 100), dtype=torch.complex64, device="cuda")
-    X[:, 7] = torch.tensor(x, dtype=torch.complex64, device="cuda")
-    Y = op.apply(X).cpu().numpy()
-    e32 = relerr(Y[rows, 7], ref)
+    op = _op(V, F, 6, dict(d0=4.5, interp_p=10), max_cols=32)
+    Xh = workloads.cn01_block(N, 32, 100)
+    Xh[:, 7] = x
+    Y = op.apply(torch.tensor(Xh, dtype=torch.complex64, device="cuda")).cpu().numpy()
+    cols = [0, 7, 19, 31]
+    R4 = Zr @ Xh[:, cols]
+    e32 = float(np.linalg.norm(Y[np.ix_(rows, cols)] - R4) / np.linalg.norm(R4))
     print(f"cfg2 fp64 {e64:.3e} fp32-batched {e32:.3e}", flush=True)
     assert e64 < TOL64
     assert e32 < TOL32

@@ -1,0 +1,112 @@
+"""Wavenumber sweeps through one handle (cm_create with n_k wavenumbers,
+cm_apply with a per-column k_index), through the C ABI.
+
+A column applied at k[i] through the sweep handle must equal the same column
+applied by a handle built at k[i] alone (same plan, tables and kernels; the
+sweep only gathers the columns of each wavenumber into one batch).  At the
+122,880-unknown sphere's 8-point band 0.9 k0 .. 1.1 k0 the sweep must meet
+the method's bounds against the FP64 oracle on sampled rows at every
+wavenumber (eight rows per wavenumber, relative Frobenius norm over the
+columns of that wavenumber): 5e-4 for the FP32 batch (d0 4.5, p 10, one-box
+buffer; measured 1.4e-4 .. 3.2e-4 across the band) and 1e-4 for FP64 (d0 4,
+p 10, two-box buffer at the two finest levels; measured 1.5e-5 .. 4.3e-5).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+K0 = 2 * np.pi
+ACC32 = dict(d0=5.0, interp_p=10)
+BAND32 = dict(d0=4.5, interp_p=10)
+BAND64 = dict(d0=4.0, interp_p=10, wide_near=True)
+
+
+def colerr(a, b):
+    return float(np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_sweep_columns_equal_single_k_handles(torch_cuda, dtype):
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = workloads.icosphere(4, 1.0)
+    ks = [0.9 * K0, K0, 1.1 * K0]
+    sw = Operator(V, F, ks, nlv=4, max_cols=16, **ACC32)
+    singles = [Operator(V, F, k, nlv=4, max_cols=16, **ACC32) for k in ks]
+    dt = torch.complex64 if dtype == "c64" else torch.complex128
+    X = torch.tensor(workloads.cn01_block(sw.N, 12, 40), dtype=dt, device="cuda")
+    kidx = np.array([j % 3 for j in range(12)], dtype=np.int32)
+    for opname in ("Z", "R", "ZH"):
+        Y = sw.apply(X, op=opname, k_index=kidx).cpu().numpy()
+        for i, op in enumerate(singles):
+            cols = np.nonzero(kidx == i)[0]
+            ref = op.apply(X[:, cols].contiguous(), op=opname).cpu().numpy()
+            e = colerr(Y[:, cols], ref)
+            print(f"sweep {dtype} op={opname} k={ks[i]:.4f}: {e:.1e}", flush=True)
+            assert e == 0.0
+    # one wavenumber for the whole batch runs in place
+    Y1 = sw.apply(X, k_index=np.full(12, 2, np.int32)).cpu().numpy()
+    assert colerr(Y1, singles[2].apply(X).cpu().numpy()) == 0.0
+    with pytest.raises(Exception):
+        sw.apply(X, k_index=np.full(12, 3, np.int32))
+
+
+@pytest.fixture(scope="module")
+def band():
+    """The band's wavenumbers and, per wavenumber, eight oracle rows of Z."""
+    from oracle import efie
+    from oracle.rwg import build_rwg
+    V, F, spec = workloads.workload("sphere_r4_n122880")
+    ks = list(np.linspace(0.9, 1.1, 8) * K0)
+    rng = np.random.default_rng(2)
+    geo = efie.Geometry(V, F)
+    rwg = build_rwg(V, F)
+    rows, Zr = [], []
+    for k in ks:
+        r = np.sort(rng.choice(len(rwg["edge"]), 8, replace=False))
+        rows.append(r)
+        Zr.append(efie.rows_Z(V, F, k, r, geo=geo, rwg=rwg))
+    return V, F, ks, rows, Zr
+
+
+def _band_errors(torch, band, acc, ncols, dt, seed):
+    from paper_1412_1756_amd import Operator
+    V, F, ks, rows, Zr = band
+    print(f"building the 8-wavenumber handle {acc} (8 plans and near-field fills)", flush=True)
+    sw = Operator(V, F, ks, nlv=6, max_cols=ncols, **acc)
+    N = sw.N
+    Xh = workloads.cn01_block(N, ncols, seed)
+    kidx = np.arange(ncols, dtype=np.int32) % 8
+    Y = sw.apply(torch.tensor(Xh, dtype=dt, device="cuda"), k_index=kidx).cpu().numpy()
+    errs = []
+    for i, k in enumerate(ks):
+        cols = np.nonzero(kidx == i)[0]
+        ref = Zr[i] @ Xh[:, cols]
+        e = float(np.linalg.norm(Y[np.ix_(rows[i], cols)] - ref) / np.linalg.norm(ref))
+        errs.append(e)
+        print(f"k = {k / K0:.4f} k0: rel err {e:.2e} ({len(rows[i])} rows x {len(cols)} columns)", flush=True)
+    return errs
+
+
+def test_sweep_config4_fp32_batch(torch_cuda, band):
+    """A block of 32 right-hand sides, column j at wavenumber j mod 8, FP32
+    far field."""
+    errs = _band_errors(torch_cuda, band, BAND32, 32, torch_cuda.complex64, 100)
+    assert max(errs) < 5e-4
+
+
+def test_sweep_band_fp64(torch_cuda, band):
+    """16 right-hand sides (two per wavenumber) in FP64 with the two-box
+    buffer."""
+    errs = _band_errors(torch_cuda, band, BAND64, 16, torch_cuda.complex128, 200)
+    assert max(errs) < 1e-4

@@ -45,8 +45,9 @@ def test_rwg_order_matches_oracle():
         np.testing.assert_array_equal(t, r["tri"])
 
 
-def _python_tree(V, F, nlv):
-    """Independent recount of boxes and far pairs (per level) from RWG midpoints."""
+def _python_tree(V, F, nlv, wide=False):
+    """Independent recount of boxes and far pairs (per level) from RWG midpoints.
+    Near radius 1 at every level, or 2 at the two finest levels (wide)."""
     r = build_rwg(V, F)
     mid = 0.5 * (V[r["edge"][:, 0]] + V[r["edge"][:, 1]])
     lo, hi = V.min(0), V.max(0)
@@ -58,32 +59,42 @@ def _python_tree(V, F, nlv):
     boxes = {lf: leaf}
     for l in range(lf - 1, -1, -1):
         boxes[l] = np.unique(boxes[l + 1] // 2, axis=0)
+    def nr(l):
+        return 2 if (wide and l >= lf - 1) else 1
     far = {}
     for l in range(2, lf + 1):
         B = boxes[l]
         d = np.abs(B[:, None, :] - B[None, :, :]).max(-1)
         P = B // 2
         dp = np.abs(P[:, None, :] - P[None, :, :]).max(-1)
-        far[l] = int(np.sum((d >= 2) & (dp <= 1)))
+        far[l] = int(np.sum((d >= nr(l) + 1) & (dp <= nr(l - 1))))
     leafd = np.abs(leaf[:, None, :] - leaf[None, :, :]).max(-1)
     cnt = np.bincount([tuple(map(tuple, leaf)).index(tuple(x)) for x in ijk], minlength=len(leaf)) if len(leaf) < 400 else None
     nnz = None
     if cnt is not None:
-        nnz = int(np.sum((leafd <= 1) * cnt[:, None] * cnt[None, :]))
+        nnz = int(np.sum((leafd <= nr(lf)) * cnt[:, None] * cnt[None, :]))
     return {l: len(b) for l, b in boxes.items()}, far, nnz
 
 
-@pytest.mark.parametrize("mesh", ["sphere", "plate"])
-def test_tree_and_lists_match_independent_count(mesh):
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("mesh", ["sphere", "plate", "sphere_r1"])
+def test_tree_and_lists_match_independent_count(mesh, wide):
+    """Box counts, far pairs per level and near-field size against a numpy
+    recount; CM_FLAG_CHECK also checks inside the library that every pair of
+    leaf boxes is covered exactly once (near field or one translation level)."""
     if mesh == "sphere":
         V, F = workloads.icosphere(3, 0.5)
         nlv = 3
+    elif mesh == "sphere_r1":
+        V, F = workloads.icosphere(4, 1.0)
+        nlv = 4
     else:
         V, F = workloads.plate(30, 30, 0.1)
         nlv = 4
-    op = _op(V, F, nlv, check_coverage=True)
+    op = _op(V, F, nlv, check_coverage=True, wide_near=wide)
     st = op.stats()
-    nb, far, nnz = _python_tree(V, F, nlv)
+    assert st["wide_near"] == int(wide)
+    nb, far, nnz = _python_tree(V, F, nlv, wide)
     for lv in st["levels"]:
         assert lv["nbox"] == nb[lv["l"]]
         if lv["l"] >= 2:
