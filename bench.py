@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--d0", type=float, default=4.5, help="digits (truncation rule) of the FP32 batched path")
     ap.add_argument("--p", type=int, default=10, help="interpolation points of the FP32 batched path")
     ap.add_argument("--wide", action="store_true", help="two-box buffer (wide near field) on the FP32 path")
+    ap.add_argument("--no-autotune", action="store_true", help="default matrix-core shapes on the FP32 path")
     ap.add_argument("--d0-64", type=float, default=4.0, help="digits of the FP64 single-vector path")
     ap.add_argument("--p-64", type=int, default=10, help="interpolation points of the FP64 path")
     ap.add_argument("--narrow-64", action="store_true",
@@ -130,7 +131,8 @@ def main():
     V, F, spec = workloads.workload(name)
     k = spec["k"]
     dev = torch.device("cuda:0")
-    op32 = Operator(V, F, k, nlv=a.nlv, d0=a.d0, interp_p=a.p, max_cols=max(a.ncols, 1), wide_near=a.wide)
+    op32 = Operator(V, F, k, nlv=a.nlv, d0=a.d0, interp_p=a.p, max_cols=max(a.ncols, 1), wide_near=a.wide,
+                    autotune=not a.no_autotune)
     op64 = Operator(V, F, k, nlv=a.nlv, d0=a.d0_64, interp_p=a.p_64, max_cols=1, wide_near=not a.narrow_64)
     N = op32.N
     st = op32.stats()
@@ -183,7 +185,8 @@ def main():
     dom64 = max((s for s in times64 if s in model64), key=lambda s: times64[s]["ms"])
     roof = roofline(dom32, times32, None, model32)
     roof64 = roofline(dom64, times64, None, model64)
-    cfg32 = f"d0 {a.d0:g}, p {a.p}, {a.ncols} columns" + (", wide near" if a.wide else "")
+    cfg32 = f"d0 {a.d0:g}, p {a.p}, {a.ncols} columns" + (", wide near" if a.wide else "") + \
+        ("" if a.no_autotune else ", autotuned")
     cfg64 = f"d0 {a.d0_64:g}, p {a.p_64}, 1 columns" + ("" if a.narrow_64 else ", wide near")
     roof["traffic"] = measured_traffic(dom32, "fp32_batched", cfg32)
     roof64["traffic"] = measured_traffic(dom64, "fp64_single", cfg64)
@@ -199,6 +202,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "N": N, "nlv": a.nlv, "d0": a.d0, "interp_p": a.p, "ncols": a.ncols,
                    "wide_near": bool(a.wide), "nnz_near": st["nnz_near"],
+                   "autotune": st.get("autotune"),
                    "k": k, "mesh": "icosphere nsub 6, radius 4 wavelengths"},
         "fp64_single": {"matvecs_per_s": 1000.0 / ms64, "ms_per_matvec": ms64, "dtype": "c128",
                         "d0": a.d0_64, "interp_p": a.p_64, "wide_near": not a.narrow_64,

@@ -102,6 +102,16 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
                                   entries and more leaf translations.  The
                                   SAI candidate pattern is the stored near
                                   field, so it widens with it.              */
+#define CM_FLAG_AUTOTUNE  64u  /* at create, time every valid slot-chunk width
+                                  and load row-group of the matrix-core
+                                  interpolation and anterpolation kernels of
+                                  each level at the batch width (largest
+                                  multiple of 8 up to max_cols, at most 64)
+                                  and keep the fastest (reported by
+                                  cm_stats under "autotune").  Changes only
+                                  the summation grouping: results differ
+                                  from an untuned handle by FP32 rounding,
+                                  and the choice may differ between handles */
 
 typedef struct {
   int32_t nlv;       /* number of octree levels including level 0 (>= 3)        */

@@ -161,6 +161,15 @@ static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<in
           D.zg = upload_zg(d, P.shift[l], P.mf_at[l], Lv.nt, Lv.np, s);
           if (P.opt.flags & CM_FLAG_DERIV) D.dzg = upload_zg(d, P.dshift[l], P.mf_at[l], Lv.nt, Lv.np, s);
         }
+        if (P.opt.flags & CM_FLAG_AUTOTUNE) {   // the autotuner's other slot-chunk width
+          D.mip_alt = upload_mf(d, P.mf_ip_alt[l], s);
+          D.mat_alt = upload_mf(d, P.mf_at_alt[l], s);
+          if (D.mat_alt.ok) {
+            D.zg_alt = upload_zg(d, P.shift[l], P.mf_at_alt[l], Lv.nt, Lv.np, s);
+            if (P.opt.flags & CM_FLAG_DERIV)
+              D.dzg_alt = upload_zg(d, P.dshift[l], P.mf_at_alt[l], Lv.nt, Lv.np, s);
+          }
+        }
       }
     }
   }
@@ -281,6 +290,17 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   }
   d.xi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
   d.yi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
+  // autotuning of the matrix-core interpolation shapes at the batch width
+  // (the largest multiple of 8 up to max_cols, at most 64) on zeroed workspace
+  if ((P.opt.flags & CM_FLAG_AUTOTUNE) && !(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) && d.max_cols >= 8) {
+    for (int l = 2; l <= lf; ++l) {
+      const size_t b = (size_t)P.lev[l].nbox * 2 * P.lev[l].K * d.max_cols * colmul * sizeof(double2);
+      chk(hipMemsetAsync(d.S[l], 0, b, s), "hipMemsetAsync");
+      chk(hipMemsetAsync(d.G[l], 0, b, s), "hipMemsetAsync");
+    }
+    d.tune_json = mf_autotune(d.f32, lf, d.S, d.G, std::min(64, d.max_cols / 8 * 8), s);
+    chk(hipGetLastError(), "autotune launches");
+  }
   chk(hipStreamSynchronize(s), "device set-up");
 }
 
@@ -565,6 +585,8 @@ cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_
 cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* needed) {
   if (!h) return fail(CM_E_BADARG, "null argument");
   std::string s = h->plan.stats_json();
+  if (h->has_dev && !h->dev.tune_json.empty() && !s.empty() && s.back() == '}')
+    s = s.substr(0, s.size() - 1) + ", \"autotune\": " + h->dev.tune_json + "}";
   if (needed) *needed = (int64_t)s.size() + 1;
   if (!buf || buf_len < (int64_t)s.size() + 1) return fail(CM_E_BADARG, "buffer too small");
   std::memcpy(buf, s.c_str(), s.size() + 1);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "../../include/cmmlfma.h"
@@ -58,6 +59,11 @@ struct LevelD {
   // anterpolation: phase values per slot chunk and octant in K-step key order,
   // [nchunk][8][nt][4 kmax] complex (and the k-derivative)
   void *zg = nullptr, *dzg = nullptr;
+  // autotuning: the tables with the other slot-chunk width (swapped in when
+  // faster) and the rows per load group of each kernel (0: default)
+  MfD mip_alt, mat_alt;
+  void *zg_alt = nullptr, *dzg_alt = nullptr;
+  int rg_ip = 0, rg_at = 0;
 };
 
 template <typename R>
@@ -104,6 +110,7 @@ struct Dev {
   std::vector<hipEvent_t> event_pool;
   std::vector<double> stage_ms;
   std::vector<int64_t> stage_calls;
+  std::string tune_json;                    // autotuner's choices (empty when not tuned)
 };
 
 // stage ids for timing: 0 permute, 1 near, 2 aggregate, 3 interp, 4 m2l,
@@ -137,6 +144,10 @@ bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bc
 bool mf_near32(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
                const int32_t* self_off, const float2* Zn, const float2* xi, float2* yi, int nleaf,
                int max_cols_box, int nc, int mode, hipStream_t s);
+// Time the matrix-core interpolation/anterpolation variants of every level on
+// the workspace at nc columns and keep the fastest; returns the choices (JSON).
+std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, const std::vector<void*>& G, int nc,
+                        hipStream_t s);
 // whether mf_anterp takes the anterpolation from level Lp for nc columns
 bool mf_covers(const LevelD<float>& Lp, int nc);
 

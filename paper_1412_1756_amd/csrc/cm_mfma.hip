@@ -17,6 +17,10 @@
 // the per-lane A operand (lane 16 g + r: output row r, input key 4 k + g).
 #include <hip/hip_runtime.h>
 
+#include <sstream>
+#include <string>
+#include <utility>
+
 #include "cm_device.h"
 
 namespace cm {
@@ -812,23 +816,15 @@ static size_t anterp_lds(const MfD& T, int ntp) {
   return (size_t)T.NT * T.ktmax * 68 * 4 + (size_t)ntp * 4 * T.kmax * 8 + (size_t)4 * ntp * RS * 4;
 }
 
-// rows per double-buffered load group (by the K-step register budget)
-#ifndef CM_RG_I8
-#define CM_RG_I8 2
-#endif
-#ifndef CM_RG_I16
-#define CM_RG_I16 1
-#endif
-#ifndef CM_RG_A8
-#define CM_RG_A8 2
-#endif
-#ifndef CM_RG_A16
-#define CM_RG_A16 1
-#endif
-template <int NT, int S2, int MK>
-static void launch_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
-                          int ldp, int accum, const void* shiftT, hipStream_t s) {
-  constexpr int RG = MK <= 8 ? CM_RG_I8 : CM_RG_I16;
+// Rows per double-buffered load group: by default from the K-step register
+// budget (two rows up to 8 K steps, one row at 16), or the autotuner's choice
+// for the level (LevelD::rg_ip / rg_at; 4 rows only up to 8 K steps).
+static int rg_default(int mk) { return mk <= 8 ? 2 : 1; }
+static bool rg_valid(int mk, int rg) { return rg == 1 || rg == 2 || (rg == 4 && mk <= 8); }
+
+template <int NT, int S2, int MK, int RG>
+static void launch_interp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
+                             int ldp, int accum, const void* shiftT, hipStream_t s) {
   const MfD& T = Lp.mip;
   const int nb = (Lp.nbox * T.nchunk + 7) / 8 * 8;
   const int ntiles = nc / 4;   // 2 components x nc/8
@@ -840,9 +836,17 @@ static void launch_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, cons
 }
 
 template <int NT, int S2, int MK>
-static void launch_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
-                          int ldp, int add, const void* zg, hipStream_t s) {
-  constexpr int RG = MK <= 8 ? CM_RG_A8 : CM_RG_A16;
+static void launch_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
+                          int ldp, int accum, const void* shiftT, int rg, hipStream_t s) {
+  if constexpr (MK <= 8)
+    if (rg == 4) return launch_interp_rg<NT, S2, MK, 4>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+  if (rg == 1) return launch_interp_rg<NT, S2, MK, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+  launch_interp_rg<NT, S2, MK, 2>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+}
+
+template <int NT, int S2, int MK, int RG>
+static void launch_anterp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
+                             int ldp, int add, const void* zg, hipStream_t s) {
   const MfD& T = Lp.mat;
   const int nb = (Lc.nbox * T.nchunk + 7) / 8 * 8;
   const int ntiles = nc / 4;
@@ -851,6 +855,15 @@ static void launch_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, cons
   hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + 3) / 4), dim3(256), sh, s, (const float*)Gp,
                      (float*)Gc, Lc.parent, Lc.octant, T, (const float2*)zg, Lc.nt, Lc.np, Lp.nt, Lp.np, Lc.nbox, nc,
                      ldp, add);
+}
+
+template <int NT, int S2, int MK>
+static void launch_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
+                          int ldp, int add, const void* zg, int rg, hipStream_t s) {
+  if constexpr (MK <= 8)
+    if (rg == 4) return launch_anterp_rg<NT, S2, MK, 4>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+  if (rg == 1) return launch_anterp_rg<NT, S2, MK, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+  launch_anterp_rg<NT, S2, MK, 2>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
 }
 
 #define CM_MF_CASES(X)                                                    \
@@ -874,9 +887,10 @@ bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* S
   const MfD& T = Lp.mip;
   if (!T.ok || nc % 8 != 0 || !shiftT || !lds_fits(interp_lds(T, Lc.nt)) || !has_case(T)) return false;
   const int mk = mk_of(T);
+  const int rg = rg_valid(mk, Lp.rg_ip) ? Lp.rg_ip : rg_default(mk);
 #define X(a, b, c)                                                           \
   if (T.NT == a && T.S2 == b && mk == c) {                                   \
-    launch_interp<a, b, c>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);       \
+    launch_interp<a, b, c>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, rg, s);   \
     return true;                                                             \
   }
   CM_MF_CASES(X)
@@ -894,14 +908,112 @@ bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* G
   const MfD& T = Lp.mat;
   if (!mf_covers(Lp, nc) || !zg) return false;
   const int mk = mk_of(T);
+  const int rg = rg_valid(mk, Lp.rg_at) ? Lp.rg_at : rg_default(mk);
 #define X(a, b, c)                                                       \
   if (T.NT == a && T.S2 == b && mk == c) {                               \
-    launch_anterp<a, b, c>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);         \
+    launch_anterp<a, b, c>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, rg, s);     \
     return true;                                                         \
   }
   CM_MF_CASES(X)
 #undef X
   return false;
+}
+
+// Autotuning of the matrix-core interpolation and anterpolation per level:
+// for each level, every valid combination of slot-chunk width (the plan's
+// table or the alternate one) and rows per load group is timed on the
+// workspace (one untimed and three timed launches at nc columns, HIP events
+// on the stream) and the fastest is kept.  The choices change only the
+// summation grouping, so results differ from the untuned handle by FP32
+// rounding.  Returns the choices and times as a JSON array.
+std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, const std::vector<void*>& G, int nc,
+                        hipStream_t s) {
+  std::ostringstream js;
+  js << "[";
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    throw Error(-4, "hipEventCreate (autotune)");
+  auto time_it = [&](auto&& launch) -> float {
+    if (!launch()) return -1.f;
+    if (hipEventRecord(e0, s) != hipSuccess) throw Error(-4, "hipEventRecord (autotune)");
+    for (int i = 0; i < 3; ++i) launch();
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      throw Error(-4, "autotune timing");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) throw Error(-4, "hipEventElapsedTime (autotune)");
+    return ms / 3.f;
+  };
+  bool first = true;
+  for (int l = 2; l < lf; ++l) {
+    LevelD<float>& Lp = pd.lev[l];
+    const LevelD<float>& Lc = pd.lev[l + 1];
+    for (int kind = 0; kind < 2; ++kind) {      // 0 interpolation into l, 1 anterpolation from l
+      MfD& cur = kind ? Lp.mat : Lp.mip;
+      MfD& alt = kind ? Lp.mat_alt : Lp.mip_alt;
+      int& rgsel = kind ? Lp.rg_at : Lp.rg_ip;
+      float best = 1e30f;
+      int best_alt = 0, best_rg = 0, best_s2 = 0;
+      float base = -1.f;
+      for (int a = 0; a < 2; ++a) {
+        if (a) {
+          std::swap(cur, alt);
+          if (kind) {
+            std::swap(Lp.zg, Lp.zg_alt);
+            std::swap(Lp.dzg, Lp.dzg_alt);
+          }
+        }
+        if (cur.ok) {
+          const int mk = mk_of(cur);
+          for (int rg : {1, 2, 4}) {
+            if (!rg_valid(mk, rg)) continue;
+            rgsel = rg;
+            const float ms = kind ? time_it([&] {
+              return mf_anterp(Lp, Lc, (const float2*)G[l], (float2*)G[l + 1], nc, nc, 1, Lp.zg, s);
+            })
+                                  : time_it([&] {
+                                      return mf_interp(Lp, Lc, (const float2*)S[l + 1], (float2*)S[l], nc, nc, 0,
+                                                       Lp.shiftT, s);
+                                    });
+            if (ms < 0.f) break;   // this table is not covered at all
+            if (a == 0 && rg == rg_default(mk)) base = ms;
+            if (ms < best) {
+              best = ms;
+              best_alt = a;
+              best_rg = rg;
+              best_s2 = cur.S2;
+            }
+          }
+        }
+        if (a) {   // back to the plan's table
+          std::swap(cur, alt);
+          if (kind) {
+            std::swap(Lp.zg, Lp.zg_alt);
+            std::swap(Lp.dzg, Lp.dzg_alt);
+          }
+        }
+      }
+      if (best >= 1e30f) {
+        rgsel = 0;
+        continue;
+      }
+      if (best_alt) {
+        std::swap(cur, alt);
+        if (kind) {
+          std::swap(Lp.zg, Lp.zg_alt);
+          std::swap(Lp.dzg, Lp.dzg_alt);
+        }
+      }
+      rgsel = best_rg;
+      js << (first ? "" : ", ") << "{\"stage\": \"" << (kind ? "anterp_l" : "interp_l") << (kind ? l + 1 : l)
+         << "\", \"half_slots\": " << best_s2 << ", \"row_group\": " << best_rg << ", \"ms\": " << best
+         << ", \"default_ms\": " << base << "}";
+      first = false;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  js << "]";
+  return js.str();
 }
 
 }  // namespace cm

@@ -158,11 +158,19 @@ int gather_steps(const RowList& rows, std::vector<int32_t>& key, std::vector<dou
 // lds_rows: theta rows each wave keeps in LDS (32 S2 + 16 floats per row);
 // the half slot count drops to 4 where S2 = 8 would take more than 80 KiB
 // for a block of four waves (two blocks per CU), or more than 128
-// accumulator registers.
+// accumulator registers.  alt: the other width instead (8 <-> 4); the table
+// is left not ok where that is 8 and would need more than 128 accumulators.
 template <typename PhiRows, typename ThetaRows>
-void build_tab(MfTab& T, int nth, int nph, int lds_rows, PhiRows phi_rows, ThetaRows theta_rows) {
+void build_tab(MfTab& T, int nth, int nph, int lds_rows, PhiRows phi_rows, ThetaRows theta_rows, bool alt = false) {
   T.NT = (nth + 15) / 16;
   T.S2 = (T.NT <= 2 && (size_t)lds_rows * (16 * 16 + 16) * 4 * 4 <= 80 * 1024) ? 8 : 4;
+  if (alt) {
+    T.S2 = 12 - T.S2;
+    if (T.S2 == 8 && T.NT > 2) {
+      T.ok = false;
+      return;
+    }
+  }
   T.half = nph / 2;
   T.nchunk = (T.half + T.S2 - 1) / T.S2;
   std::vector<std::vector<int32_t>> keys(T.nchunk);
@@ -211,16 +219,18 @@ void build_tab(MfTab& T, int nth, int nph, int lds_rows, PhiRows phi_rows, Theta
 }
 }  // namespace
 
-static void build_mf_tables(Plan& P) {
-  P.mf_ip.assign(P.lf + 1, MfTab());
-  P.mf_at.assign(P.lf + 1, MfTab());
+static void build_mf_tables(Plan& P, bool alt) {
+  std::vector<MfTab>& ip = alt ? P.mf_ip_alt : P.mf_ip;
+  std::vector<MfTab>& at = alt ? P.mf_at_alt : P.mf_at;
+  ip.assign(P.lf + 1, MfTab());
+  at.assign(P.lf + 1, MfTab());
   for (int l = 2; l < P.lf; ++l) {
     const Interp& I = P.ip[l];
     const int p = I.p;
     // interpolation child l+1 -> l: phi first (child phi -> parent phi), then
     // theta over child rows, reflected entries read the partner phi column
     build_tab(
-        P.mf_ip[l], I.ntp, I.npp, I.ntc,
+        ip[l], I.ntp, I.npp, I.ntc,
         [&](int up) {
           std::vector<std::pair<int32_t, double>> e;
           for (int j = 0; j < p; ++j) e.push_back({I.ph_idx[up * p + j], I.ph_w[up * p + j]});
@@ -233,11 +243,12 @@ static void build_mf_tables(Plan& P) {
             e.push_back({I.th_idx[tp * p + j] | (ref << 16), ref ? -I.th_w[tp * p + j] : I.th_w[tp * p + j]});
           }
           return e;
-        });
+        },
+        alt);
     // anterpolation l -> l+1: weighted transposes, phi first (parent phi ->
     // child phi), then theta over parent rows with reflection in child phi
     build_tab(
-        P.mf_at[l], I.ntc, I.npc, I.ntp,
+        at[l], I.ntc, I.npc, I.ntp,
         [&](int uc) {
           std::vector<std::pair<int32_t, double>> e;
           for (int q = I.pht_ptr[uc]; q < I.pht_ptr[uc + 1]; ++q) e.push_back({I.pht_idx[q], I.pht_w[q]});
@@ -250,7 +261,8 @@ static void build_mf_tables(Plan& P) {
             e.push_back({I.tht_idx[q] | (ref << 16), ref ? -I.tht_w[q] : I.tht_w[q]});
           }
           return e;
-        });
+        },
+        alt);
   }
 }
 
@@ -801,7 +813,8 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
       }
     }
   }
-  build_mf_tables(*this);
+  build_mf_tables(*this, false);
+  if (o.flags & 64u) build_mf_tables(*this, true);   // candidates for the autotuner
   if (o.flags & 4u) check_coverage();
 }
 

@@ -116,6 +116,8 @@ struct Plan {
   std::vector<Level> lev;       // 0..lf
   std::vector<Interp> ip;       // ip[l] maps level l+1 -> l, for l = 2..lf-1
   std::vector<MfTab> mf_ip, mf_at;  // matrix-core tables: interpolation into l, anterpolation from l
+  // the same with the other slot-chunk width (built for autotuning only; ok = false where none)
+  std::vector<MfTab> mf_ip_alt, mf_at_alt;
   std::vector<int32_t> perm;    // internal index -> public RWG index
   std::vector<int32_t> iperm;   // public -> internal
   std::vector<int32_t> box_start;  // leaf box -> first internal unknown (nleaf+1)

@@ -142,3 +142,41 @@ def test_mfma_repeat_is_deterministic(torch_cuda, ops):
     y1 = mf.apply(X).clone()
     y2 = mf.apply(X)
     assert torch.equal(y1, y2)
+
+
+def test_autotune_choices_and_parity(torch_cuda, sphere2, ops):
+    """CM_FLAG_AUTOTUNE: every matrix-core interpolation and anterpolation
+    stage gets a timed choice no slower than the default shape, and the tuned
+    product differs from the untuned one by FP32 rounding only (same bounds
+    as the matrix-core/vector-ALU comparison), for Z, Z^H and dZ/dk."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = sphere2
+    mf, _ = ops
+    at = Operator(V, F, K0, nlv=5, max_cols=32, autotune=True, **ACC32)
+    tune = at.stats()["autotune"]
+    print("autotune:", tune, flush=True)
+    assert {t["stage"] for t in tune} == {"interp_l2", "interp_l3", "anterp_l3", "anterp_l4"}
+    for t in tune:
+        assert t["half_slots"] in (4, 8) and t["row_group"] in (1, 2, 4)
+        assert t["default_ms"] < 0 or t["ms"] <= t["default_ms"]
+    Xh = workloads.cn01_block(mf.N, 32, 1234)
+    X = torch.tensor(Xh, dtype=torch.complex64, device="cuda")
+    for opname in ("Z", "ZH"):
+        y1 = mf.apply(X, op=opname).cpu().numpy()
+        y2 = at.apply(X, op=opname).cpu().numpy()
+        y3 = mf.apply(torch.tensor(Xh, dtype=torch.complex128, device="cuda"), op=opname).cpu().numpy()
+        e, e1, e2 = colerr(y2, y1), colerr(y1, y3), colerr(y2, y3)
+        print(f"autotuned op={opname}: vs untuned {e:.2e}; vs fp64 {e2:.2e} (untuned {e1:.2e})", flush=True)
+        assert e < TOL_PATH
+        assert e2 <= 1.5 * e1 + 2e-6
+    del at
+    d1 = Operator(V, F, K0, nlv=5, max_cols=8, deriv=True, **ACC32)
+    d2 = Operator(V, F, K0, nlv=5, max_cols=8, deriv=True, autotune=True, **ACC32)
+    X8 = torch.tensor(Xh[:, :8], dtype=torch.complex64, device="cuda")
+    y1 = d1.apply(X8, op="DZDK").cpu().numpy()
+    y2 = d2.apply(X8, op="DZDK").cpu().numpy()
+    y3 = d1.apply(torch.tensor(Xh[:, :8], dtype=torch.complex128, device="cuda"), op="DZDK").cpu().numpy()
+    e1, e2 = colerr(y1, y3), colerr(y2, y3)
+    print(f"autotuned dZ/dk vs fp64 {e2:.2e} (untuned {e1:.2e}); tuned {d2.stats()['autotune']}", flush=True)
+    assert e2 <= 1.25 * e1 + 1e-6
