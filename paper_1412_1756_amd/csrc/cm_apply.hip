@@ -366,30 +366,15 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
     int lo[QPT];
 #pragma unroll
     for (int u = 0; u < QPT; ++u) lo[u] = (act[u] ? q[u] * ldp : 0) + (c < nc ? c : 0);
-    C2<R> n0[QPT], n1[QPT];
-    if (e0 < e1) {
-      const C2<R>* sp = S + tsrc[e0] * bstride;
+    auto load_src = [&](int e, C2<R>(&n0)[QPT], C2<R>(&n1)[QPT]) {
+      const C2<R>* sp = S + tsrc[e] * bstride;
 #pragma unroll
       for (int u = 0; u < QPT; ++u) {
         n0[u] = sp[lo[u]];
         n1[u] = sp[cstride + lo[u]];
       }
-    }
-    for (int e = e0; e < e1; ++e) {
-      C2<R> s0[QPT], s1[QPT];
-#pragma unroll
-      for (int u = 0; u < QPT; ++u) {
-        s0[u] = n0[u];
-        s1[u] = n1[u];
-      }
-      if (e + 1 < e1) {
-        const C2<R>* sp = S + tsrc[e + 1] * bstride;
-#pragma unroll
-        for (int u = 0; u < QPT; ++u) {
-          n0[u] = sp[lo[u]];
-          n1[u] = sp[cstride + lo[u]];
-        }
-      }
+    };
+    auto apply_src = [&](int e, const C2<R>(&s0)[QPT], const C2<R>(&s1)[QPT]) {
       // the translator ids of this pass's receivers for this source: uniform,
       // one batch of scalar loads
       const int4* of4 = reinterpret_cast<const int4*>(toff + (int64_t)e * kTile + h);
@@ -415,6 +400,18 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
           }
         }
       }
+    };
+    C2<R> n0[QPT], n1[QPT];
+    if (e0 < e1) load_src(e0, n0, n1);
+    for (int e = e0; e < e1; ++e) {
+      C2<R> s0[QPT], s1[QPT];
+#pragma unroll
+      for (int u = 0; u < QPT; ++u) {
+        s0[u] = n0[u];
+        s1[u] = n1[u];
+      }
+      if (e + 1 < e1) load_src(e + 1, n0, n1);
+      apply_src(e, s0, s1);
     }
 #pragma unroll
     for (int u = 0; u < QPT; ++u) {
@@ -1182,11 +1179,13 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   // then the parent's anterpolated pattern is added onto them (the
   // matrix-core kernel adds with one atomic per element, so the sum is still
   // formed in a fixed order).
-  bool mf_down = false;
-  if constexpr (sizeof(R) == 4) {
-    mf_down = !(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) && nc % 8 == 0;
-    for (int l = 2; l < lf && mf_down; ++l) mf_down = mf_covers(pd.lev[l], nc);
-  }
+  // matrix-core anterpolation where it covers the level (both kernels add
+  // onto the child level's stored translations)
+  auto mf_down = [&](int l) {
+    if constexpr (sizeof(R) == 4)
+      return !(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) && nc % 8 == 0 && mf_covers(pd.lev[l], nc);
+    return false;
+  };
   auto m2l_level = [&](int l, int accum) {
     LevelD<R>& Lv = pd.lev[l];
     const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
@@ -1198,7 +1197,7 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   for (int l = 2; l <= lf; ++l) m2l_level(l, 0);
   for (int l = 2; l < lf; ++l) {
     stage_begin(d, s, 5 + 10 * (l + 1));
-    if (mf_down) {
+    if (mf_down(l)) {
       st.anterp_mf(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift, 1);
       if (dual) st.anterp_mf(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift, 1);
     } else {

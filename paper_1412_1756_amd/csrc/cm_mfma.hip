@@ -58,19 +58,25 @@ __device__ __forceinline__ void load_rows(float (&v)[kRG][kMK], const float* bas
   }
 }
 
-// theta-step tables of all row tiles into LDS (ktmax steps each: 4 keys, 64 A values)
-__device__ __forceinline__ void stage_theta_tables(const MfD& T, int NT, int* tcode, float* tA) {
-  for (int e = threadIdx.x; e < NT * T.ktmax * 4; e += blockDim.x) tcode[e] = T.tidx[e];
-  for (int e = threadIdx.x; e < NT * T.ktmax * 64; e += blockDim.x) tA[e] = T.tA[e];
+// theta-step tables of the block's row tiles t0 .. t0+NT-1 into LDS (ktmax
+// steps each: 4 keys, 64 A values; tiles past the last are zero)
+__device__ __forceinline__ void stage_theta_tables(const MfD& T, int t0, int NT, int* tcode, float* tA) {
+  const int nv = (T.NT - t0) * T.ktmax;   // valid steps of the group
+  for (int e = threadIdx.x; e < NT * T.ktmax * 4; e += blockDim.x)
+    tcode[e] = (e / 4 < nv) ? T.tidx[t0 * T.ktmax * 4 + e] : 0;
+  for (int e = threadIdx.x; e < NT * T.ktmax * 64; e += blockDim.x)
+    tA[e] = (e / 64 < nv) ? T.tA[t0 * T.ktmax * 64 + e] : 0.f;
 }
 
 // Interpolation child level -> parent level, summed over the children of a
 // parent with the shift phase of each child's octant; parent rows are written
 // (or accumulated onto, accum != 0).  Grid: x = parent boxes x slot chunks
-// (padded to a multiple of 8, XCD-major order), y = groups of four column
-// tiles; 256 threads, one column tile per wave.  The phi-step loads of a
-// child are double-buffered in groups of kRG rows and the first group of the
-// next child is loaded during the theta step, which touches only LDS.
+// (padded to a multiple of 8, XCD-major order), y = groups of column tiles,
+// one per wave (four waves per block, fewer where their LDS rows do not fit),
+// z = groups of NT theta row tiles (more than four tiles are split over
+// blocks, each redoing the phi step).  The phi-step loads of a child are
+// double-buffered in groups of kRG rows and the first group of the next
+// child is loaded during the theta step, which touches only LDS.
 template <int NT, int S2, int kMK, int kRG>
 __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc, float* __restrict__ Sp,
                                                    const int32_t* __restrict__ child_ptr,
@@ -82,12 +88,13 @@ __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   if (b >= nbox * T.nchunk) return;   // whole block
+  const int t0 = blockIdx.z * NT;   // first theta row tile of this block
   int* tcode = reinterpret_cast<int*>(lds);
   float* tAl = lds + NT * T.ktmax * 4;
-  stage_theta_tables(T, NT, tcode, tAl);
+  stage_theta_tables(T, t0, NT, tcode, tAl);
   __syncthreads();
   const int cpt = nc >> 3;
-  const int tile = blockIdx.y * 4 + w;
+  const int tile = blockIdx.y * (int)(blockDim.x >> 6) + w;
   if (tile >= 2 * cpt) return;
   float* O = tAl + NT * T.ktmax * 64 + w * (ntc * RS + 2 * SH);
   float2* ShL = reinterpret_cast<float2*>(O + ntc * RS);   // [slot][16 NT] shift of the current child
@@ -144,14 +151,15 @@ __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc,
   for (int ch = ch0; ch < ch1; ++ch) {
     const float* src = child_src(ch);
     // this child's shift rows of the chunk's slots (written to LDS after the phi step)
-    const float4* shg = reinterpret_cast<const float4*>(shiftT + (size_t)octant[ch] * npp * (16 * NT));
+    // table rows hold 16 T.NT values per phi slot; this block's tiles start at 16 t0
+    const float4* shg = reinterpret_cast<const float4*>(shiftT + (size_t)octant[ch] * npp * (16 * T.NT));
     float4 shv[(SH / 2 + 63) / 64];
 #pragma unroll
     for (int i = 0; i < (SH / 2 + 63) / 64; ++i) {
       const int e = lane + 64 * i;                  // float4 index: slot e / (8 NT), pair e % (8 NT)
       const int sl = e / (8 * NT), q = e - sl * (8 * NT);
       const int up = (sl % S2) < h ? u0 + (sl % S2) + (sl / S2) * T.half : u0;
-      if (e < SH / 2) shv[i] = shg[up * (8 * NT) + q];
+      if (e < SH / 2) shv[i] = (t0 + q / 8 < T.NT) ? shg[up * (8 * T.NT) + 8 * t0 + q] : float4{0.f, 0.f, 0.f, 0.f};
     }
     // phi step, double-buffered row groups
     for (int tc0 = 0; tc0 < ntc; tc0 += 2 * kRG) {
@@ -173,7 +181,7 @@ __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc,
     // theta step per row tile and slot batch, then shift and accumulate
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int nkt = T.nkt[t];
+      const int nkt = (t0 + t < T.NT) ? T.nkt[t0 + t] : 0;
 #pragma unroll
       for (int s0 = 0; s0 < S; s0 += SB) {
         f4 d2[SB];
@@ -220,7 +228,7 @@ __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc,
       const int up = u0 + (s % S2) + (s / S2) * T.half;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int tp = 16 * t + 4 * g + j;
+        const int tp = 16 * (t0 + t) + 4 * g + j;
         if (tp < ntp) {
           float* o = dst + ((int64_t)tp * npp + up) * ld2;
           if (accum)
@@ -233,7 +241,8 @@ __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc,
 }
 
 // Anterpolation parent level -> child level, one child box (and slot chunk
-// over the child phi grid) per block: conj(shift) times the parent pattern,
+// over the child phi grid, and group of NT child theta row tiles) per block:
+// conj(shift) times the parent pattern,
 // the transposed phi step (parent phi -> child slots) into LDS, the
 // transposed theta step with the child-grid reflection, stored into the child
 // rows (add != 0: added onto them).  The block stages the chunk's shift
@@ -253,10 +262,11 @@ __global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp,
   if (b >= nchild * T.nchunk) return;   // whole block
   const int ch = b / T.nchunk, c = b - ch * T.nchunk;
   const int kz = 4 * T.kmax;
+  const int t0 = blockIdx.z * NT;   // first child theta row tile of this block
   int* tcode = reinterpret_cast<int*>(lds);
   float* tAl = lds + NT * T.ktmax * 4;
   float2* Z = reinterpret_cast<float2*>(tAl + NT * T.ktmax * 64);
-  stage_theta_tables(T, NT, tcode, tAl);
+  stage_theta_tables(T, t0, NT, tcode, tAl);
   {
     const float4* zs = reinterpret_cast<const float4*>(zg + ((size_t)c * 8 + octant[ch]) * ntp * kz);
     float4* zd = reinterpret_cast<float4*>(Z);
@@ -264,7 +274,7 @@ __global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp,
   }
   __syncthreads();
   const int cpt = nc >> 3;
-  const int tile = blockIdx.y * 4 + w;
+  const int tile = blockIdx.y * (int)(blockDim.x >> 6) + w;
   if (tile >= 2 * cpt) return;
   float* O = reinterpret_cast<float*>(Z + ntp * kz) + w * ntp * RS;
   const int m = parent[ch];
@@ -333,7 +343,7 @@ __global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp,
     for (int s = 0; s < S; ++s) acc[t][s] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int nkt = T.nkt[t];
+    const int nkt = (t0 + t < T.NT) ? T.nkt[t0 + t] : 0;
     for (int kk = 0; kk < nkt; ++kk) {
       const int code = tcode[(t * T.ktmax + kk) * 4 + g];
       const float a = tAl[(t * T.ktmax + kk) * 64 + lane];
@@ -351,8 +361,8 @@ __global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp,
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (16 * t + 4 * g + j >= ntc) continue;
-      const unsigned ro = loff + (unsigned)(16 * t + j) * rstep;
+      if (16 * (t0 + t) + 4 * g + j >= ntc) continue;
+      const unsigned ro = loff + (unsigned)(16 * (t0 + t) + j) * rstep;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         if ((s % S2) >= h) continue;
@@ -807,13 +817,34 @@ static void lds_limit(const void* f, size_t bytes) {
 
 static bool lds_fits(size_t bytes) { return bytes <= 160 * 1024; }
 
-static size_t interp_lds(const MfD& T, int ntc) {
-  const int S = 2 * T.S2, RS = 16 * S + 16, SH = S * 16 * T.NT;
-  return (size_t)T.NT * T.ktmax * 68 * 4 + (size_t)4 * (ntc * RS + 2 * SH) * 4;
+// theta row tiles per block: all of them up to four, else split evenly over
+// ceil(NT / 4) blocks
+static int nt_block(const MfD& T) {
+  const int groups = (T.NT + 3) / 4;
+  return (T.NT + groups - 1) / groups;
 }
-static size_t anterp_lds(const MfD& T, int ntp) {
+static int nt_groups(const MfD& T) { return (T.NT + nt_block(T) - 1) / nt_block(T); }
+
+// LDS of a block of wpb waves (each wave keeps its own phi-step rows)
+static size_t interp_lds(const MfD& T, int ntc, int wpb) {
+  const int nb = nt_block(T), S = 2 * T.S2, RS = 16 * S + 16, SH = S * 16 * nb;
+  return (size_t)nb * T.ktmax * 68 * 4 + (size_t)wpb * (ntc * RS + 2 * SH) * 4;
+}
+static size_t anterp_lds(const MfD& T, int ntp, int wpb) {
   const int S = 2 * T.S2, RS = 16 * S + 16;
-  return (size_t)T.NT * T.ktmax * 68 * 4 + (size_t)ntp * 4 * T.kmax * 8 + (size_t)4 * ntp * RS * 4;
+  return (size_t)nt_block(T) * T.ktmax * 68 * 4 + (size_t)ntp * 4 * T.kmax * 8 + (size_t)wpb * ntp * RS * 4;
+}
+// waves per block: four (one column tile each), fewer where the rows of four
+// waves do not fit in LDS (large angular grids at coarse levels); 0: none fits
+static int interp_wpb(const MfD& T, int ntc) {
+  for (int w = 4; w >= 1; w /= 2)
+    if (lds_fits(interp_lds(T, ntc, w))) return w;
+  return 0;
+}
+static int anterp_wpb(const MfD& T, int ntp) {
+  for (int w = 4; w >= 1; w /= 2)
+    if (lds_fits(anterp_lds(T, ntp, w))) return w;
+  return 0;
 }
 
 // Rows per double-buffered load group: by default from the K-step register
@@ -828,9 +859,12 @@ static void launch_interp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, c
   const MfD& T = Lp.mip;
   const int nb = (Lp.nbox * T.nchunk + 7) / 8 * 8;
   const int ntiles = nc / 4;   // 2 components x nc/8
-  const size_t sh = interp_lds(T, Lc.nt);
+  const int wpb = interp_wpb(T, Lc.nt);
+  const size_t sh = interp_lds(T, Lc.nt, wpb);
   lds_limit((const void*)k_interp_mf<NT, S2, MK, RG>, sh);
-  hipLaunchKernelGGL((k_interp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + 3) / 4), dim3(256), sh, s, (const float*)Sc,
+  hipLaunchKernelGGL((k_interp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
+                     sh, s,
+                     (const float*)Sc,
                      (float*)Sp, Lp.child_ptr, Lc.octant, T, (const float2*)shiftT, Lc.nt, Lc.np, Lp.nt, Lp.np,
                      Lp.nbox, nc, ldp, accum);
 }
@@ -850,9 +884,12 @@ static void launch_anterp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, c
   const MfD& T = Lp.mat;
   const int nb = (Lc.nbox * T.nchunk + 7) / 8 * 8;
   const int ntiles = nc / 4;
-  const size_t sh = anterp_lds(T, Lp.nt);
+  const int wpb = anterp_wpb(T, Lp.nt);
+  const size_t sh = anterp_lds(T, Lp.nt, wpb);
   lds_limit((const void*)k_anterp_mf<NT, S2, MK, RG>, sh);
-  hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + 3) / 4), dim3(256), sh, s, (const float*)Gp,
+  hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
+                     sh, s,
+                     (const float*)Gp,
                      (float*)Gc, Lc.parent, Lc.octant, T, (const float2*)zg, Lc.nt, Lc.np, Lp.nt, Lp.np, Lc.nbox, nc,
                      ldp, add);
 }
@@ -874,9 +911,9 @@ static void launch_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, cons
 static int mk_of(const MfD& T) { return T.kmax <= 4 ? 4 : T.kmax <= 8 ? 8 : 16; }
 
 static bool has_case(const MfD& T) {
-  const int mk = mk_of(T);
+  const int mk = mk_of(T), nb = nt_block(T);
 #define X(a, b, c) \
-  if (T.NT == a && T.S2 == b && mk == c) return true;
+  if (nb == a && T.S2 == b && mk == c) return true;
   CM_MF_CASES(X)
 #undef X
   return false;
@@ -885,11 +922,12 @@ static bool has_case(const MfD& T) {
 bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc, int ldp,
                int accum, const void* shiftT, hipStream_t s) {
   const MfD& T = Lp.mip;
-  if (!T.ok || nc % 8 != 0 || !shiftT || !lds_fits(interp_lds(T, Lc.nt)) || !has_case(T)) return false;
+  if (!T.ok || nc % 8 != 0 || !shiftT || !interp_wpb(T, Lc.nt) || !has_case(T)) return false;
   const int mk = mk_of(T);
   const int rg = rg_valid(mk, Lp.rg_ip) ? Lp.rg_ip : rg_default(mk);
+  const int nb = nt_block(T);
 #define X(a, b, c)                                                           \
-  if (T.NT == a && T.S2 == b && mk == c) {                                   \
+  if (nb == a && T.S2 == b && mk == c) {                                   \
     launch_interp<a, b, c>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, rg, s);   \
     return true;                                                             \
   }
@@ -900,7 +938,7 @@ bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* S
 
 bool mf_covers(const LevelD<float>& Lp, int nc) {
   const MfD& T = Lp.mat;
-  return T.ok && nc % 8 == 0 && Lp.zg && lds_fits(anterp_lds(T, Lp.nt)) && has_case(T);
+  return T.ok && nc % 8 == 0 && Lp.zg && anterp_wpb(T, Lp.nt) && has_case(T);
 }
 
 bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc, int ldp,
@@ -909,8 +947,9 @@ bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* G
   if (!mf_covers(Lp, nc) || !zg) return false;
   const int mk = mk_of(T);
   const int rg = rg_valid(mk, Lp.rg_at) ? Lp.rg_at : rg_default(mk);
+  const int nb = nt_block(T);
 #define X(a, b, c)                                                       \
-  if (T.NT == a && T.S2 == b && mk == c) {                               \
+  if (nb == a && T.S2 == b && mk == c) {                               \
     launch_anterp<a, b, c>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, rg, s);     \
     return true;                                                         \
   }

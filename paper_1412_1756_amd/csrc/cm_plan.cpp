@@ -215,7 +215,7 @@ void build_tab(MfTab& T, int nth, int nph, int lds_rows, PhiRows phi_rows, Theta
   }
   T.kmax = km;
   T.ktmax = ktm;
-  T.ok = T.NT <= 4 && T.kmax <= 16;
+  T.ok = T.kmax <= 16;   // more than four theta tiles are split over blocks
 }
 }  // namespace
 

@@ -180,3 +180,41 @@ def test_autotune_choices_and_parity(torch_cuda, sphere2, ops):
     e1, e2 = colerr(y1, y3), colerr(y2, y3)
     print(f"autotuned dZ/dk vs fp64 {e2:.2e} (untuned {e1:.2e}); tuned {d2.stats()['autotune']}", flush=True)
     assert e2 <= 1.25 * e1 + 1e-6
+
+
+def test_interp_theta_tiles_split_over_blocks(torch_cuda):
+    """Two 1 x 1 wavelength plates at opposite corners of a 32-wavelength cube
+    (8 levels, 0.25-wavelength leaves, 560 unknowns): their only coupling is
+    the translation at level 2, whose sampling (L = 109, 110 theta rows) has
+    seven theta row tiles, so the matrix-core interpolation into level 2
+    splits them over two blocks, and the matrix-core anterpolation out of
+    level 2 (110 parent rows per wave in LDS) runs with one wave per block.  The field on plate B from
+    sources on plate A against the oracle's Z[B, A] x_A, and the whole
+    product against the dense oracle (FP32 bound 5e-4), for the matrix-core
+    and the vector-ALU kernels."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    from oracle import efie
+    V0, F0 = workloads.plate(10, 10, 0.1)
+    V = np.vstack([V0 - 15.5, V0 + 15.5])
+    F = np.vstack([F0, F0 + len(V0)]).astype(np.int32)
+    Z = efie.dense_Z(V, F, K0)
+    N = Z.shape[0]
+    mf = Operator(V, F, K0, nlv=8, max_cols=8, **ACC32)
+    st = {x["l"]: x for x in mf.stats()["levels"]}
+    assert st[2]["mf_interp"]["NT"] > 4 and st[2]["far_pairs"] == 2
+    e, _ = mf.rwg_table()
+    onA = e.max(axis=1) < len(V0)
+    Xh = workloads.cn01_block(N, 8, 60)
+    Xh[~onA, :] = 0
+    ref = Z @ Xh
+    refB = ref[~onA]
+    va = Operator(V, F, K0, nlv=8, max_cols=8, matrix_cores=False, **ACC32)
+    y1 = mf.apply(torch.tensor(Xh, dtype=torch.complex64, device="cuda")).cpu().numpy()
+    y2 = va.apply(torch.tensor(Xh, dtype=torch.complex64, device="cuda")).cpu().numpy()
+    eB = [colerr(y[~onA], refB) for y in (y1, y2)]
+    eAll = [colerr(y, ref) for y in (y1, y2)]
+    print(f"plates 32 wl apart: field on B mfma {eB[0]:.2e} valu {eB[1]:.2e}; "
+          f"whole product {eAll[0]:.2e} / {eAll[1]:.2e}; mfma-valu on B {colerr(y1[~onA], y2[~onA]):.2e}", flush=True)
+    assert max(eB) < TOL32 and max(eAll) < TOL32
+    assert colerr(y1[~onA], y2[~onA]) < TOL_PATH
