@@ -563,12 +563,14 @@ __device__ __forceinline__ double pair_swap64(double v) {
 }
 
 // Near-field product y_i = sum_t Z_near[i, t] x[col_t] (mode 1: Re Z_near on
-// the box's own columns, mode 2: Im Z_near) on the FP64 matrix cores.  One
-// wave per leaf box: two row tiles of 16 at a time times every column tile
-// of 16 reals (x rows gathered from memory and converted to FP64), so each
-// near-field value is loaded once.  Complex steps as in the leaf
-// aggregation: C += Re(A) B + Im(A) B~.  nc <= 32.
-template <typename R, int MODE>
+// the box's own columns, mode 2: Im Z_near) on the FP64 matrix cores.  Each
+// leaf box takes (2 / MT) x (4 / NW) waves: a wave owns MT of every two row
+// tiles of 16 (rows 32 k + 16 h .. for its half h when MT = 1) times NW of
+// the four column tiles of 16 reals (x rows gathered from memory and
+// converted to FP64), so each near-field value is loaded by 4 / NW waves.
+// Complex steps as in the leaf aggregation: C += Re(A) B + Im(A) B~.
+// nc <= 32.
+template <typename R, int MODE, int MT, int NW>
 __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ box_start,
                                                  const int32_t* __restrict__ bcol_ptr,
@@ -579,7 +581,10 @@ __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row
   extern __shared__ int32_t xoff_all[];   // per wave: the box's column rows as offsets into x (floats)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const int b = blockIdx.x * 4 + w;
+  constexpr int WM = 2 / MT, WB = WM * (4 / NW);   // waves per box (row halves x column groups)
+  const int b = blockIdx.x * (4 / WB) + w / WB;
+  const int mh = (MT == 1) ? 16 * (w % WM) : 0;    // first row of this wave's tile in each 32
+  const int n0 = NW * ((w % WB) / WM);             // first column tile of this wave
   if (b >= nleaf) return;
   int32_t* xoff = xoff_all + w * xcap;
   const int r0 = box_start[b], nb = box_start[b + 1] - r0;
@@ -596,43 +601,44 @@ __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row
   wave_lds_sync();
   const int tlast = t1 - t0 - 1;
   const double sg = (r & 1) ? 1.0 : -1.0;
-  for (int m0 = 0; m0 < nb; m0 += 32) {
+  for (int m0 = mh; m0 < nb; m0 += 32) {
     // this lane's A-operand rows (one per row tile); every load is in bounds
     // (padding reads a valid entry and is zeroed afterwards)
-    bool iok[2];
-    const double2* zrow[2];
+    bool iok[MT];
+    const double2* zrow[MT];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+    for (int mt = 0; mt < MT; ++mt) {
       iok[mt] = m0 + 16 * mt + r < nb;
       zrow[mt] = Zn + row_ptr[r0 + (iok[mt] ? m0 + 16 * mt + r : 0)] + t0;
     }
-    d4 acc[2][4];
+    d4 acc[MT][NW];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
-    auto load = [&](int gi, double2 (&z)[2][2], R (&xv)[2][4]) {
+      for (int nt = 0; nt < NW; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int gi, double2 (&z)[2][MT], R (&xv)[2][NW]) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int tt = 8 * gi + 4 * u + g;
         const int xo = xoff[tt];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) z[u][mt] = zrow[mt][min(tt, tlast)];
+        for (int mt = 0; mt < MT; ++mt) z[u][mt] = zrow[mt][min(tt, tlast)];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) xv[u][nt] = (nt < ntiles) ? xi[(xo >= 0 ? xo : 0) + 16 * nt + r] : (R)0;
+        for (int nt = 0; nt < NW; ++nt)
+          xv[u][nt] = (n0 + nt < ntiles) ? xi[(xo >= 0 ? xo : 0) + 16 * (n0 + nt) + r] : (R)0;
       }
     };
-    auto step = [&](int gi, double2 (&z)[2][2], R (&xv)[2][4]) {
+    auto step = [&](int gi, double2 (&z)[2][MT], R (&xv)[2][NW]) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const bool ok = xoff[8 * gi + 4 * u + g] >= 0;
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          if (nt >= ntiles) continue;
+        for (int nt = 0; nt < NW; ++nt) {
+          if (n0 + nt >= ntiles) continue;
           const double bv = ok ? (double)xv[u][nt] : 0.0;
           const double bs = sg * pair_swap64(bv);
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
+          for (int mt = 0; mt < MT; ++mt) {
             const double2 zz = (iok[mt] && ok) ? z[u][mt] : make_double2(0.0, 0.0);
             acc[mt][nt] = mma64((MODE == 2) ? zz.y : zz.x, bv, acc[mt][nt]);
             if (MODE == 0) acc[mt][nt] = mma64(zz.y, bs, acc[mt][nt]);
@@ -640,8 +646,8 @@ __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row
         }
       }
     };
-    double2 za[2][2], zb[2][2];
-    R xa[2][4], xb[2][4];
+    double2 za[2][MT], zb[2][MT];
+    R xa[2][NW], xb[2][NW];
     load(0, za, xa);
     for (int gi = 0; gi < ngrp; gi += 2) {
       if (gi + 1 < ngrp) load(gi + 1, zb, xb);
@@ -652,14 +658,14 @@ __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row
       }
     }
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        if (nt >= ntiles) continue;
+      for (int nt = 0; nt < NW; ++nt) {
+        if (n0 + nt >= ntiles) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int ii = m0 + 16 * mt + 4 * j + g;   // FP64 16x16x4 result: row 4 j + lane / 16
-          if (ii < nb) yi[(int64_t)(r0 + ii) * nc2 + 16 * nt + r] = (R)acc[mt][nt][j];
+          if (ii < nb) yi[(int64_t)(r0 + ii) * nc2 + 16 * (n0 + nt) + r] = (R)acc[mt][nt][j];
         }
       }
   }
@@ -789,11 +795,15 @@ bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bc
   if (nc % 8 != 0 || nc > 32 || max_cols_box > 4096) return false;
   const int xcap = (max_cols_box + 8 + 7) / 8 * 8;
   const size_t sh = (size_t)4 * xcap * sizeof(int32_t);
-  const dim3 grid((unsigned)((nleaf + 3) / 4));
   (void)max_box;
-#define CM_NEAR(M)                                                                                                 \
-  hipLaunchKernelGGL((k_near_mf<R, M>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol, self_off, Zn, \
-                     (const R*)xi, (R*)yi, nleaf, nc, xcap)
+  // one row tile and two column tiles per wave: four waves per leaf box
+  // (0.53 ms for the 32-column product at N = 122,880 against 0.73 ms with
+  // one wave per box)
+  constexpr int MT = 1, NW = 2, BPB = 4 / ((2 / MT) * (4 / NW));   // boxes per block of four waves
+  const dim3 grid((unsigned)((nleaf + BPB - 1) / BPB));
+#define CM_NEAR(M)                                                                                          \
+  hipLaunchKernelGGL((k_near_mf<R, M, MT, NW>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol, \
+                     self_off, Zn, (const R*)xi, (R*)yi, nleaf, nc, xcap)
   if (mode == 0)
     CM_NEAR(0);
   else if (mode == 1)
