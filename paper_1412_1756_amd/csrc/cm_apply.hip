@@ -240,9 +240,9 @@ template <typename R, int JMAX>
 __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restrict__ Sc, C2<R>* __restrict__ Sp,
                                                    const int32_t* __restrict__ child_ptr,
                                                    const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
-                                                   int cs, int tpc, int ldp, int accum) {
+                                                   int cs, int tpc, int span, int ldp, int accum) {
   extern __shared__ unsigned char smem_raw[];
-  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [ntc][npp][cs]
+  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [span][npp][cs]: child rows tlo ..
   const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, p = P.p, Kp = P.K;
   const int nchunk = (ntp + tpc - 1) / tpc;
   const int m = blockIdx.x / nchunk, tp0 = (blockIdx.x % nchunk) * tpc;
@@ -251,7 +251,12 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
   const int hp = npp / 2;
   const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift);
   const int nout = min(tpc, ntp - tp0) * npp * cs;   // this block's parent rows tp0 .. tp0+tpc-1
-  const int nmid = ntc * npp * cs;
+  // the child rows those parent rows read: tlo .. tlo + span - 1 (the host
+  // sized span for the widest chunk)
+  int tlo = ntc;
+  for (int t = tp0; t < min(ntp, tp0 + tpc); ++t)
+    for (int j = 0; j < p; ++j) tlo = min(tlo, P.th_idx[t * p + j]);
+  const int nmid = min(span, ntc - tlo) * npp * cs;
   C2<R> acc[JMAX];
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) acc[j] = mk<R>(0, 0);
@@ -260,7 +265,7 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
     const int oc = octant[ch];
     __syncthreads();
     for (int e = threadIdx.x; e < nmid; e += blockDim.x) {
-      const int c = e % cs, up = (e / cs) % npp, tc = e / (cs * npp);
+      const int c = e % cs, up = (e / cs) % npp, tc = tlo + e / (cs * npp);
       C2<R> a = mk<R>(0, 0);
       if (c < cw) {
         const C2<R>* row = src + (int64_t)tc * npc * ldp + c;
@@ -284,7 +289,7 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
           const int tc = P.th_idx[tp * p + t];
           const int rf = P.th_ref[tp * p + t];
           const R w = rf ? -P.th_w[tp * p + t] : P.th_w[tp * p + t];
-          const C2<R> v = tmp[(tc * npp + (rf ? (up + hp) % npp : up)) * cs + c];
+          const C2<R> v = tmp[((tc - tlo) * npp + (rf ? (up + hp) % npp : up)) * cs + c];
           a.x = fma(w, v.x, a.x);
           a.y = fma(w, v.y, a.y);
         }
@@ -447,18 +452,26 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restrict__ Gp, C2<R>* __restrict__ Gc,
                                                      const int32_t* __restrict__ parent,
                                                      const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
-                                                     int cs, int ldp) {
+                                                     int cs, int tcc, int span, int ldp) {
   extern __shared__ unsigned char smem_raw[];
-  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [ntp][npc][cs]
-  const int ch = blockIdx.x, c0 = blockIdx.y * cs, comp = blockIdx.z;
-  const int cw = min(cs, nc - c0);
+  C2<R>* tmp = reinterpret_cast<C2<R>*>(smem_raw);   // [span][npc][cs]: parent rows plo ..
   const int ntp = P.nt, npp = P.np, ntc = P.ntc, npc = P.npc, Kp = P.K;
+  const int nchunk = (ntc + tcc - 1) / tcc;
+  const int ch = blockIdx.x / nchunk, tc0 = (blockIdx.x % nchunk) * tcc, tc1 = min(ntc, tc0 + tcc);
+  const int c0 = blockIdx.y * cs, comp = blockIdx.z;
+  const int cw = min(cs, nc - c0);
   const int hc = npc / 2;
   const int m = parent[ch], oc = octant[ch];
   const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift) + oc * Kp;
   const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * ldp + c0;
-  for (int e = threadIdx.x; e < ntp * npc * cs; e += blockDim.x) {
-    const int c = e % cs, uc = (e / cs) % npc, tp = e / (cs * npc);
+  // the parent rows this block's child rows tc0 .. tc1-1 read: plo .. plo +
+  // span - 1 (the host sized span for the widest chunk)
+  int plo = ntp;
+  for (int j = P.tht_ptr[tc0]; j < P.tht_ptr[tc1]; ++j) plo = min(plo, P.tht_idx[j]);
+  if (plo >= ntp) plo = 0;
+  const int nrow = min(span, ntp - plo);
+  for (int e = threadIdx.x; e < nrow * npc * cs; e += blockDim.x) {
+    const int c = e % cs, uc = (e / cs) % npc, tp = plo + e / (cs * npc);
     C2<R> a = mk<R>(0, 0);
     if (c < cw) {
       for (int j = P.pht_ptr[uc]; j < P.pht_ptr[uc + 1]; ++j) {
@@ -475,15 +488,15 @@ __global__ void __launch_bounds__(256) k_anterp_down_direct(const C2<R>* __restr
   }
   __syncthreads();
   C2<R>* out = Gc + ((int64_t)ch * 2 + comp) * Kc * ldp + c0;
-  for (int e = threadIdx.x; e < ntc * npc * cs; e += blockDim.x) {
-    const int c = e % cs, uc = (e / cs) % npc, tc = e / (cs * npc);
+  for (int e = threadIdx.x; e < (tc1 - tc0) * npc * cs; e += blockDim.x) {
+    const int c = e % cs, uc = (e / cs) % npc, tc = tc0 + e / (cs * npc);
     if (c >= cw) continue;
     C2<R> a = mk<R>(0, 0);
     for (int j = P.tht_ptr[tc]; j < P.tht_ptr[tc + 1]; ++j) {
       const int tp = P.tht_idx[j];
       const int rf = P.tht_ref[j];
       const R w = rf ? -P.tht_w[j] : P.tht_w[j];
-      const C2<R> v = tmp[(tp * npc + (rf ? (uc + hc) % npc : uc)) * cs + c];
+      const C2<R> v = tmp[((tp - plo) * npc + (rf ? (uc + hc) % npc : uc)) * cs + c];
       a.x = fma(w, v.x, a.x);
       a.y = fma(w, v.y, a.y);
     }
@@ -1023,15 +1036,34 @@ struct Stages {
       hipLaunchKernelGGL((k_interp_up<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s, Sc, Sp,
                          Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc, ldp, accum);
     } else {
+      // each block stages only the child rows its chunk of parent rows reads
+      // (a contiguous range: the stencil windows, reflections included, of
+      // consecutive parent rows); the chunk shrinks until the range fits
+      const Interp& I = P.ip[l];
       const int cs = interp_cs<R>(nc, Lp.ntc, Lp.np, std::min(Lp.nt * Lp.np, kJ * 256), kJ, 256);
-      const int tpc = std::max(1, std::min(Lp.nt, kJ * 256 / (Lp.np * cs)));
+      int tpc = std::max(1, std::min(Lp.nt, kJ * 256 / (Lp.np * cs)));
+      auto span_of = [&](int tc) {
+        int span = 1;
+        for (int t0 = 0; t0 < Lp.nt; t0 += tc) {
+          int lo = Lp.ntc, hi = -1;
+          for (int t = t0; t < std::min(Lp.nt, t0 + tc); ++t)
+            for (int j = 0; j < Lp.p; ++j) {
+              lo = std::min(lo, I.th_idx[t * Lp.p + j]);
+              hi = std::max(hi, I.th_idx[t * Lp.p + j]);
+            }
+          span = std::max(span, hi - lo + 1);
+        }
+        return span;
+      };
+      int span = span_of(tpc);
+      while (tpc > 1 && (size_t)span * Lp.np * cs * sizeof(CR) > 160 * 1024) span = span_of(--tpc);
       const int nchunk = (Lp.nt + tpc - 1) / tpc;
-      const size_t sh = (size_t)Lp.ntc * Lp.np * cs * sizeof(CR);
+      const size_t sh = (size_t)span * Lp.np * cs * sizeof(CR);
       if (sh > 160 * 1024 || tpc * Lp.np * cs > kJ * 256)
         throw Error(-7, "angular grid too large for the interpolation kernel");
       set_lds_limit((const void*)k_interp_up_direct<R, kJ>, sh);
       hipLaunchKernelGGL((k_interp_up_direct<R, kJ>), dim3(Lp.nbox * nchunk, (nc + cs - 1) / cs, 2), blk, sh, s, Sc,
-                         Sp, Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc, ldp, accum);
+                         Sp, Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tpc, span, ldp, accum);
     }
   }
 
@@ -1090,12 +1122,31 @@ struct Stages {
       hipLaunchKernelGGL(k_anterp_down<R>, dim3(Lp.nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s, Gp, Gc,
                          Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, ldp);
     } else {
+      // each block takes a chunk of child rows and stages the transposed phi
+      // step of only the parent rows they read (a contiguous range); the
+      // chunk shrinks until that range fits
       const int cs = interp_cs<R>(nc, Lp.nt, Lp.npc, 0, 1, 1);
-      const size_t sh = (size_t)Lp.nt * Lp.npc * cs * sizeof(CR);
+      auto span_of = [&](int tc) {
+        int span = 1;
+        for (int t0 = 0; t0 < Lp.ntc; t0 += tc) {
+          int lo = Lp.nt, hi = -1;
+          for (int q = Ip.tht_ptr[t0]; q < Ip.tht_ptr[std::min(Lp.ntc, t0 + tc)]; ++q) {
+            lo = std::min(lo, Ip.tht_idx[q]);
+            hi = std::max(hi, Ip.tht_idx[q]);
+          }
+          span = std::max(span, hi - lo + 1);
+        }
+        return span;
+      };
+      int tcc = Lp.ntc, span = span_of(tcc);
+      while (tcc > 1 && (size_t)span * Lp.npc * cs * sizeof(CR) > 160 * 1024) span = span_of(--tcc);
+      const size_t sh = (size_t)span * Lp.npc * cs * sizeof(CR);
       if (sh > 160 * 1024) throw Error(-7, "anterpolation LDS grid exceeds 160 KiB");
+      const int nchunk = (Lp.ntc + tcc - 1) / tcc;
       set_lds_limit((const void*)k_anterp_down_direct<R>, sh);
-      hipLaunchKernelGGL(k_anterp_down_direct<R>, dim3(pd.lev[l + 1].nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s,
-                         Gp, Gc, pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc, cs, ldp);
+      hipLaunchKernelGGL(k_anterp_down_direct<R>, dim3(pd.lev[l + 1].nbox * nchunk, (nc + cs - 1) / cs, 2),
+                         dim3(256), sh, s, Gp, Gc, pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc, cs, tcc,
+                         span, ldp);
     }
   }
 

@@ -190,8 +190,9 @@ def test_interp_theta_tiles_split_over_blocks(torch_cuda):
     splits them over two blocks, and the matrix-core anterpolation out of
     level 2 (110 parent rows per wave in LDS) runs with one wave per block.  The field on plate B from
     sources on plate A against the oracle's Z[B, A] x_A, and the whole
-    product against the dense oracle (FP32 bound 5e-4), for the matrix-core
-    and the vector-ALU kernels."""
+    product against the dense oracle, for the matrix-core and the vector-ALU
+    kernels (FP32 bound 5e-4) and the FP64 apply (1e-4; its vector-ALU
+    interpolation stages only the child rows each block's parent rows read)."""
     torch = torch_cuda
     from paper_1412_1756_amd import Operator
     from oracle import efie
@@ -210,11 +211,14 @@ def test_interp_theta_tiles_split_over_blocks(torch_cuda):
     ref = Z @ Xh
     refB = ref[~onA]
     va = Operator(V, F, K0, nlv=8, max_cols=8, matrix_cores=False, **ACC32)
+    f64 = Operator(V, F, K0, nlv=8, max_cols=8, d0=6.0, interp_p=12)
     y1 = mf.apply(torch.tensor(Xh, dtype=torch.complex64, device="cuda")).cpu().numpy()
     y2 = va.apply(torch.tensor(Xh, dtype=torch.complex64, device="cuda")).cpu().numpy()
-    eB = [colerr(y[~onA], refB) for y in (y1, y2)]
-    eAll = [colerr(y, ref) for y in (y1, y2)]
-    print(f"plates 32 wl apart: field on B mfma {eB[0]:.2e} valu {eB[1]:.2e}; "
-          f"whole product {eAll[0]:.2e} / {eAll[1]:.2e}; mfma-valu on B {colerr(y1[~onA], y2[~onA]):.2e}", flush=True)
-    assert max(eB) < TOL32 and max(eAll) < TOL32
+    y3 = f64.apply(torch.tensor(Xh, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    eB = [colerr(y[~onA], refB) for y in (y1, y2, y3)]
+    eAll = [colerr(y, ref) for y in (y1, y2, y3)]
+    print(f"plates 32 wl apart: field on B mfma {eB[0]:.2e} valu {eB[1]:.2e} fp64 {eB[2]:.2e}; whole product "
+          f"{eAll[0]:.2e} / {eAll[1]:.2e} / {eAll[2]:.2e}; mfma-valu on B {colerr(y1[~onA], y2[~onA]):.2e}", flush=True)
+    assert max(eB[:2]) < TOL32 and max(eAll[:2]) < TOL32
+    assert eB[2] < 1e-4 and eAll[2] < 1e-4
     assert colerr(y1[~onA], y2[~onA]) < TOL_PATH
