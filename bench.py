@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--rows", type=int, default=16, help="oracle rows for error and CPU baseline")
     ap.add_argument("--err-cols", type=int, default=8, help="FP32 batch columns checked against the oracle rows")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no error, no CPU baseline)")
+    ap.add_argument("--no-eigs", action="store_true", help="skip the eigenmodes-per-hour measurement")
     return ap.parse_args()
 
 
@@ -115,6 +116,41 @@ def measured_traffic(stage, path_tag, cfg):
     if h.hexdigest() != rec["source_sha256"]:
         return None
     return rec["read_bytes"] + rec["write_bytes"]
+
+
+def eigs_small(no_cpu):
+    """Eigenmodes per hour on the 1,920-unknown sphere: the 10 smallest
+    characteristic values by implicitly restarted Arnoldi on Z^-1 R with
+    SAI-preconditioned GMRES inner solves, handle set-up + SAI build + IRA
+    timed together; beside it the oracle's dense fill + QZ on the host cores."""
+    import torch
+    import workloads
+    from paper_1412_1756_amd import Operator
+    V, F, spec = workloads.workload("sphere_r0.5_n1920")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = Operator(V, F, spec["k"], nlv=spec["nlv"], d0=6.0, interp_p=12, max_cols=1)
+    op.sai_build(0.01, 0.014, 0.18)
+    v0 = torch.tensor(workloads.cn01(op.N, 3), dtype=torch.complex128, device="cuda")
+    r = op.eigs(10, 30, v0, tol=1e-6, maxrestart=30, gmres_tol=1e-8, vectors=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"workload": "sphere_r0.5_n1920", "N": op.N, "modes": r["nconv"], "seconds": t,
+           "modes_per_hour": r["nconv"] / t * 3600.0, "op_products": r["n_op"], "gmres_iters": r["gmres_iters"],
+           "restarts": r["restarts"]}
+    if not no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle import efie, modes
+        cores = os.cpu_count() or 1
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            Z = efie.dense_Z(V, F, spec["k"])
+            lam = modes.qz_modes(Z.imag, Z.real, nev=10)
+            tc = time.perf_counter() - t0
+        out["max_abs_diff_vs_qz"] = float(np.max(np.abs(np.sort(r["lam"].real) - np.sort(lam.real))))
+        out["cpu_oracle"] = {"seconds": tc, "modes_per_hour": 10 / tc * 3600.0, "cores": cores,
+                             "kind": "oracle dense fill + QZ"}
+    return out
 
 
 def main():
@@ -236,6 +272,8 @@ def main():
                                "kind": "oracle",
                                "sample": f"{a.rows} of {N} rows of Z filled by the FP64 oracle and applied to x "
                                          f"({t_rows:.1f} s), extrapolated x N/{a.rows} to one full Z.x"}
+    if not a.no_eigs:
+        out["eigenmodes"] = eigs_small(a.no_cpu)
     print(json.dumps(out))
 
 
