@@ -118,6 +118,27 @@ def measured_traffic(stage, path_tag, cfg):
     return rec["read_bytes"] + rec["write_bytes"]
 
 
+def hbm_copy_rate(dev):
+    """Achievable HBM bandwidth on this GPU: a plain 2 GiB device-to-device
+    copy (2 x 2 GiB of traffic per copy), ten copies between HIP events."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.complex64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": gbs, "frac_of_peak": gbs * 1e9 / HBM_PEAK, "kernel": "device copy 2 GiB (torch copy_)"}
+
+
 def eigs_small(no_cpu):
     """Eigenmodes per hour on the 1,920-unknown sphere: the 10 smallest
     characteristic values by implicitly restarted Arnoldi on Z^-1 R with
@@ -272,6 +293,7 @@ def main():
                                "kind": "oracle",
                                "sample": f"{a.rows} of {N} rows of Z filled by the FP64 oracle and applied to x "
                                          f"({t_rows:.1f} s), extrapolated x N/{a.rows} to one full Z.x"}
+    out["hbm_achievable"] = hbm_copy_rate(dev)
     if not a.no_eigs:
         out["eigenmodes"] = eigs_small(a.no_cpu)
     print(json.dumps(out))

@@ -157,6 +157,34 @@ def test_plate_small_leaf_error_is_bounded(torch_cuda):
     assert e < 1e-3
 
 
+def test_config3_plate_sampled_rows(torch_cuda):
+    """The 10 x 10 wavelength plate (0.1-wavelength cells, 29,800 unknowns, 6
+    levels, 0.3125-wavelength leaves) on 16 oracle rows, with the two-box
+    buffer at the two finest levels: FP64 vector (d0 4, p 10) within 1e-4 and
+    the 32-column FP32 batch (d0 4.5, p 10) within 5e-4 on four of its
+    columns.  (With the one-box buffer the plate's cells reach far past their
+    leaf boxes: 6.2e-4 in FP64 at d0 6, 6.7e-4 in FP32.)"""
+    torch = torch_cuda
+    from oracle import efie
+    V, F, spec = workloads.workload("plate_10x10_n29800")
+    N = 29800
+    rows = np.sort(np.random.default_rng(2).choice(N, 16, replace=False))
+    Zr = efie.rows_Z(V, F, K0, rows)
+    Xh = workloads.cn01_block(N, 32, 100)
+    Xh[:, 0] = workloads.cn01(N, 0)
+    R = Zr @ Xh[:, :4]
+    op = _op(V, F, 6, dict(d0=4.0, interp_p=10), max_cols=1, wide_near=True)
+    y = op.apply(torch.tensor(Xh[:, 0], dtype=torch.complex128, device="cuda")).cpu().numpy()
+    e64 = relerr(y[rows], R[:, 0])
+    del op
+    op = _op(V, F, 6, dict(d0=4.5, interp_p=10), max_cols=32, wide_near=True)
+    Y = op.apply(torch.tensor(Xh, dtype=torch.complex64, device="cuda")).cpu().numpy()
+    e32 = relerr(Y[np.ix_(rows, np.arange(4))], R)
+    print(f"plate 10x10 nlv6 two-box: fp64 {e64:.3e} fp32-batched {e32:.3e}", flush=True)
+    assert e64 < TOL64
+    assert e32 < TOL32
+
+
 @pytest.mark.parametrize("wide", [False, True])
 def test_sphere_r1_sampled_rows(torch_cuda, wide):
     """7,680 unknowns, 4 levels: sampled oracle rows; with and without the
