@@ -531,7 +531,9 @@ bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const 
                int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
                hipStream_t s) {
   if (nc % 8 != 0 || max_box > 64) return false;
-  constexpr int NTL = 4;
+  // two column tiles per pass: the LDS reduction buffer (4 waves x MTU x
+  // NTL x 4 floats per lane) then leaves room for four blocks per CU
+  constexpr int NTL = 2;
 #define CM_DIS(MTU)                                                                                            \
   hipLaunchKernelGGL((k_disagg_mf<MTU, NTL>), dim3(nbox), dim3(256), (size_t)4 * MTU * NTL * 4 * 64 * 4, s,   \
                      (const float2*)V, (const float*)G, ldp, qwc, (const float*)yi, box_start, perm, K, nc,   \
@@ -569,7 +571,7 @@ __device__ __forceinline__ double pair_swap64(double v) {
 // the four column tiles of 16 reals (x rows gathered from memory and
 // converted to FP64), so each near-field value is loaded by 4 / NW waves.
 // Complex steps as in the leaf aggregation: C += Re(A) B + Im(A) B~.
-// nc <= 32.
+// Columns beyond 32 take further blocks (grid y); nc <= 64.
 template <typename R, int MODE, int MT, int NW>
 __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ box_start,
@@ -584,7 +586,8 @@ __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row
   constexpr int WM = 2 / MT, WB = WM * (4 / NW);   // waves per box (row halves x column groups)
   const int b = blockIdx.x * (4 / WB) + w / WB;
   const int mh = (MT == 1) ? 16 * (w % WM) : 0;    // first row of this wave's tile in each 32
-  const int n0 = NW * ((w % WB) / WM);             // first column tile of this wave
+  // first column tile of this wave (grid y: groups of four column tiles, 32 columns)
+  const int n0 = 4 * (int)blockIdx.y + NW * ((w % WB) / WM);
   if (b >= nleaf) return;
   int32_t* xoff = xoff_all + w * xcap;
   const int r0 = box_start[b], nb = box_start[b + 1] - r0;
@@ -792,7 +795,7 @@ template <typename R>
 bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
              const int32_t* self_off, const double2* Zn, const void* xi, void* yi, int nleaf, int max_box,
              int max_cols_box, int nc, int mode, hipStream_t s) {
-  if (nc % 8 != 0 || nc > 32 || max_cols_box > 4096) return false;
+  if (nc % 8 != 0 || nc > 64 || max_cols_box > 4096) return false;
   const int xcap = (max_cols_box + 8 + 7) / 8 * 8;
   const size_t sh = (size_t)4 * xcap * sizeof(int32_t);
   (void)max_box;
@@ -800,7 +803,7 @@ bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bc
   // (0.53 ms for the 32-column product at N = 122,880 against 0.73 ms with
   // one wave per box)
   constexpr int MT = 1, NW = 2, BPB = 4 / ((2 / MT) * (4 / NW));   // boxes per block of four waves
-  const dim3 grid((unsigned)((nleaf + BPB - 1) / BPB));
+  const dim3 grid((unsigned)((nleaf + BPB - 1) / BPB), (unsigned)((nc + 31) / 32));
 #define CM_NEAR(M)                                                                                          \
   hipLaunchKernelGGL((k_near_mf<R, M, MT, NW>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol, \
                      self_off, Zn, (const R*)xi, (R*)yi, nleaf, nc, xcap)

@@ -222,3 +222,19 @@ def test_interp_theta_tiles_split_over_blocks(torch_cuda):
     assert max(eB[:2]) < TOL32 and max(eAll[:2]) < TOL32
     assert eB[2] < 1e-4 and eAll[2] < 1e-4
     assert colerr(y1[~onA], y2[~onA]) < TOL_PATH
+
+
+def test_batch_of_64_columns_equals_two_of_32(torch_cuda, sphere2):
+    """A 64-column batch (the near-field product takes a second column group
+    of blocks) gives the same columns, bit for bit, as two 32-column batches
+    through the same handle: every kernel treats column tiles independently."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = sphere2
+    op = Operator(V, F, K0, nlv=5, max_cols=64, **ACC32)
+    X = torch.tensor(workloads.cn01_block(op.N, 64, 1100), dtype=torch.complex64, device="cuda")
+    for opname in ("Z", "R", "X"):
+        Y = op.apply(X, op=opname)
+        Y1 = op.apply(X[:, :32].contiguous(), op=opname)
+        Y2 = op.apply(X[:, 32:].contiguous(), op=opname)
+        assert torch.equal(Y[:, :32], Y1) and torch.equal(Y[:, 32:], Y2), opname
