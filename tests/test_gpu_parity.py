@@ -428,6 +428,42 @@ def test_autograd_backward_matches_dense_gradient(torch_cuda, cfg1_deriv):
     assert ek < 10 * TOL64
 
 
+def test_config3_autograd_sampled_rows(torch_cuda):
+    """Forward and autograd backward on the 10 x 10 wavelength plate (29,800
+    unknowns, 6 levels, two-box buffer, FP64) with a loss that reads 16
+    sampled outputs, L = Re sum_{i in S} conj(c_i) y_i, so that both
+    gradients follow from the oracle's rows S of Z and dZ/dk: x.grad =
+    Z[S, :]^H c_S (every entry, through the adjoint pass) and k.grad =
+    Re c_S^H dZ[S, :] x (through the dual pass).  Bounds: 1e-4 for the
+    product and its adjoint, 1e-3 for dZ/dk through interpolation."""
+    torch = torch_cuda
+    from oracle import efie
+    from paper_1412_1756_amd.autograd import z_apply
+    V, F, spec = workloads.workload("plate_10x10_n29800")
+    N = 29800
+    rows = np.sort(np.random.default_rng(2).choice(N, 16, replace=False))
+    Zr, dZr = efie.rows_Z(V, F, K0, rows, deriv=True)
+    op = _op(V, F, 6, dict(d0=4.0, interp_p=10), max_cols=2, deriv=True, wide_near=True)
+    x0 = workloads.cn01(N, 0)
+    c = workloads.cn01(N, 1)
+    m = np.zeros(N)
+    m[rows] = 1.0
+    x = torch.tensor(x0, dtype=torch.complex128, device="cuda", requires_grad=True)
+    k = torch.tensor(K0, dtype=torch.float64, device="cuda", requires_grad=True)
+    cm = torch.tensor(c * m, dtype=torch.complex128, device="cuda")
+    y = z_apply(op, x, k)
+    loss = (cm.conj() * y).real.sum()
+    loss.backward()
+    ey = relerr(y.detach().cpu().numpy()[rows], Zr @ x0)
+    gx_ref = Zr.conj().T @ c[rows]
+    gk_ref = float(np.real(np.vdot(c[rows], dZr @ x0)))
+    ex = relerr(x.grad.cpu().numpy(), gx_ref)
+    ek = abs(k.grad.item() - gk_ref) / abs(gk_ref)
+    print(f"plate autograd: y {ey:.2e}, x.grad {ex:.2e}, k.grad {ek:.2e}", flush=True)
+    assert ey < TOL64 and ex < TOL64
+    assert ek < 1e-3
+
+
 def test_dlambda_dk_matches_oracle(torch_cuda, cfg1_deriv):
     """d lambda/dk of the TE1 and TE2 clusters from IRA Ritz vectors and the
     dZ/dk pass, against the oracle (dense QZ vectors and dense dZ/dk, cluster
