@@ -1187,7 +1187,21 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   const int conj = (op == 3);
   const int kind = (op == 1) ? 1 : (op == 2) ? 2 : 0;   // 0 Z, 1 R, 2 X
   const int ldp = dual ? 2 * nc : nc;                   // pattern column stride
+  // Concurrent schedule (not with stage timing or the dual pass): the near
+  // field runs on aux[0] and the translations of levels lf .. 3 on aux[1],
+  // each level's as soon as its patterns exist, while the main stream runs
+  // the critical path aggregate -> interpolation -> M2L at level 2 ->
+  // anterpolation -> disaggregation; both auxiliary streams join the main
+  // stream before the first kernel that reads their results.
+  const bool fork = !d.timing && !dual && d.aux[0] && d.aux[1] && d.fork_ev.size() >= (size_t)(4 + lf);
+  hipStream_t sA = fork ? d.aux[0] : s, sB = fork ? d.aux[1] : s;
+  auto fork_to = [&](hipStream_t from, hipStream_t to, int e) {
+    if (!fork) return;
+    chk(hipEventRecord(d.fork_ev[e], from), "hipEventRecord");
+    chk(hipStreamWaitEvent(to, d.fork_ev[e], 0), "hipStreamWaitEvent");
+  };
   Stages<R> st{d, P, pd, s};
+  Stages<R> stB{d, P, pd, sB};
   {
     int64_t tot = N * nc;
     stage_begin(d, s, 0);
@@ -1195,41 +1209,60 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
                        d.perm, xi, N, conj);
     stage_end(d, s);
   }
+  fork_to(s, sA, 0);
   const dim3 rows_grid((unsigned)((N + 3) / 4));
-  stage_begin(d, s, 1);
+  stage_begin(d, sA, 1);
   bool near_done = false;
   if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES)) {
     if (sizeof(R) == 4 && (P.opt.flags & CM_FLAG_NEAR_FP32))
       near_done = mf_near32(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off, dual ? d.dZn32 : d.Zn32,
-                            (const float2*)xi, (float2*)yi, d.nleaf, d.max_near_cols, nc, kind, s);
+                            (const float2*)xi, (float2*)yi, d.nleaf, d.max_near_cols, nc, kind, sA);
     else
       near_done = mf_near<R>(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off,
                              (const double2*)(dual ? d.dZn : d.Zn), xi, yi, d.nleaf, d.max_box, d.max_near_cols, nc,
-                             kind, s);
+                             kind, sA);
   }
   if (near_done) {
   } else if (nc % 4 == 0 && nc <= 64)
-    hipLaunchKernelGGL(k_near_box<R>, dim3(d.nleaf), dim3(256), 0, s, d.row_ptr, d.box_start, d.bcol_ptr, d.bcol,
+    hipLaunchKernelGGL(k_near_box<R>, dim3(d.nleaf), dim3(256), 0, sA, d.row_ptr, d.box_start, d.bcol_ptr, d.bcol,
                        d.self_off, (const double2*)(dual ? d.dZn : d.Zn), (const CR*)xi, yi, nc, kind);
   else
-    hipLaunchKernelGGL(k_near<R>, rows_grid, dim3(256), 0, s, d.row_ptr, d.box_of, d.bcol_ptr, d.bcol, d.self_off,
+    hipLaunchKernelGGL(k_near<R>, rows_grid, dim3(256), 0, sA, d.row_ptr, d.box_of, d.bcol_ptr, d.bcol, d.self_off,
                        d.box_start, (const double2*)(dual ? d.dZn : d.Zn), (const CR*)xi, yi, N, nc, kind);
-  stage_end(d, s);
-  // upward pass
+  stage_end(d, sA);
+  if (fork) chk(hipEventRecord(d.fork_ev[1], sA), "hipEventRecord");   // near field done
+  // translations and downward pass: the translations of a level are stored,
+  // then the parent's anterpolated pattern is added onto them (the
+  // matrix-core kernel adds with one atomic per element, so the sum is still
+  // formed in a fixed order).
+  auto m2l_level = [&](Stages<R>& sx, hipStream_t ss, int l, int accum) {
+    LevelD<R>& Lv = pd.lev[l];
+    const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
+    stage_begin(d, ss, 4 + 10 * l);
+    sx.m2l(l, kind, T, (const CR*)d.S[l], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, accum);
+    if (dual) sx.m2l(l, 0, Lv.dTZ, (const CR*)d.S[l], (CR*)d.G[l] + nc, nc, ldp, 1);
+    stage_end(d, ss);
+  };
+  // upward pass; each level's translations start once its patterns exist
   stage_begin(d, s, 2);
   st.aggregate(pd.V, xi, nc, (CR*)d.S[lf], ldp, nc);
   if (dual) st.aggregate(pd.dV, xi, nc, (CR*)d.S[lf] + nc, ldp, nc);
   stage_end(d, s);
+  fork_to(s, sB, 2);
+  m2l_level(stB, sB, lf, 0);
   for (int l = lf - 1; l >= 2; --l) {
     stage_begin(d, s, 3 + 10 * l);
     st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l], dual ? 2 * nc : nc, ldp, 0, pd.lev[l].shift);
     if (dual) st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l] + nc, nc, ldp, 1, pd.lev[l].dshift);
     stage_end(d, s);
+    if (l >= 3) {
+      fork_to(s, sB, 3 + l);
+      m2l_level(stB, sB, l, 0);
+    } else {
+      m2l_level(st, s, l, 0);
+    }
   }
-  // translations and downward pass: the translations of a level are stored,
-  // then the parent's anterpolated pattern is added onto them (the
-  // matrix-core kernel adds with one atomic per element, so the sum is still
-  // formed in a fixed order).
+  fork_to(sB, s, 3);   // the translations of levels 3 .. lf are stored
   // matrix-core anterpolation where it covers the level (both kernels add
   // onto the child level's stored translations)
   auto mf_down = [&](int l) {
@@ -1237,15 +1270,6 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
       return !(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) && nc % 8 == 0 && mf_covers(pd.lev[l], nc);
     return false;
   };
-  auto m2l_level = [&](int l, int accum) {
-    LevelD<R>& Lv = pd.lev[l];
-    const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
-    stage_begin(d, s, 4 + 10 * l);
-    st.m2l(l, kind, T, (const CR*)d.S[l], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, accum);
-    if (dual) st.m2l(l, 0, Lv.dTZ, (const CR*)d.S[l], (CR*)d.G[l] + nc, nc, ldp, 1);
-    stage_end(d, s);
-  };
-  for (int l = 2; l <= lf; ++l) m2l_level(l, 0);
   for (int l = 2; l < lf; ++l) {
     stage_begin(d, s, 5 + 10 * (l + 1));
     if (mf_down(l)) {
@@ -1257,6 +1281,7 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     }
     stage_end(d, s);
   }
+  if (fork) chk(hipStreamWaitEvent(s, d.fork_ev[1], 0), "hipStreamWaitEvent");   // near field
   stage_begin(d, s, 6);
   if (dual) {
     // d/dk of (k^2 eta/4pi) sum w conj(V).G = (2/k)(...) + conj(dV).G + conj(V).dG

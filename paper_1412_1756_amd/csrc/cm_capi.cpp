@@ -290,6 +290,10 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   }
   d.xi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
   d.yi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
+  // streams and events of the concurrent apply
+  for (auto& a : d.aux) chk(hipStreamCreateWithFlags(&a, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  d.fork_ev.assign(4 + lf, nullptr);
+  for (auto& e : d.fork_ev) chk(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
   // autotuning of the matrix-core interpolation shapes at the batch width
   // (the largest multiple of 8 up to max_cols, at most 64) on zeroed workspace
   if ((P.opt.flags & CM_FLAG_AUTOTUNE) && !(P.opt.flags & CM_FLAG_NO_MATRIX_CORES) && d.max_cols >= 8) {
@@ -319,6 +323,13 @@ void dev_free(Dev& d) {
   }
   d.marks.clear();
   for (auto e : d.event_pool) (void)hipEventDestroy(e);
+  for (auto e : d.fork_ev) (void)hipEventDestroy(e);
+  d.fork_ev.clear();
+  for (auto& a : d.aux)
+    if (a) {
+      (void)hipStreamDestroy(a);
+      a = nullptr;
+    }
   d.event_pool.clear();
 }
 

@@ -108,6 +108,11 @@ struct Dev {
   };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> event_pool;
+  // concurrent apply: two auxiliary streams (default priority, non-blocking)
+  // for the near field and the translations off the critical path, and the
+  // fork/join events (timing disabled); null when not created
+  hipStream_t aux[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> fork_ev;
   std::vector<double> stage_ms;
   std::vector<int64_t> stage_calls;
   std::string tune_json;                    // autotuner's choices (empty when not tuned)

@@ -238,3 +238,21 @@ def test_batch_of_64_columns_equals_two_of_32(torch_cuda, sphere2):
         Y1 = op.apply(X[:, :32].contiguous(), op=opname)
         Y2 = op.apply(X[:, 32:].contiguous(), op=opname)
         assert torch.equal(Y[:, :32], Y1) and torch.equal(Y[:, 32:], Y2), opname
+
+
+def test_concurrent_schedule_equals_sequential(torch_cuda, ops):
+    """The apply runs the near field and the translations of levels 3 .. lf
+    on two auxiliary streams (joined before their results are read); with
+    per-stage timing on it runs everything on the caller's stream in
+    dependency order.  Both give the same result bit for bit (FP32 batch and
+    FP64 single vector), also over repeated back-to-back applies."""
+    torch = torch_cuda
+    mf, _ = ops
+    for dt, ncols in ((torch.complex64, 32), (torch.complex128, 1)):
+        X = torch.tensor(workloads.cn01_block(mf.N, ncols, 950), dtype=dt, device="cuda")
+        ys = [mf.apply(X).clone() for _ in range(3)]
+        mf.stage_timing(True)
+        yt = mf.apply(X).clone()
+        mf.stage_timing(False)
+        for y in ys:
+            assert torch.equal(y, yt)
