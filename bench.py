@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--err-cols", type=int, default=8, help="FP32 batch columns checked against the oracle rows")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no error, no CPU baseline)")
     ap.add_argument("--no-eigs", action="store_true", help="skip the eigenmodes-per-hour measurement")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 8-wavenumber sweep measurement")
     return ap.parse_args()
 
 
@@ -137,6 +138,38 @@ def hbm_copy_rate(dev):
     del src, dst
     torch.cuda.empty_cache()
     return {"GBps": gbs, "frac_of_peak": gbs * 1e9 / HBM_PEAK, "kernel": "device copy 2 GiB (torch copy_)"}
+
+
+def sweep_rate(V, F, k0, ncols, steps, d0, p):
+    """The wavenumber-sweep workload: one handle at 8 wavenumbers 0.9 k0 ..
+    1.1 k0 (a plan, tables and near field per wavenumber), a block of ncols
+    columns with column j at wavenumber j mod 8, FP32 far field, autotuned;
+    column-matvecs/s over `steps` applies between HIP events."""
+    import torch
+    import workloads
+    from paper_1412_1756_amd import Operator
+    ks = list(np.linspace(0.9, 1.1, 8) * k0)
+    t0 = time.perf_counter()
+    sw = Operator(V, F, ks, nlv=6, d0=d0, interp_p=p, max_cols=ncols, autotune=True)
+    t_build = time.perf_counter() - t0
+    X = torch.tensor(workloads.cn01_block(sw.N, ncols, 100), dtype=torch.complex64, device="cuda")
+    Y = torch.empty_like(X)
+    kidx = np.arange(ncols, dtype=np.int32) % 8
+    sw.apply(X, out=Y, k_index=kidx)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sw.apply(X, out=Y, k_index=kidx)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del sw
+    torch.cuda.empty_cache()
+    return {"workload": "sphere_r4_n122880, 8 wavenumbers 0.9-1.1 k0, column j at j mod 8", "ncols": ncols,
+            "ms_per_apply": ms, "column_matvecs_per_s": ncols * 1000.0 / ms, "setup_s": t_build,
+            "d0": d0, "interp_p": p}
 
 
 def eigs_small(no_cpu):
@@ -294,6 +327,10 @@ def main():
                                "sample": f"{a.rows} of {N} rows of Z filled by the FP64 oracle and applied to x "
                                          f"({t_rows:.1f} s), extrapolated x N/{a.rows} to one full Z.x"}
     out["hbm_achievable"] = hbm_copy_rate(dev)
+    if not a.no_sweep:
+        del op32, op64
+        torch.cuda.empty_cache()
+        out["sweep_8k"] = sweep_rate(V, F, k, a.ncols, max(3, a.steps // 2), a.d0, a.p)
     if not a.no_eigs:
         out["eigenmodes"] = eigs_small(a.no_cpu)
     print(json.dumps(out))

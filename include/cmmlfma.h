@@ -154,9 +154,10 @@ cm_status cm_rwg_table(const cm_handle* h, int32_t* edge_v, int32_t* tri_pm);
 /* y = op(x) on ncols columns (1 <= ncols <= max_cols).  k_index: NULL (all
    columns at k[0]) or a host array of ncols indices into the handle's k
    array, column j being applied at k[k_index[j]] (columns sharing a
-   wavenumber are gathered into one batched apply; a batch at a single
-   wavenumber runs in place).  Asynchronous on hip_stream; CM_E_BADARG for an
-   index outside [0, n_k). */
+   wavenumber are gathered into one batched apply, padded with zero columns
+   to a multiple of 8 where max_cols allows, so that it takes the
+   matrix-core kernels; a batch at a single wavenumber runs in place).
+   Asynchronous on hip_stream; CM_E_BADARG for an index outside [0, n_k). */
 cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols,
                    const int32_t* k_index, cm_dtype dt, void* hip_stream);
 

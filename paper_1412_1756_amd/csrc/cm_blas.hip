@@ -93,40 +93,45 @@ __global__ void __launch_bounds__(256) k_to_c128(const float2* __restrict__ x, d
 
 // xs[i][j] = x[i][cols[j]] (xs dense, ld = cols.n); ys -> y the other way
 template <typename C>
-__global__ void __launch_bounds__(256) k_gather_cols(const C* __restrict__ x, int64_t ld, ColList cols,
+__global__ void __launch_bounds__(256) k_gather_cols(const C* __restrict__ x, int64_t ld, ColList cols, int ws,
                                                      C* __restrict__ xs, int64_t N) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N * cols.n) return;
-  const int64_t i = e / cols.n;
-  const int j = (int)(e - i * cols.n);
-  xs[e] = x[i * ld + cols.c[j]];
+  if (e >= N * ws) return;
+  const int64_t i = e / ws;
+  const int j = (int)(e - i * ws);
+  C v;
+  v.x = 0;
+  v.y = 0;
+  xs[e] = (j < cols.n) ? x[i * ld + cols.c[j]] : v;   // columns past the list: zero padding
 }
 template <typename C>
-__global__ void __launch_bounds__(256) k_scatter_cols(const C* __restrict__ ys, ColList cols, C* __restrict__ y,
-                                                      int64_t ld, int64_t N) {
+__global__ void __launch_bounds__(256) k_scatter_cols(const C* __restrict__ ys, int ws, ColList cols,
+                                                      C* __restrict__ y, int64_t ld, int64_t N) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N * cols.n) return;
   const int64_t i = e / cols.n;
   const int j = (int)(e - i * cols.n);
-  y[i * ld + cols.c[j]] = ys[e];
+  y[i * ld + cols.c[j]] = ys[i * ws + j];
 }
 
 static inline dim3 g1(int64_t N) { return dim3((unsigned)((N + 255) / 256)); }
 
-void blas_gather_cols(const void* x, int64_t ld, ColList cols, void* xs, int64_t N, bool fp64, hipStream_t s) {
+void blas_gather_cols(const void* x, int64_t ld, ColList cols, int ws, void* xs, int64_t N, bool fp64,
+                      hipStream_t s) {
   if (fp64)
-    hipLaunchKernelGGL(k_gather_cols<double2>, g1(N * cols.n), dim3(256), 0, s, (const double2*)x, ld, cols,
+    hipLaunchKernelGGL(k_gather_cols<double2>, g1(N * ws), dim3(256), 0, s, (const double2*)x, ld, cols, ws,
                        (double2*)xs, N);
   else
-    hipLaunchKernelGGL(k_gather_cols<float2>, g1(N * cols.n), dim3(256), 0, s, (const float2*)x, ld, cols,
+    hipLaunchKernelGGL(k_gather_cols<float2>, g1(N * ws), dim3(256), 0, s, (const float2*)x, ld, cols, ws,
                        (float2*)xs, N);
 }
-void blas_scatter_cols(const void* ys, ColList cols, void* y, int64_t ld, int64_t N, bool fp64, hipStream_t s) {
+void blas_scatter_cols(const void* ys, int ws, ColList cols, void* y, int64_t ld, int64_t N, bool fp64,
+                       hipStream_t s) {
   if (fp64)
-    hipLaunchKernelGGL(k_scatter_cols<double2>, g1(N * cols.n), dim3(256), 0, s, (const double2*)ys, cols,
+    hipLaunchKernelGGL(k_scatter_cols<double2>, g1(N * cols.n), dim3(256), 0, s, (const double2*)ys, ws, cols,
                        (double2*)y, ld, N);
   else
-    hipLaunchKernelGGL(k_scatter_cols<float2>, g1(N * cols.n), dim3(256), 0, s, (const float2*)ys, cols,
+    hipLaunchKernelGGL(k_scatter_cols<float2>, g1(N * cols.n), dim3(256), 0, s, (const float2*)ys, ws, cols,
                        (float2*)y, ld, N);
 }
 

@@ -377,6 +377,9 @@ static void destroy_handle(cm_handle* h) {
   h->sub.clear();
   if (h->xs) (void)hipFree(h->xs);
   if (h->ys) (void)hipFree(h->ys);
+  if (h->ks_in) (void)hipEventDestroy(h->ks_in);
+  if (h->ks_out) (void)hipEventDestroy(h->ks_out);
+  if (h->ks) (void)hipStreamDestroy(h->ks);
   cm::dev_free(h->dev);
   delete h;
 }
@@ -419,8 +422,15 @@ cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64
         h->sub.push_back(build_handle(xyz, n_vert, tri, n_tri, k[i], op, o->flags, (hipStream_t)hip_stream));
       if (n_k > 1 && h->has_dev) {
         const size_t b = (size_t)h->dev.N * h->dev.max_cols * 16;
-        if (hipMalloc(&h->xs, b) != hipSuccess || hipMalloc(&h->ys, b) != hipSuccess)
-          throw cm::Error(CM_E_OOM, "sweep staging buffers");
+        for (int i = 0; i < n_k; ++i) {
+          cm_handle* t = i == 0 ? h : h->sub[i - 1];
+          if (hipMalloc(&t->xs, b) != hipSuccess || hipMalloc(&t->ys, b) != hipSuccess)
+            throw cm::Error(CM_E_OOM, "sweep staging buffers");
+          if (hipStreamCreateWithFlags(&t->ks, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&t->ks_in, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&t->ks_out, hipEventDisableTiming) != hipSuccess)
+            throw cm::Error(CM_E_HIP, "sweep stream and events");
+        }
       }
     } catch (...) {
       destroy_handle(h);
@@ -481,20 +491,30 @@ cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, i
       cm::dev_apply(t->dev, t->plan, (int)op, x, y, ld, ncols, fp64, s);
       return CM_OK;
     }
-    // gather the columns of each wavenumber, apply, scatter back
+    // gather the columns of each wavenumber into that wavenumber's staging
+    // block, apply and scatter back, each wavenumber on its own stream (forked
+    // from and joined to the caller's stream by events)
+    auto ok = [](hipError_t e) {
+      if (e != hipSuccess) throw cm::Error(CM_E_HIP, std::string("sweep: ") + hipGetErrorString(e));
+    };
+    ok(hipEventRecord(h->ks_in, s));
     for (int kk = 0; kk < nk; ++kk) {
       cm::ColList cl;
       cl.n = 0;
-      for (int j = 0; j <= ncols; ++j) {
-        if (j < ncols && k_index[j] == kk) cl.c[cl.n++] = j;
-        if (cl.n == 64 || (j == ncols && cl.n > 0)) {
-          cm_handle* t = at(kk);
-          cm::blas_gather_cols(x, ld, cl, h->xs, h->dev.N, fp64, s);
-          cm::dev_apply(t->dev, t->plan, (int)op, h->xs, h->ys, cl.n, cl.n, fp64, s);
-          cm::blas_scatter_cols(h->ys, cl, y, ld, h->dev.N, fp64, s);
-          cl.n = 0;
-        }
-      }
+      for (int j = 0; j < ncols; ++j)
+        if (k_index[j] == kk) cl.c[cl.n++] = j;
+      if (cl.n == 0) continue;
+      cm_handle* t = at(kk);
+      // staging width padded with zero columns to a multiple of 8 where the
+      // buffers allow it, so the batch takes the matrix-core kernels
+      const int w8 = (cl.n + 7) / 8 * 8;
+      const int ws = (w8 <= h->dev.max_cols) ? w8 : cl.n;
+      ok(hipStreamWaitEvent(t->ks, h->ks_in, 0));
+      cm::blas_gather_cols(x, ld, cl, ws, t->xs, h->dev.N, fp64, t->ks);
+      cm::dev_apply(t->dev, t->plan, (int)op, t->xs, t->ys, ws, ws, fp64, t->ks);
+      cm::blas_scatter_cols(t->ys, ws, cl, y, ld, h->dev.N, fp64, t->ks);
+      ok(hipEventRecord(t->ks_out, t->ks));
+      ok(hipStreamWaitEvent(s, t->ks_out, 0));
     }
     if (hipGetLastError() != hipSuccess) throw cm::Error(CM_E_HIP, "sweep gather/scatter launch");
     return CM_OK;

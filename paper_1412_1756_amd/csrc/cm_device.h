@@ -174,8 +174,13 @@ struct ColList {
   int n;
   int c[64];
 };
-void blas_gather_cols(const void* x, int64_t ld, ColList cols, void* xs, int64_t N, bool fp64, hipStream_t s);
-void blas_scatter_cols(const void* ys, ColList cols, void* y, int64_t ld, int64_t N, bool fp64, hipStream_t s);
+// gather the listed columns of x into the staging block xs (N x ws, ws >=
+// cols.n; columns past the list are zero) / scatter the first cols.n columns
+// of ys (N x ws) back to the listed columns of y
+void blas_gather_cols(const void* x, int64_t ld, ColList cols, int ws, void* xs, int64_t N, bool fp64,
+                      hipStream_t s);
+void blas_scatter_cols(const void* ys, int ws, ColList cols, void* y, int64_t ld, int64_t N, bool fp64,
+                       hipStream_t s);
 }  // namespace cm
 
 // the opaque handle of the C ABI; a wavenumber sweep keeps one handle per
@@ -185,5 +190,10 @@ struct cm_handle {
   cm::Dev dev;
   bool has_dev = false;
   std::vector<cm_handle*> sub;
-  void *xs = nullptr, *ys = nullptr;   // N x max_cols complex128 each (sweeps only)
+  // sweeps (n_k > 1), on every wavenumber's handle: staging blocks N x
+  // max_cols complex128 each, and a stream (default priority) with two
+  // events so that the wavenumbers' batched applies run concurrently
+  void *xs = nullptr, *ys = nullptr;
+  hipStream_t ks = nullptr;
+  hipEvent_t ks_in = nullptr, ks_out = nullptr;
 };
