@@ -26,8 +26,12 @@
  *    stored and applied in FP64), CM_C128 = complex double (all FP64).
  *    The caller owns x and y; they must not alias.  y is overwritten.
  *  - Streams.  cm_apply / cm_sai_apply enqueue work on the given HIP stream
- *    (NULL = default stream) and return without synchronising.  cm_create and
- *    cm_sai_build block until their device work is done.
+ *    (NULL = default stream) and return without synchronising.  Inside an
+ *    apply the library forks work to streams of its own (created with the
+ *    handle, default priority) and joins them back to the given stream with
+ *    events before the call's last kernel, so the given stream alone orders
+ *    the call against the caller's other work.  cm_create and cm_sai_build
+ *    block until their device work is done.
  *  - Errors.  Every call returns a cm_status; no exception crosses the ABI.
  *    cm_last_error() returns a thread-local message for the last failure.
  *  - Threads.  One handle must not be used by two host threads at once, and

@@ -982,9 +982,17 @@ std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, c
                         hipStream_t s) {
   std::ostringstream js;
   js << "[";
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+  // the two timing events, destroyed on every way out
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess)
     throw Error(-4, "hipEventCreate (autotune)");
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   auto time_it = [&](auto&& launch) -> float {
     if (!launch()) return -1.f;
     if (hipEventRecord(e0, s) != hipSuccess) throw Error(-4, "hipEventRecord (autotune)");
@@ -1062,8 +1070,6 @@ std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, c
       first = false;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   js << "]";
   return js.str();
 }
