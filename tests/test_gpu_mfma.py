@@ -256,3 +256,34 @@ def test_concurrent_schedule_equals_sequential(torch_cuda, ops):
         mf.stage_timing(False)
         for y in ys:
             assert torch.equal(y, yt)
+
+
+def test_apply_replays_from_a_captured_graph(torch_cuda, ops):
+    """The apply (with its fork/join over the library's streams) captured once
+    into a HIP graph through torch.cuda.graph and replayed: every replay, with
+    a new input copied into the captured buffer and eager work and
+    synchronisations between the replays, equals the eager apply bit for bit
+    (FP32 batch and FP64 vector)."""
+    torch = torch_cuda
+    mf, _ = ops
+    for dt, ncols in ((torch.complex64, 32), (torch.complex128, 1)):
+        X = torch.zeros((mf.N, ncols), dtype=dt, device="cuda")
+        Y = torch.zeros_like(X)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            mf.apply(X, out=Y, stream=s)            # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            mf.apply(X, out=Y)
+        for seed in (1201, 1202, 1203):
+            Xh = torch.tensor(workloads.cn01_block(mf.N, ncols, seed), dtype=dt, device="cuda")
+            X.copy_(Xh)
+            g.replay()
+            torch.cuda.synchronize()
+            yg = Y.clone()
+            ye = mf.apply(Xh)                       # eager, between the replays
+            torch.cuda.synchronize()
+            assert torch.equal(yg, ye), (dt, seed)
