@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-eigs", action="store_true", help="skip the eigenmodes-per-hour measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 8-wavenumber sweep measurement")
     ap.add_argument("--no-d0-3", action="store_true", help="skip the 3-digit truncation measurement")
+    ap.add_argument("--no-sai", action="store_true", help="skip the SAI build and apply measurement")
     return ap.parse_args()
 
 
@@ -327,6 +328,27 @@ def main():
                                "kind": "oracle",
                                "sample": f"{a.rows} of {N} rows of Z filled by the FP64 oracle and applied to x "
                                          f"({t_rows:.1f} s), extrapolated x N/{a.rows} to one full Z.x"}
+    if not a.no_sai:
+        # SAI preconditioner apply (FP64 CSR, the FP64 handle's near-field pattern)
+        t0 = time.perf_counter()
+        op64.sai_build(0.01, 0.014, 0.18)
+        t_sai = time.perf_counter() - t0
+        nnz_p = op64.sai_nnz()
+        Ys = torch.empty_like(X64)
+        op64.sai_apply(X64, out=Ys)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            op64.sai_apply(X64, out=Ys)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_sai = e0.elapsed_time(e1) / 20
+        sai_bytes = nnz_p * 20 + (N + 1) * 8 + 2 * N * 16
+        out["sai_apply"] = {"nnz": nnz_p, "ms": ms_sai, "alg_bytes": sai_bytes,
+                            "GBps": sai_bytes / (ms_sai * 1e-3) / 1e9, "frac_of_hbm_peak": sai_bytes / (ms_sai * 1e-3) / HBM_PEAK,
+                            "build_s": t_sai, "thresholds": [0.01, 0.014, 0.18]}
     if not a.no_d0_3:
         # the workload's named truncation (3 digits, eq. (30)) on the same batch: faster, and
         # past the FP32 error bound on this tree (stated, not the headline)

@@ -154,6 +154,12 @@ class Operator:
     def sai_build(self, eps1=0.01, eps2=0.014, eps3=0.18):
         check(lib().cm_sai_build(self._h, eps1, eps2, eps3))
 
+    def sai_nnz(self):
+        """Stored entries of the SAI matrix (after sai_build)."""
+        nnz = C.c_int64()
+        check(lib().cm_export_near(self._h, 2, C.byref(nnz), None, None, None))
+        return int(nnz.value)
+
     def sai_apply(self, x, out=None, stream=None):
         X, Y, dt, squeeze = self._vec_args(x, out)
         st = lib().cm_sai_apply(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.stride(0),
