@@ -202,6 +202,13 @@ def test_sphere_r1_sampled_rows(torch_cuda, wide):
         e = relerr(y[rows], Zr @ x)
         print(f"r1 nlv4 wide={wide} {dt}: {e:.3e}", flush=True)
         assert e < tol
+        # R (sin kernel; with the two-box buffer the neighbouring leaf boxes
+        # out to distance 2 are translated) and X, against Re Z and Im Z rows
+        for opname, part in (("R", Zr.real), ("X", Zr.imag)):
+            yo = op.apply(torch.tensor(x, dtype=dt, device="cuda"), op=opname).cpu().numpy()
+            eo = relerr(yo[rows], part @ x)
+            print(f"  op {opname}: {eo:.3e}", flush=True)
+            assert eo < (2 * tol if opname == "X" else tol)
 
 
 def test_config2_sampled_rows(torch_cuda):
