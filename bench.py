@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the 8-wavenumber sweep measurement")
     ap.add_argument("--no-d0-3", action="store_true", help="skip the 3-digit truncation measurement")
     ap.add_argument("--no-sai", action="store_true", help="skip the SAI build and apply measurement")
+    ap.add_argument("--no-r", action="store_true",
+                    help="skip the R x measurement (sibling against standard translation lists)")
     return ap.parse_args()
 
 
@@ -238,9 +240,9 @@ def main():
     Y64 = torch.empty_like(X64)
     torch.cuda.synchronize()
 
-    def timed(op, X, Y, steps, warm, stage_timing=True):
+    def timed(op, X, Y, steps, warm, stage_timing=True, opname="Z"):
         for _ in range(warm):
-            op.apply(X, out=Y)
+            op.apply(X, op=opname, out=Y)
         torch.cuda.synchronize()
         op.stage_timing(stage_timing)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -248,7 +250,7 @@ def main():
         t0 = time.perf_counter()
         e0.record()
         for _ in range(steps):
-            op.apply(X, out=Y)
+            op.apply(X, op=opname, out=Y)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -261,13 +263,35 @@ def main():
     ms64, wall64, _ = timed(op64, X64, Y64, a.steps, a.warmup, stage_timing=False)
     _, _, times32 = timed(op32, X32, Y32, max(3, a.steps // 4), 1)
     _, _, times64 = timed(op64, X64, Y64, max(3, a.steps // 4), 1)
+    ne = max(1, min(a.err_cols, a.ncols))
+    r_out = None
+    if not a.no_r:
+        # R x (sin kernel) on the same batch: the sibling lists of the FP32 handle
+        # against a handle with the standard MLFMA lists (same d0, p, tuning)
+        YR = torch.empty_like(X32)
+        msR, _, _ = timed(op32, X32, YR, a.steps, a.warmup, stage_timing=False, opname="R")
+        yR = YR[:, :ne].cpu().numpy().astype(np.complex128)
+        t0 = time.perf_counter()
+        opS = Operator(V, F, k, nlv=a.nlv, d0=a.d0, interp_p=a.p, max_cols=max(a.ncols, 1), wide_near=a.wide,
+                       autotune=not a.no_autotune, r_standard=True)
+        t_setup_s = time.perf_counter() - t0
+        msRs, _, _ = timed(opS, X32, YR, a.steps, a.warmup, stage_timing=False, opname="R")
+        yRs = YR[:, :ne].cpu().numpy().astype(np.complex128)
+        stS = opS.stats()
+        del opS, YR
+        torch.cuda.empty_cache()
+        pairs = lambda s_: {L["l"]: L["farR_pairs"] for L in s_["levels"] if L["l"] >= 2}
+        r_out = {"op": "R", "ncols": a.ncols, "dtype": "c64 far field / c128 near field",
+                 "siblings": {"ms_per_apply": msR, "column_matvecs_per_s": a.ncols * 1000.0 / msR,
+                              "translation_pairs": pairs(st)},
+                 "standard": {"ms_per_apply": msRs, "column_matvecs_per_s": a.ncols * 1000.0 / msRs,
+                              "translation_pairs": pairs(stS), "setup_s": t_setup_s}}
     if a.copy_calib:
         src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)       # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    ne = max(1, min(a.err_cols, a.ncols))
     y32 = Y32[:, :ne].cpu().numpy().astype(np.complex128)
     y64 = Y64[:, 0].cpu().numpy()
 
@@ -324,10 +348,16 @@ def main():
         out["config"]["rel_err_cols"] = ne
         out["fp64_single"]["rel_err"] = e64
         out["config"]["rel_err_rows"] = int(a.rows)
+        if r_out is not None:
+            refR = Zr.real @ Xh[:, :ne]
+            for key, yy in (("siblings", yR), ("standard", yRs)):
+                r_out[key]["rel_err"] = float(np.linalg.norm(yy[rows] - refR) / np.linalg.norm(refR))
         out["cpu_baseline"] = {"value": 1.0 / (t_rows / a.rows * N), "unit": "matvecs/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"{a.rows} of {N} rows of Z filled by the FP64 oracle and applied to x "
                                          f"({t_rows:.1f} s), extrapolated x N/{a.rows} to one full Z.x"}
+    if r_out is not None:
+        out["r_apply"] = r_out
     if not a.no_sai:
         # SAI preconditioner apply (FP64 CSR, the FP64 handle's near-field pattern)
         t0 = time.perf_counter()

@@ -66,8 +66,11 @@ typedef enum {
 
 typedef enum {
   CM_OP_Z = 0,      /* y = Z x                                                 */
-  CM_OP_R = 1,      /* y = R x   (sin kernel; near field = own leaf box only,
-                                  neighbouring leaf boxes translated, eq. (22)) */
+  CM_OP_R = 1,      /* y = R x   (sin kernel, eq. (22); near field = own leaf
+                                  box only.  Translations: between children
+                                  of the same parent at levels 3..leaf and
+                                  between all distinct level-2 boxes, unless
+                                  CM_FLAG_R_STANDARD)                        */
   CM_OP_X = 2,      /* y = X x   (cos kernel, eq. (18))                        */
   CM_OP_ZH = 3,     /* y = Z^H x = conj(Z conj(x))  (Z = Z^T)                  */
   CM_OP_DZDK = 4    /* y = (dZ/dk) x, tree and sampling frozen (needs
@@ -116,6 +119,13 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
                                   the summation grouping: results differ
                                   from an untuned handle by FP32 rounding,
                                   and the choice may differ between handles */
+#define CM_FLAG_R_STANDARD 128u /* R x with the standard MLFMA lists (the far
+                                  lists of Z at every level plus the
+                                  neighbouring leaf boxes) instead of the
+                                  sibling bookkeeping that the paper
+                                  recommends for R after eq. (22); same
+                                  operator, several times more leaf
+                                  translations                               */
 
 typedef struct {
   int32_t nlv;       /* number of octree levels including level 0 (>= 3)        */

@@ -11,7 +11,7 @@ CM_E_NOT_CONVERGED = -8
 OPS = {"Z": 0, "R": 1, "X": 2, "ZH": 3, "DZDK": 4}
 CM_C64, CM_C128 = 0, 1
 CM_FLAG_HOST_ONLY, CM_FLAG_DERIV, CM_FLAG_CHECK, CM_FLAG_NO_MATRIX_CORES, CM_FLAG_NEAR_FP32 = 1, 2, 4, 8, 16
-CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE = 32, 64
+CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD = 32, 64, 128
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
            "cm_sai_build", "cm_sai_apply", "cm_gmres", "cm_eigs", "cm_export_near", "cm_stats", "cm_stage_timing",

@@ -530,6 +530,15 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
   }
 
   // ---- far (translation) lists, levels 2..lf
+  // R (sin kernel, eq. (22)): its addition theorem holds at any separation, so
+  // a box needs no near field beyond itself.  Default bookkeeping (the one
+  // the paper recommends for R): at levels 3..lf a box translates from the
+  // other children of its parent only, and at the coarsest level (2 here,
+  // where the paper goes on to level 1) from every other box; each pair of
+  // distinct leaf boxes is then covered at the coarsest level where their
+  // ancestors differ.  Flag 128 selects the standard MLFMA lists instead
+  // (Z's far lists, plus the neighbouring boxes at the leaf level).
+  const bool r_std = (o.flags & 128u) != 0;
   for (int l = 2; l <= lf; ++l) {
     Level& Lv = lev[l];
     const Level& Pl = lev[l - 1];
@@ -538,6 +547,13 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     for (int m = 0; m < Lv.nbox; ++m) {
       std::vector<std::pair<int, int>> lst, lstR;
       int P = Lv.parent[m];
+      if (!r_std) {
+        const int c0 = (l == 2) ? 0 : Pl.child_ptr[P], c1 = (l == 2) ? Lv.nbox : Pl.child_ptr[P + 1];
+        for (int c = c0; c < c1; ++c)
+          if (c != m)
+            lstR.push_back({c, off_id(Lv.ijk[3 * m] - Lv.ijk[3 * c], Lv.ijk[3 * m + 1] - Lv.ijk[3 * c + 1],
+                                      Lv.ijk[3 * m + 2] - Lv.ijk[3 * c + 2])});
+      }
       // parents within the near radius of the level above; children beyond
       // this level's near radius are translated here
       const int pr = near_radius(l - 1), dfar = near_radius(l) + 1;
@@ -552,8 +568,8 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
                                Lv.ijk[3 * m + 2] - Lv.ijk[3 * c + 2]);
               if (dd >= dfar) {
                 lst.push_back({c, off});
-                lstR.push_back({c, off});
-              } else if (l == lf && dd >= 1) {
+                if (r_std) lstR.push_back({c, off});
+              } else if (r_std && l == lf && dd >= 1) {
                 lstR.push_back({c, off});   // R translates neighbouring leaf boxes too
               }
             }
@@ -858,7 +874,7 @@ std::string Plan::stats_json() const {
   std::ostringstream s;
   s.precision(17);
   s << "{\"N\": " << rwg.N << ", \"n_tri\": " << nt << ", \"k\": " << k << ", \"nlv\": " << nlv
-    << ", \"d0\": " << opt.d0 << ", \"interp_p\": " << opt.p << ", \"wide_near\": " << ((opt.flags & 32u) ? 1 : 0) << ", \"root_side\": " << side
+    << ", \"d0\": " << opt.d0 << ", \"interp_p\": " << opt.p << ", \"wide_near\": " << ((opt.flags & 32u) ? 1 : 0) << ", \"r_lists\": \"" << ((opt.flags & 128u) ? "standard" : "siblings") << "\"" << ", \"root_side\": " << side
     << ", \"nnz_near\": " << nnz << ", \"near_cols_total\": " << bcol.size()
     << ", \"n_leaf\": " << lev[lf].nbox << ", \"levels\": [";
   for (int l = 0; l <= lf; ++l) {

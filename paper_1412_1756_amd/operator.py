@@ -17,14 +17,16 @@ class Operator:
     GPU needed); deriv=True also builds dZ/dk tables; wide_near=True selects
     the two-box buffer at the two finest levels (CM_FLAG_WIDE_NEAR);
     autotune=True times the matrix-core interpolation variants per level at
-    create and keeps the fastest (CM_FLAG_AUTOTUNE).  k may
+    create and keeps the fastest (CM_FLAG_AUTOTUNE); r_standard=True gives
+    R x the standard MLFMA lists instead of the sibling bookkeeping
+    (CM_FLAG_R_STANDARD).  k may
     be a sequence of wavenumbers (a sweep; apply's k_index picks one per
     column).
     """
 
     def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
                  deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, wide_near=False,
-                 autotune=False, stream=None):
+                 autotune=False, r_standard=False, stream=None):
         L = lib()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -41,7 +43,8 @@ class Operator:
                    | (0 if matrix_cores else _lib.CM_FLAG_NO_MATRIX_CORES)
                    | (_lib.CM_FLAG_NEAR_FP32 if near_fp32 else 0)
                    | (_lib.CM_FLAG_WIDE_NEAR if wide_near else 0)
-                   | (_lib.CM_FLAG_AUTOTUNE if autotune else 0))
+                   | (_lib.CM_FLAG_AUTOTUNE if autotune else 0)
+                   | (_lib.CM_FLAG_R_STANDARD if r_standard else 0))
         kk = np.atleast_1d(np.asarray(k, dtype=np.float64)).copy()
         h = C.c_void_p()
         s = self._stream_ptr(stream) if not host_only else None

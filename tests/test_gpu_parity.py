@@ -240,6 +240,35 @@ def test_config2_sampled_rows(torch_cuda):
     assert e32 < TOL32
 
 
+def test_config2_R_sibling_and_standard_lists(torch_cuda):
+    """R x at N = 122,880 against the real parts of 12 oracle rows of Z, with
+    the sibling translation lists (default: children of one parent at levels
+    3..5, every other box at level 2) and with the standard MLFMA lists, at
+    the benchmark's settings: FP32 far field on 8 columns (d0 4.5, p 10) and
+    the FP64 vector (d0 4, p 10, two-box buffer)."""
+    torch = torch_cuda
+    from oracle import efie
+    V, F = workloads.icosphere(6, 4.0)
+    N = 122880
+    rows = np.sort(np.random.default_rng(5).choice(N, 12, replace=False))
+    Rr = efie.rows_Z(V, F, K0, rows).real
+    Xh = workloads.cn01_block(N, 8, 300)
+    for r_standard in (False, True):
+        op = _op(V, F, 6, dict(d0=4.5, interp_p=10), max_cols=8, r_standard=r_standard)
+        assert op.stats()["r_lists"] == ("standard" if r_standard else "siblings")
+        Y = op.apply(torch.tensor(Xh, dtype=torch.complex64, device="cuda"), op="R").cpu().numpy()
+        e32 = relerr(Y[rows], Rr @ Xh)
+        del op
+        op = _op(V, F, 6, dict(d0=4.0, interp_p=10), max_cols=1, wide_near=True, r_standard=r_standard)
+        y = op.apply(torch.tensor(Xh[:, 0], dtype=torch.complex128, device="cuda"), op="R").cpu().numpy()
+        e64 = relerr(y[rows], Rr @ Xh[:, 0])
+        del op
+        print(f"cfg2 R lists={'standard' if r_standard else 'siblings'}: fp64 {e64:.3e} fp32-batched {e32:.3e}",
+              flush=True)
+        assert e64 < TOL64
+        assert e32 < TOL32
+
+
 def test_config5_sampled_rows(torch_cuda):
     """N = 1,966,080 (radius 12 wavelengths, 8 levels, 0.1875-wavelength
     leaves, 790M near-field entries): the 32-column FP32 batch (d0 4.5, p 10,

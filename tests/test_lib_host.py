@@ -68,6 +68,21 @@ def _python_tree(V, F, nlv, wide=False):
         P = B // 2
         dp = np.abs(P[:, None, :] - P[None, :, :]).max(-1)
         far[l] = int(np.sum((d >= nr(l) + 1) & (dp <= nr(l - 1))))
+    # R lists: children of the same parent at levels 3..lf, every other box at
+    # level 2 (sibling bookkeeping), or the far pairs plus the leaf
+    # neighbours (standard)
+    farR_sib, farR_std = {}, {}
+    for l in range(2, lf + 1):
+        B = boxes[l]
+        if l == 2:
+            farR_sib[l] = len(B) * (len(B) - 1)
+        else:
+            _, cnt_p = np.unique(B // 2, axis=0, return_counts=True)
+            farR_sib[l] = int(np.sum(cnt_p * (cnt_p - 1)))
+        d = np.abs(B[:, None, :] - B[None, :, :]).max(-1)
+        dp = np.abs((B // 2)[:, None, :] - (B // 2)[None, :, :]).max(-1)
+        farR_std[l] = far[l] + (int(np.sum((d >= 1) & (d <= nr(l)) & (dp <= nr(l - 1)))) if l == lf else 0)
+    far["R_siblings"], far["R_standard"] = farR_sib, farR_std
     leafd = np.abs(leaf[:, None, :] - leaf[None, :, :]).max(-1)
     cnt = np.bincount([tuple(map(tuple, leaf)).index(tuple(x)) for x in ijk], minlength=len(leaf)) if len(leaf) < 400 else None
     nnz = None
@@ -94,12 +109,20 @@ def test_tree_and_lists_match_independent_count(mesh, wide):
     op = _op(V, F, nlv, check_coverage=True, wide_near=wide)
     st = op.stats()
     assert st["wide_near"] == int(wide)
+    assert st["r_lists"] == "siblings"
     nb, far, nnz = _python_tree(V, F, nlv, wide)
     for lv in st["levels"]:
         assert lv["nbox"] == nb[lv["l"]]
         if lv["l"] >= 2:
             assert lv["far_pairs"] == far[lv["l"]]
+            assert lv["farR_pairs"] == far["R_siblings"][lv["l"]]
     assert st["nnz_near"] == nnz
+    # the standard R lists (CM_FLAG_R_STANDARD) pass the same coverage check
+    st = _op(V, F, nlv, check_coverage=True, wide_near=wide, r_standard=True).stats()
+    assert st["r_lists"] == "standard"
+    for lv in st["levels"]:
+        if lv["l"] >= 2:
+            assert lv["farR_pairs"] == far["R_standard"][lv["l"]]
 
 
 def test_config2_plan_sizes():
