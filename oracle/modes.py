@@ -15,6 +15,11 @@ k-derivatives follow from the Wronskian j_n y_n' - j_n' y_n = 1/x^2:
 
 Table II of the paper lists values with this sign convention (negative for the
 electric-energy modes).
+
+Mode tracking over a frequency sweep (the plate sweep of section V follows
+each characteristic value from one frequency to the next; the paper does not
+say how modes are matched): modal correlation of the R-normalised real
+currents, maximised over all correspondences.
 """
 import numpy as np
 import scipy.linalg as sl
@@ -98,3 +103,29 @@ def dlambda_dk_cluster(J, lam, dX, dR, R):
     Q = J @ np.linalg.inv(Lc).T
     M = Q.T @ (dX - np.mean(lam) * dR) @ Q
     return np.sort(np.linalg.eigvalsh(0.5 * (M + M.T)))
+
+
+def modal_correlation(Ja, Jb, R):
+    """|Ja^T R Jb| normalised by the R-norms of the columns: 1 for the same
+    real current, 0 for R-orthogonal ones (characteristic currents at one
+    wavenumber are R-orthogonal, eq. (6))."""
+    na = np.sqrt(np.einsum("in,ij,jn->n", Ja, R, Ja))
+    nb = np.sqrt(np.einsum("in,ij,jn->n", Jb, R, Jb))
+    return np.abs(Ja.T @ R @ Jb) / np.outer(na, nb)
+
+
+def track_by_correlation(Ja, Jb, R):
+    """Correspondence of the modes at one wavenumber (columns of Ja) with
+    those at the next (columns of Jb): the permutation p maximising the sum of
+    modal correlations C[a, p[a]] (R taken at the second wavenumber), found by
+    trying every permutation (a handful of modes).  Returns (p, C[a, p[a]])."""
+    from itertools import permutations
+    C = modal_correlation(Ja, Jb, R)
+    n = C.shape[0]
+    best, best_s = None, -1.0
+    for p in permutations(range(C.shape[1]), n):
+        s = sum(C[a, p[a]] for a in range(n))
+        if s > best_s:
+            best, best_s = p, s
+    p = np.array(best)
+    return p, C[np.arange(n), p]

@@ -328,3 +328,59 @@ def test_near_singular_pair_vs_subdivided_quadrature(shared):
                 accv += WEIGHTS[p] * geo.area[To] * np.sum(g * ((pts - geo.tv[Ts][b]) @ (r - geo.tv[To][a])))
             assert abs(Sv[0, a, b] - accv) < 1e-4 * abs(accv)
         assert abs(S0[0] - acc0) < 1e-4 * abs(acc0)
+
+
+def test_track_by_correlation_recovers_a_shuffle():
+    """Modes at the 'next' wavenumber = a shuffled, sign-flipped, slightly
+    perturbed copy of the current ones: the brute-force correspondence finds
+    the shuffle, with correlations near 1."""
+    rng = np.random.default_rng(11)
+    n, m = 40, 5
+    A = rng.standard_normal((n, n))
+    R = A @ A.T + n * np.eye(n)
+    J = rng.standard_normal((n, m))
+    perm = np.array([3, 0, 4, 1, 2])
+    Jb = np.empty_like(J)
+    Jb[:, perm] = J * np.array([1, -1, 1, -1, 1])[None, :]
+    Jb += 0.02 * rng.standard_normal(Jb.shape)
+    p, c = modes.track_by_correlation(J, Jb, R)
+    np.testing.assert_array_equal(p, perm)
+    assert c.min() > 0.95
+    C = modes.modal_correlation(J, J, R)
+    np.testing.assert_allclose(np.diag(C), 1.0, rtol=1e-12)
+
+
+def test_plate_mode_tracking_agrees_with_dlambda_dk():
+    """A 1.0 m x 0.6 m plate (the paper's sweep geometry, coarse mesh) at 300
+    and 305 MHz: the modes matched by correlation are the ones the first-order
+    prediction lambda + (d lambda/dk) dk points to, even with the second
+    frequency's modes shuffled; the prediction error is second order."""
+    c0 = 299792458.0
+    V, F = workloads.plate(10, 6, 0.1)
+    k1, k2 = 2 * np.pi * 300e6 / c0, 2 * np.pi * 305e6 / c0
+    Z1, dZ1 = efie.dense_Z(V, F, k1, deriv=True)
+    Z2 = efie.dense_Z(V, F, k2)
+    l1, J1 = modes.qz_modes(Z1.imag, Z1.real, nev=4, vectors=True)
+    l2, J2 = modes.qz_modes(Z2.imag, Z2.real, nev=6, vectors=True)
+    l1, l2 = l1.real, l2.real
+    shuffle = np.array([4, 2, 0, 5, 1, 3])
+    l2s, J2s = l2[shuffle], J2[:, shuffle]
+    p, c = modes.track_by_correlation(J1, J2s, Z2.real)
+    d = modes.dlambda_dk(J1, l1, dZ1.imag, dZ1.real, Z1.real)
+    pred = l1 + d * (k2 - k1)
+    print("lambda(300 MHz)", l1, "predicted", pred, "tracked", l2s[p], "corr", c)
+    assert c.min() > 0.9
+    nearest = np.array([np.argmin(np.abs(l2s - q)) for q in pred])
+    np.testing.assert_array_equal(p, nearest)
+    step = np.abs(d * (k2 - k1))
+    err = np.abs(l2s[p] - pred)
+    assert np.all(err < 0.15 * step)
+    # second order: at half the step the prediction error drops about 4x
+    kh = 0.5 * (k1 + k2)
+    Zh = efie.dense_Z(V, F, kh)
+    lh, Jh = modes.qz_modes(Zh.imag, Zh.real, nev=6, vectors=True)
+    ph, ch = modes.track_by_correlation(J1, Jh, Zh.real)
+    errh = np.abs(lh.real[ph] - (l1 + d * (kh - k1)))
+    print("prediction error, full / half step", err, errh)
+    assert ch.min() > 0.9
+    assert np.all(errh < 0.35 * err)
