@@ -206,10 +206,14 @@ cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t restart, int32_
    complex characteristic values lambda = i (1 - 1/mu), largest |mu| (smallest
    |lambda|) first; ritz_resid[nev] (may be NULL) the relative Ritz residual
    estimates; J (device, may be NULL) the N x nev Ritz vectors, column-major,
-   unit 2-norm; *nconv the number with residual <= tol; counters[4] (may be
-   NULL): OP products, GMRES iterations, operator applies, restarts.  Returns
-   CM_E_NOT_CONVERGED if fewer than nev converged within maxrestart restarts.
-   Synchronises. */
+   unit 2-norm; *nconv the number with residual <= tol; counters[6] (may be
+   NULL): OP products, GMRES iterations, operator applies, restarts, inner
+   solves redone without the preconditioner, inner solves that missed
+   gmres_tol.  A preconditioned inner solve that misses gmres_tol within
+   gmres_maxit is redone once without the SAI (which can be nearly singular).
+   Returns CM_E_NOT_CONVERGED if fewer than nev converged within maxrestart
+   restarts, or if any inner solve missed gmres_tol (the Ritz values then
+   belong to an inexact OP).  Synchronises. */
 cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
                   int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond,
                   cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,

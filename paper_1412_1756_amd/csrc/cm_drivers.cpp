@@ -337,6 +337,8 @@ static void schur_vectors(const Mat& T, const Mat& Z, int n, Mat& Y) {
 struct EigsResult {
   int nconv = 0, restarts = 0;
   int64_t n_op = 0, gmres_iters = 0, n_matvec = 0;
+  int64_t inner_retries = 0;   // preconditioned solves that missed gm_tol, redone without P
+  int64_t inner_failures = 0;  // solves that missed gm_tol either way
   std::vector<cplx> mu;       // Ritz values of OP, largest magnitude first
   std::vector<double> resid;  // Ritz residual estimates |beta e_m^T y| / |mu|
 };
@@ -365,6 +367,16 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
       K.apply(1, V + (size_t)j * N, ru.d());
       GmresResult g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, precond);
       out.gmres_iters += g.iters;
+      if (!g.converged && precond) {
+        // the SAI can be nearly singular (e.g. the plate at low frequency,
+        // where the column-wise least squares leave Z P with condition
+        // number ~1e5): solve this product again without it
+        ++out.inner_retries;
+        g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, false);
+        out.gmres_iters += g.iters;
+      }
+      // an inexact OP product makes the Ritz residual estimates meaningless
+      if (!g.converged) ++out.inner_failures;
       ++out.n_op;
       double hn = K.orth(V, j + 1, f.d(), h);
       for (int k = 0; k <= j; ++k) at(H, ncv, k, j) = h[k];
@@ -489,8 +501,10 @@ extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t max
       counters[1] = r.gmres_iters;
       counters[2] = r.n_matvec;
       counters[3] = r.restarts;
+      counters[4] = r.inner_retries;
+      counters[5] = r.inner_failures;
     }
-    return r.nconv >= nev ? CM_OK : CM_E_NOT_CONVERGED;
+    return (r.nconv >= nev && r.inner_failures == 0) ? CM_OK : CM_E_NOT_CONVERGED;
   } catch (const cm::Error& e) {
     return cm::driver_fail(e.code, e.what());
   } catch (const std::exception& e) {

@@ -193,12 +193,14 @@ class Operator:
              precond=True, far="fp64", vectors=True, stream=None):
         """Characteristic values by implicitly restarted Arnoldi on Z^-1 R.
         v0: CUDA complex128 start vector.  Returns dict(lam, resid, J, nconv,
-        n_op, gmres_iters, n_matvec, restarts, converged)."""
+        n_op, gmres_iters, n_matvec, restarts, inner_retries, inner_failures,
+        converged); converged is False when fewer than nev Ritz values
+        converged or when an inner GMRES solve missed gmres_tol."""
         import torch
         v0 = v0.contiguous()
         lam = np.zeros(2 * nev)
         res = np.zeros(nev)
-        cnt = np.zeros(4, dtype=np.int64)
+        cnt = np.zeros(6, dtype=np.int64)
         J = torch.empty((nev, self.N), dtype=torch.complex128, device=v0.device) if vectors else None
         nconv = C.c_int32()
         st = lib().cm_eigs(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
@@ -210,4 +212,4 @@ class Operator:
             check(st)
         return dict(lam=lam[0::2] + 1j * lam[1::2], resid=res, J=(J.T if vectors else None), nconv=int(nconv.value),
                     n_op=int(cnt[0]), gmres_iters=int(cnt[1]), n_matvec=int(cnt[2]), restarts=int(cnt[3]),
-                    converged=(st == _lib.CM_OK))
+                    inner_retries=int(cnt[4]), inner_failures=int(cnt[5]), converged=(st == _lib.CM_OK))

@@ -528,3 +528,77 @@ def test_dlambda_dk_matches_oracle(torch_cuda, cfg1_deriv):
         print(f"TE{n}: dlam/dk {d} oracle {do} closed form {cf:.4f}", flush=True)
         assert np.abs(d - do).max() < 1e-3 * np.abs(do).max()
         assert abs(np.mean(d) - cf) < 0.15 * abs(cf)
+
+
+def test_plate_mode_tracking_matches_oracle(torch_cuda):
+    """The paper's plate sweep geometry (1.0 m x 0.6 m PEC plate, 1,085 RWG
+    unknowns, 3 levels) at 280, 300 and 320 MHz: IRA for five modes at each
+    frequency and the four smallest-|lambda| modes of 280 MHz followed by
+    tracking.track_modes (IRA, SAI, dZ/dk pass, correlation matching) against
+    the oracle (dense QZ at each frequency, brute-force correlation matching
+    over seven candidates, dense dZ/dk): characteristic values within 1e-3,
+    the same correspondence, d lambda/dk within 1e-3 relative."""
+    torch = torch_cuda
+    from oracle import efie, modes
+    from paper_1412_1756_amd import Operator
+    from paper_1412_1756_amd.tracking import track_modes
+    c0 = 299792458.0
+    V, F = workloads.plate(25, 15, 0.04)
+    ks = [2 * np.pi * f / c0 for f in (280e6, 300e6, 320e6)]
+    nev, ntrack = 5, 4
+
+    def make_op(k):
+        return Operator(V, F, k, nlv=3, max_cols=16, deriv=True, **ACC64)
+
+    N = make_op(ks[0]).N
+    v0 = torch.tensor(workloads.cn01(N, 3), dtype=torch.complex128, device="cuda")
+    t = track_modes(make_op, ks, nev, 20, v0, ntrack=ntrack, tol=1e-8, maxrestart=60, gmres_tol=1e-10)
+    assert all(t["converged"])
+    # oracle: QZ at every frequency (two spare modes so a mode may move past the fifth)
+    lam_o, d_o = [], []
+    Jp = None
+    for i, k in enumerate(ks):
+        Z, dZ = efie.dense_Z(V, F, k, deriv=True)
+        lo, Jo = modes.qz_modes(Z.imag, Z.real, nev=nev + 2, vectors=True)
+        lo = lo.real
+        if Jp is None:
+            p = np.arange(ntrack)
+        else:
+            p, c = modes.track_by_correlation(Jp, Jo, Z.real)
+            assert c.min() > 0.9
+        lam_o.append(lo[p])
+        d_o.append(modes.dlambda_dk(Jo[:, p], lo[p], dZ.imag, dZ.real, Z.real))
+        Jp = Jo[:, p]
+    lam_o, d_o = np.array(lam_o), np.array(d_o)
+    print("tracked lambda", t["lam"], "oracle", lam_o, "corr", t["corr"], flush=True)
+    print("dlambda/dk", t["dldk"], "oracle", d_o, flush=True)
+    assert np.abs(t["lam"] - lam_o).max() < 1e-3 * max(1.0, np.abs(lam_o).max())
+    assert np.abs(t["dldk"] - d_o).max() < 1e-3 * np.abs(d_o).max()
+    assert t["corr"].min() > 0.9
+
+
+def test_plate_low_frequency_eigs_redo_inner_solves_without_sai(torch_cuda):
+    """At 220 MHz the SAI of the 1.0 m x 0.6 m plate (thresholds 0.01 / 0.014
+    / 0.18) leaves Z P with condition number ~1e5 (the oracle's SAI shows the
+    same), and preconditioned GMRES stalls near residual 0.87.  cm_eigs must
+    redo those inner solves without the preconditioner and still return the
+    QZ characteristic values; with a budget too small for the unpreconditioned
+    solves it must report non-convergence instead of Ritz values of an
+    inexact operator."""
+    torch = torch_cuda
+    from oracle import efie, modes
+    from paper_1412_1756_amd import Operator
+    V, F = workloads.plate(25, 15, 0.04)
+    k = 2 * np.pi * 220e6 / 299792458.0
+    op = Operator(V, F, k, nlv=3, max_cols=4, **ACC64)
+    op.sai_build(0.01, 0.014, 0.18)
+    v0 = torch.tensor(workloads.cn01(op.N, 3), dtype=torch.complex128, device="cuda")
+    r = op.eigs(4, 16, v0, tol=1e-8, maxrestart=40, gmres_tol=1e-9, gmres_maxit=3000, vectors=False)
+    Z = efie.dense_Z(V, F, k)
+    lo = modes.qz_modes(Z.imag, Z.real, nev=4).real
+    print("220 MHz eigs", np.sort(r["lam"].real), "qz", np.sort(lo), "retries", r["inner_retries"],
+          "failures", r["inner_failures"], flush=True)
+    assert r["inner_retries"] > 0 and r["inner_failures"] == 0 and r["converged"]
+    assert np.abs(np.sort(r["lam"].real) - np.sort(lo)).max() < 1e-3
+    r = op.eigs(4, 16, v0, tol=1e-8, maxrestart=2, gmres_tol=1e-9, gmres_maxit=50, vectors=False)
+    assert r["inner_failures"] > 0 and not r["converged"]
