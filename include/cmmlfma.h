@@ -219,6 +219,27 @@ cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, do
                   cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
                   int64_t* counters, void* hip_stream);
 
+/* Characteristic modes by Jacobi-Davidson on the pencil X J = lambda R J
+   (eq. (6)) with the R-orthonormal search space and the projected correction
+   equation of eqs. (28)-(29): no inner solve with Z or X, each correction an
+   approximate solution by inner_steps unpreconditioned GMRES steps (one R and
+   one X apply each).  Finds the nev characteristic values closest to target
+   (0 for the significant modes); the search space holds at most mmax vectors
+   and restarts from the mmin Ritz vectors nearest the target.  A pair is
+   accepted when ||X u - theta R u|| <= tol max(1, |theta|) ||R u||, then
+   locked (deflated).  v0: device start vector (N complex128; the caller
+   draws it).  Outputs (host): lambda[nev] real characteristic values in the
+   order found; resid[nev] (may be NULL) their relative residuals; J (device,
+   may be NULL) the N x nev eigenvectors, column-major, R-normalised
+   (J^H R J = I); *nconv the number found; counters[3] (may be NULL): outer
+   iterations, inner GMRES steps, operator applies.  Returns
+   CM_E_NOT_CONVERGED when fewer than nev were found within maxit outer
+   iterations (the first *nconv outputs are valid), CM_E_NUMERIC when an
+   expansion vector has no R-norm (R is singular on it).  Synchronises. */
+cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t mmax, int32_t maxit, double tol,
+                int32_t inner_steps, const void* v0, cm_dtype far_dtype, double* lambda, double* resid, void* J,
+                int32_t* nconv, int64_t* counters, void* hip_stream);
+
 /* Copy the near-field matrix to host (public unknown order, CSR by row):
    row_ptr (N+1, int64), col (nnz, int32), val (nnz complex128 interleaved).
    Pass NULLs to query *nnz only.  which = 0: Z_near, 1: dZ_near/dk,

@@ -446,6 +446,255 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
   return out;
 }
 
+// ---------------------------------------------------------------- Jacobi-Davidson on the pencil (X, R)
+// Eigenpairs X J = lambda R J of the characteristic-mode pencil (eq. (6))
+// without inverting Z or X (eqs. (28)-(29)): an R-orthonormal search space V,
+// Ritz pairs of the Hermitian projection V^H X V (V^H R V = I), the Ritz value
+// closest to the target selected, and the space expanded by an approximate
+// solution t (a fixed number of unpreconditioned GMRES steps) of the
+// projected correction equation
+//   (I - R Qu Qu^H)(X - theta R)(I - Qu Qu^H R) t = -(X u - theta R u),
+// with Qu = [locked eigenvectors, u], t R-orthogonal to Qu.  Converged pairs
+// are locked (deflation); the space restarts from the mmin Ritz vectors
+// nearest the target when it reaches mmax.
+
+// Eigenvalues (ascending) and eigenvectors (columns of S) of a small
+// Hermitian matrix by cyclic complex Jacobi rotations.
+static void herm_eig(Mat A, int n, std::vector<double>& w, Mat& S) {
+  S.assign((size_t)n * n, cplx(0));
+  for (int i = 0; i < n; ++i) at(S, n, i, i) = 1;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int c = 0; c < n; ++c)
+      for (int r = 0; r < n; ++r) {
+        double a2 = std::norm(at(A, n, r, c));
+        tot += a2;
+        if (r != c) off += a2;
+      }
+    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        cplx apq = at(A, n, p, q);
+        double ab = std::abs(apq);
+        if (ab == 0) continue;
+        double app = at(A, n, p, p).real(), aqq = at(A, n, q, q).real();
+        // rotate so that the (p, q) entry vanishes: with apq = |apq| e^{i phi},
+        // G = [[c, -s e^{i phi}], [s e^{-i phi}, c]] applied as A <- G^H A G
+        cplx ph = apq / ab;
+        double tau = (aqq - app) / (2 * ab);
+        double t = (tau >= 0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1 + tau * tau));
+        double c = 1 / std::sqrt(1 + t * t), sn = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q of A and S
+          cplx akp = at(A, n, k, p), akq = at(A, n, k, q);
+          at(A, n, k, p) = c * akp - sn * std::conj(ph) * akq;
+          at(A, n, k, q) = sn * ph * akp + c * akq;
+          cplx skp = at(S, n, k, p), skq = at(S, n, k, q);
+          at(S, n, k, p) = c * skp - sn * std::conj(ph) * skq;
+          at(S, n, k, q) = sn * ph * skp + c * skq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q of A
+          cplx apk = at(A, n, p, k), aqk = at(A, n, q, k);
+          at(A, n, p, k) = c * apk - sn * ph * aqk;
+          at(A, n, q, k) = sn * std::conj(ph) * apk + c * aqk;
+        }
+        at(A, n, p, q) = at(A, n, q, p) = 0;
+      }
+  }
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return at(A, n, a, a).real() < at(A, n, b, b).real(); });
+  Mat S2((size_t)n * n);
+  w.resize(n);
+  for (int c = 0; c < n; ++c) {
+    w[c] = at(A, n, ord[c], ord[c]).real();
+    for (int r = 0; r < n; ++r) at(S2, n, r, c) = at(S, n, r, ord[c]);
+  }
+  S.swap(S2);
+}
+
+struct JdResult {
+  std::vector<double> lam, resid;
+  int nconv = 0, outer = 0;
+  int64_t inner_steps = 0, n_apply = 0;
+};
+
+static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int maxit, double tol, int inner,
+                   const double2* v0, double2* Jout) {
+  const int64_t N = K.N();
+  hipStream_t s = K.stream();
+  DevBuf Vb((size_t)mmax * N * sizeof(double2)), XVb((size_t)mmax * N * sizeof(double2)),
+      RVb((size_t)mmax * N * sizeof(double2)), Tmp((size_t)mmax * N * sizeof(double2)),
+      Qb((size_t)(nev + 1) * N * sizeof(double2)), RQb((size_t)(nev + 1) * N * sizeof(double2)),
+      t(N * sizeof(double2)), Rt(N * sizeof(double2)), Xt(N * sizeof(double2)), r(N * sizeof(double2)),
+      Xu(N * sizeof(double2)), y(N * sizeof(double2)), Ry(N * sizeof(double2)),
+      Gb((size_t)(inner + 1) * N * sizeof(double2)), gw(N * sizeof(double2)), hd(1024 * sizeof(double2));
+  double2 *V = Vb.d(), *XV = XVb.d(), *RV = RVb.d(), *Q = Qb.d(), *RQ = RQb.d();
+  JdResult out;
+  std::vector<double2> hh(1024);
+  auto dots = [&](const double2* A, int nk, const double2* w) {   // A^H w, nk <= 1024, on the host
+    blas_multidot(A, N, w, N, nk, hd.d(), s);
+    chk_d(hipMemcpyAsync(hh.data(), hd.p, nk * sizeof(double2), hipMemcpyDeviceToHost, s), "jd dots");
+    chk_d(hipStreamSynchronize(s), "jd dots");
+  };
+  // w -= B (A^H w) for the nk columns of A, B
+  auto project = [&](const double2* A, const double2* B, int nk, double2* w) {
+    if (nk == 0) return;
+    blas_multidot(A, N, w, N, nk, hd.d(), s);
+    blas_gemv_sub(B, N, hd.d(), nk, w, N, s);
+  };
+  auto copy = [&](const double2* x, double2* z, size_t n) {
+    chk_d(hipMemcpyAsync(z, x, n * sizeof(double2), hipMemcpyDeviceToDevice, s), "jd copy");
+  };
+  // basis restart / deflation: M <- M S[:, c0 .. c0 + nc)
+  auto recombine = [&](double2* M, int m, const Mat& S, int c0, int nc) {
+    Mat Sc((size_t)m * nc);
+    for (int c = 0; c < nc; ++c)
+      for (int r2 = 0; r2 < m; ++r2) Sc[(size_t)c * m + r2] = S[(size_t)(c0 + c) * m + r2];
+    K.combine(M, m, Sc, m, nc, Tmp.d());
+    copy(Tmp.d(), M, (size_t)nc * N);
+  };
+  copy(v0, t.d(), N);
+  int k = 0, m = 0;
+  Mat H;   // m x m, V^H X V
+  std::vector<double> w;
+  Mat S;
+  while (out.outer < maxit) {
+    ++out.outer;
+    // R-orthonormalise t against the locked vectors and V (two passes)
+    for (int pass = 0; pass < 2; ++pass) {
+      project(RQ, Q, k, t.d());
+      project(RV, V, m, t.d());
+    }
+    K.apply(1, t.d(), Rt.d());
+    dots(t.d(), 1, Rt.d());
+    double nr = std::sqrt(std::max(hh[0].x, 0.0));
+    if (!(nr > 1e-300)) throw Error(-6, "Jacobi-Davidson: expansion vector has no R-norm");
+    K.scale_copy(t.d(), 1.0 / nr, V + (size_t)m * N);
+    K.scale_copy(Rt.d(), 1.0 / nr, RV + (size_t)m * N);
+    K.apply(2, V + (size_t)m * N, XV + (size_t)m * N);
+    dots(V, m + 1, XV + (size_t)m * N);
+    Mat Hn((size_t)(m + 1) * (m + 1), cplx(0));
+    for (int c = 0; c < m; ++c)
+      for (int r2 = 0; r2 < m; ++r2) at(Hn, m + 1, r2, c) = at(H, m, r2, c);
+    for (int r2 = 0; r2 <= m; ++r2) {
+      cplx v(hh[r2].x, hh[r2].y);
+      at(Hn, m + 1, r2, m) = v;
+      at(Hn, m + 1, m, r2) = std::conj(v);
+    }
+    at(Hn, m + 1, m, m) = at(Hn, m + 1, m, m).real();
+    H.swap(Hn);
+    ++m;
+    double theta = 0;
+    bool expand = false;
+    while (m > 0) {
+      herm_eig(H, m, w, S);
+      // order by distance to the target
+      std::vector<int> ord(m);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](int a, int b) { return std::abs(w[a] - target) < std::abs(w[b] - target); });
+      Mat So((size_t)m * m);
+      std::vector<double> wo(m);
+      for (int c = 0; c < m; ++c) {
+        wo[c] = w[ord[c]];
+        for (int r2 = 0; r2 < m; ++r2) So[(size_t)c * m + r2] = S[(size_t)ord[c] * m + r2];
+      }
+      S.swap(So);
+      w.swap(wo);
+      theta = w[0];
+      // u (into the locked block's next column), R u, X u, r = X u - theta R u
+      Mat s0(S.begin(), S.begin() + m);
+      K.combine(V, m, s0, m, 1, Q + (size_t)k * N);
+      K.combine(RV, m, s0, m, 1, RQ + (size_t)k * N);
+      K.combine(XV, m, s0, m, 1, Xu.d());
+      copy(Xu.d(), r.d(), N);
+      K.axpy(RQ + (size_t)k * N, -theta, r.d());
+      double rn = K.norm(r.d()) / std::max(K.norm(RQ + (size_t)k * N), 1e-300);
+      if (rn <= tol * std::max(1.0, std::abs(theta))) {
+        out.lam.push_back(theta);
+        out.resid.push_back(rn);
+        ++k;
+        if (k == nev) break;
+        // deflate: the rest of the Ritz vectors stay
+        recombine(V, m, S, 1, m - 1);
+        recombine(XV, m, S, 1, m - 1);
+        recombine(RV, m, S, 1, m - 1);
+        --m;
+        H.assign((size_t)m * m, cplx(0));
+        for (int c = 0; c < m; ++c) at(H, m, c, c) = w[c + 1];
+        continue;
+      }
+      expand = true;
+      break;
+    }
+    if (k == nev) break;
+    if (!expand) {   // every Ritz vector locked: expand from the start vector again
+      copy(v0, t.d(), N);
+      continue;
+    }
+    if (m >= mmax) {
+      const int keep = std::min(mmin, m);
+      recombine(V, m, S, 0, keep);
+      recombine(XV, m, S, 0, keep);
+      recombine(RV, m, S, 0, keep);
+      m = keep;
+      H.assign((size_t)m * m, cplx(0));
+      for (int c = 0; c < m; ++c) at(H, m, c, c) = w[c];
+    }
+    // correction equation, fixed number of GMRES steps from t = 0, rhs -r
+    const int kq = k + 1;   // Qu = Q[:, 0..k], R Qu = RQ[:, 0..k]
+    auto op = [&](const double2* x, double2* z) {
+      copy(x, y.d(), N);
+      project(RQ, Q, kq, y.d());          // y = (I - Qu Qu^H R) x
+      K.apply(1, y.d(), Ry.d());
+      K.apply(2, y.d(), z);
+      K.axpy(Ry.d(), -theta, z);           // z = (X - theta R) y
+      project(Q, RQ, kq, z);              // z = (I - R Qu Qu^H) z
+    };
+    double2* G = Gb.d();
+    const double bn = K.norm(r.d());
+    K.scale_copy(r.d(), -1.0 / bn, G);
+    std::vector<cplx> Hg((size_t)(inner + 1) * inner, cplx(0)), g(inner + 1, cplx(0)), cs(inner), sn(inner), h;
+    g[0] = bn;
+    int nst = 0;
+    for (int j = 0; j < inner; ++j) {
+      op(G + (size_t)j * N, gw.d());
+      double hn = K.orth(G, j + 1, gw.d(), h);
+      cplx* col = &Hg[(size_t)j * (inner + 1)];
+      for (int q = 0; q <= j; ++q) col[q] = h[q];
+      col[j + 1] = hn;
+      if (hn > 0) K.scale_copy(gw.d(), 1.0 / hn, G + (size_t)(j + 1) * N);
+      for (int q = 0; q < j; ++q) {
+        cplx a = col[q], b = col[q + 1];
+        col[q] = std::conj(cs[q]) * a + std::conj(sn[q]) * b;
+        col[q + 1] = -sn[q] * a + cs[q] * b;
+      }
+      double rr = std::hypot(std::abs(col[j]), std::abs(col[j + 1]));
+      cs[j] = rr == 0 ? cplx(1) : col[j] / rr;
+      sn[j] = rr == 0 ? cplx(0) : col[j + 1] / rr;
+      col[j] = rr;
+      col[j + 1] = 0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = std::conj(cs[j]) * g[j];
+      nst = j + 1;
+      if (hn == 0) break;
+    }
+    out.inner_steps += nst;
+    std::vector<cplx> yv(nst);
+    for (int q = nst - 1; q >= 0; --q) {
+      cplx acc = g[q];
+      for (int c = q + 1; c < nst; ++c) acc -= Hg[(size_t)c * (inner + 1) + q] * yv[c];
+      yv[q] = acc / Hg[(size_t)q * (inner + 1) + q];
+    }
+    K.combine(G, nst, yv, nst, 1, t.d());
+  }
+  out.nconv = k;
+  if (Jout && k > 0) copy(Q, Jout, (size_t)k * N);
+  out.n_apply = K.n_apply;
+  chk_d(hipStreamSynchronize(s), "jd");
+  return out;
+}
+
 }  // namespace cm
 
 // ---------------------------------------------------------------- C ABI entry points
@@ -467,6 +716,37 @@ extern "C" cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t rest
     if (iters) *iters = r.iters;
     if (relres) *relres = r.relres;
     return r.converged ? CM_OK : CM_E_NOT_CONVERGED;
+  } catch (const cm::Error& e) {
+    return cm::driver_fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return cm::driver_fail(CM_E_OOM, e.what());
+  }
+}
+
+extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t mmax, int32_t maxit,
+                           double tol, int32_t inner_steps, const void* v0, cm_dtype far_dtype, double* lambda,
+                           double* resid, void* J, int32_t* nconv, int64_t* counters, void* hip_stream) {
+  if (!h || !v0 || !lambda) return cm::driver_fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (nev < 1 || nev > 512 || mmin < 1 || mmax < mmin + 1 || mmax > 512 || mmax > h->dev.N || maxit < 1 ||
+      !(tol > 0) || inner_steps < 1 || inner_steps > 512 || !std::isfinite(target))
+    return cm::driver_fail(CM_E_BADARG,
+                           "bad Jacobi-Davidson parameters (need 1 <= nev <= 512, 1 <= mmin < mmax <= min(N, 512), "
+                           "maxit >= 1, tol > 0, 1 <= inner_steps <= 512)");
+  try {
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
+    cm::JdResult r = cm::jd(K, nev, target, mmin, mmax, maxit, tol, inner_steps, (const double2*)v0, (double2*)J);
+    for (int i = 0; i < nev; ++i) {
+      lambda[i] = i < r.nconv ? r.lam[i] : 0.0;
+      if (resid) resid[i] = i < r.nconv ? r.resid[i] : 0.0;
+    }
+    if (nconv) *nconv = r.nconv;
+    if (counters) {
+      counters[0] = r.outer;
+      counters[1] = r.inner_steps;
+      counters[2] = r.n_apply;
+    }
+    return r.nconv >= nev ? CM_OK : CM_E_NOT_CONVERGED;
   } catch (const cm::Error& e) {
     return cm::driver_fail(e.code, e.what());
   } catch (const std::exception& e) {
