@@ -249,6 +249,35 @@ def plate_sweep():
             "inner_solves_redone_without_sai": t["inner_retries"]}
 
 
+def jd_vs_ira_plate():
+    """The four characteristic values nearest 0 of the 1.0 m x 0.6 m plate at
+    300 MHz (1,085 unknowns, 3 levels, FP64) by Jacobi-Davidson on (X, R)
+    (20 GMRES steps per correction, no inner solve with Z) and by IRA on
+    Z^-1 R (SAI-preconditioned inner solves), each timed from the built
+    handle (the SAI build is counted for IRA)."""
+    import torch
+    import workloads
+    from paper_1412_1756_amd import Operator
+    V, F = workloads.plate(25, 15, 0.04)
+    k = 2 * np.pi * 300e6 / 299792458.0
+    op = Operator(V, F, k, nlv=3, d0=6.0, interp_p=12, max_cols=1)
+    v0 = torch.tensor(workloads.cn01(op.N, 3), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = op.jd(4, v0, target=0.0, mmin=6, mmax=20, maxit=300, tol=1e-8, inner_steps=20, vectors=False)
+    t_jd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op.sai_build(0.01, 0.014, 0.18)
+    e = op.eigs(4, 20, v0, tol=1e-8, maxrestart=60, gmres_tol=1e-10, vectors=False)
+    t_ira = time.perf_counter() - t0
+    return {"workload": "plate 1.0 m x 0.6 m, h 0.04 m, 300 MHz", "N": op.N, "modes": 4,
+            "jd": {"seconds": t_jd, "lam": np.sort(r["lam"]).round(6).tolist(), "outer": r["outer"],
+                   "operator_applies": r["n_matvec"], "converged": r["converged"]},
+            "ira": {"seconds": t_ira, "lam": np.sort(e["lam"].real).round(6).tolist(), "op_products": e["n_op"],
+                    "gmres_iters": e["gmres_iters"], "operator_applies": e["n_matvec"],
+                    "converged": e["converged"]}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -443,6 +472,7 @@ def main():
         out["eigenmodes"] = eigs_small(a.no_cpu)
     if not a.no_track:
         out["plate_mode_sweep"] = plate_sweep()
+        out["plate_jd_vs_ira"] = jd_vs_ira_plate()
     print(json.dumps(out))
 
 
