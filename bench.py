@@ -198,6 +198,15 @@ def eigs_small(no_cpu):
     out = {"workload": "sphere_r0.5_n1920", "N": op.N, "modes": r["nconv"], "seconds": t,
            "modes_per_hour": r["nconv"] / t * 3600.0, "op_products": r["n_op"], "gmres_iters": r["gmres_iters"],
            "restarts": r["restarts"]}
+    # the same modes by IRA on X^-1 R (eq. (14), unpreconditioned inner solves with X)
+    t0 = time.perf_counter()
+    rx = op.eigs(10, 30, v0, tol=1e-6, maxrestart=30, gmres_tol=1e-8, gmres_maxit=2000, route="X", vectors=False)
+    torch.cuda.synchronize()
+    tx = time.perf_counter() - t0
+    out["x_inverse_route"] = {"seconds": tx, "modes": rx["nconv"], "op_products": rx["n_op"],
+                              "gmres_iters": rx["gmres_iters"], "converged": rx["converged"],
+                              "max_abs_diff_vs_z_route": float(np.max(np.abs(np.sort(rx["lam"].real)
+                                                                             - np.sort(r["lam"].real))))}
     if not no_cpu:
         from threadpoolctl import threadpool_limits
         from oracle import efie, modes

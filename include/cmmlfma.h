@@ -219,6 +219,19 @@ cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, do
                   cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
                   int64_t* counters, void* hip_stream);
 
+/* Characteristic modes by the implicitly restarted Arnoldi method on
+   OP = X^-1 R (the standard eigenvalue problem of eq. (14)): mu = 1/lambda,
+   so the nev largest |mu| are the smallest |lambda|.  Arguments, outputs and
+   counters[6] as cm_eigs, with unpreconditioned inner GMRES solves with X
+   (the paper notes that no efficient preconditioner for X is documented;
+   counters[4] is 0).  The cos-kernel expansion of X degrades on boxes small
+   against the wavelength, so this route suits trees whose leaves are not
+   far below 0.25 wavelength.  Synchronises. */
+cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
+                       int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, cm_dtype far_dtype,
+                       double* lambda, double* ritz_resid, void* J, int32_t* nconv, int64_t* counters,
+                       void* hip_stream);
+
 /* Characteristic modes by Jacobi-Davidson on the pencil X J = lambda R J
    (eq. (6)) with the R-orthonormal search space and the projected correction
    equation of eqs. (28)-(29): no inner solve with Z or X, each correction an

@@ -14,7 +14,7 @@ CM_FLAG_HOST_ONLY, CM_FLAG_DERIV, CM_FLAG_CHECK, CM_FLAG_NO_MATRIX_CORES, CM_FLA
 CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD = 32, 64, 128
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
-           "cm_sai_build", "cm_sai_apply", "cm_gmres", "cm_eigs", "cm_jd", "cm_export_near", "cm_stats", "cm_stage_timing",
+           "cm_sai_build", "cm_sai_apply", "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_jd", "cm_export_near", "cm_stats", "cm_stage_timing",
            "cm_stage_times", "cm_last_error"]
 
 
@@ -66,6 +66,8 @@ def lib():
     L.cm_gmres.restype = C.c_int
     L.cm_eigs.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, i32, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
     L.cm_eigs.restype = C.c_int
+    L.cm_eigs_xinv.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
+    L.cm_eigs_xinv.restype = C.c_int
     L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
     L.cm_jd.restype = C.c_int
     L.cm_stage_timing.argtypes = [vp, i32]

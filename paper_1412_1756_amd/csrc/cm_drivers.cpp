@@ -128,8 +128,10 @@ struct GmresResult {
   bool converged = false;
 };
 
-// Solve Z x = b, right-preconditioned by the SAI P (x = P u) when precond.
-static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int maxit, double tol, bool precond) {
+// Solve A x = b, right-preconditioned by the SAI P (x = P u) when precond;
+// A = Z (aop 0) or X (aop 2, the route of eq. (14); no preconditioner).
+static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int maxit, double tol, bool precond,
+                         int aop = 0) {
   const int64_t N = K.N();
   DevBuf Vb((size_t)(m + 1) * N * sizeof(double2)), w(N * sizeof(double2)), z(N * sizeof(double2)),
       u(N * sizeof(double2));
@@ -155,9 +157,9 @@ static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int 
       const double2* vj = V + (size_t)j * N;
       if (precond) {
         K.precond(vj, z.d());
-        K.apply(0, z.d(), w.d());
+        K.apply(aop, z.d(), w.d());
       } else {
-        K.apply(0, vj, w.d());
+        K.apply(aop, vj, w.d());
       }
       double hn = K.orth(V, j + 1, w.d(), h);
       for (int k = 0; k <= j; ++k) H[(size_t)j * (m + 1) + k] = h[k];
@@ -203,7 +205,7 @@ static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int 
       K.axpy(u.d(), 1.0, x);
     }
     // explicit residual
-    K.apply(0, x, z.d());
+    K.apply(aop, x, z.d());
     K.scale_copy(b, 1.0, w.d());
     K.axpy(z.d(), -1.0, w.d());
     beta = K.norm(w.d());
@@ -343,8 +345,10 @@ struct EigsResult {
   std::vector<double> resid;  // Ritz residual estimates |beta e_m^T y| / |mu|
 };
 
+// aop: the matrix inverted by the inner solves, Z (0: OP = Z^-1 R, eq. (24))
+// or X (2: OP = X^-1 R, eq. (14), unpreconditioned)
 static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double tol, const double2* v0, int gm_m,
-                       int gm_maxit, double gm_tol, bool precond, double2* Xout) {
+                       int gm_maxit, double gm_tol, bool precond, double2* Xout, int aop = 0) {
   const int64_t N = K.N();
   DevBuf Vb((size_t)ncv * N * sizeof(double2)), Vt((size_t)ncv * N * sizeof(double2)), f(N * sizeof(double2)),
       ru(N * sizeof(double2));
@@ -365,14 +369,14 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
     for (int j = j0; j < ncv; ++j) {
       // w = Z^-1 R v_j
       K.apply(1, V + (size_t)j * N, ru.d());
-      GmresResult g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, precond);
+      GmresResult g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, precond, aop);
       out.gmres_iters += g.iters;
       if (!g.converged && precond) {
         // the SAI can be nearly singular (e.g. the plate at low frequency,
         // where the column-wise least squares leave Z P with condition
         // number ~1e5): solve this product again without it
         ++out.inner_retries;
-        g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, false);
+        g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, false, aop);
         out.gmres_iters += g.iters;
       }
       // an inexact OP product makes the Ritz residual estimates meaningless
@@ -782,6 +786,43 @@ extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t max
       counters[2] = r.n_matvec;
       counters[3] = r.restarts;
       counters[4] = r.inner_retries;
+      counters[5] = r.inner_failures;
+    }
+    return (r.nconv >= nev && r.inner_failures == 0) ? CM_OK : CM_E_NOT_CONVERGED;
+  } catch (const cm::Error& e) {
+    return cm::driver_fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return cm::driver_fail(CM_E_OOM, e.what());
+  }
+}
+
+extern "C" cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol,
+                                  const void* v0, int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol,
+                                  cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
+                                  int64_t* counters, void* hip_stream) {
+  if (!h || !v0 || !lambda) return cm::driver_fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (nev < 1 || ncv <= nev || ncv > 1000 || ncv > h->dev.N || maxrestart < 0 || !(tol > 0))
+    return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
+  if (gmres_restart < 1 || gmres_maxit < 1 || !(gmres_tol > 0)) return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters");
+  try {
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
+    cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
+                                gmres_tol, false, (double2*)J, 2);
+    for (int i = 0; i < nev; ++i) {
+      // X^-1 R J = mu J  <=>  X J = (1 / mu) R J
+      cm::cplx lam = 1.0 / r.mu[i];
+      lambda[2 * i] = lam.real();
+      lambda[2 * i + 1] = lam.imag();
+      if (ritz_resid) ritz_resid[i] = r.resid[i];
+    }
+    if (nconv) *nconv = r.nconv;
+    if (counters) {
+      counters[0] = r.n_op;
+      counters[1] = r.gmres_iters;
+      counters[2] = r.n_matvec;
+      counters[3] = r.restarts;
+      counters[4] = 0;
       counters[5] = r.inner_failures;
     }
     return (r.nconv >= nev && r.inner_failures == 0) ? CM_OK : CM_E_NOT_CONVERGED;

@@ -213,12 +213,14 @@ class Operator:
                     inner_steps=int(cnt[1]), n_matvec=int(cnt[2]), converged=(st == _lib.CM_OK))
 
     def eigs(self, nev, ncv, v0, tol=1e-8, maxrestart=50, gmres_restart=50, gmres_maxit=1000, gmres_tol=1e-8,
-             precond=True, far="fp64", vectors=True, stream=None):
+             precond=True, far="fp64", vectors=True, stream=None, route="Z"):
         """Characteristic values by implicitly restarted Arnoldi on Z^-1 R.
         v0: CUDA complex128 start vector.  Returns dict(lam, resid, J, nconv,
         n_op, gmres_iters, n_matvec, restarts, inner_retries, inner_failures,
         converged); converged is False when fewer than nev Ritz values
-        converged or when an inner GMRES solve missed gmres_tol."""
+        converged or when an inner GMRES solve missed gmres_tol.  route="X":
+        IRA on X^-1 R (eq. (14), unpreconditioned inner solves with X;
+        precond is ignored) instead of Z^-1 R."""
         import torch
         v0 = v0.contiguous()
         lam = np.zeros(2 * nev)
@@ -226,11 +228,18 @@ class Operator:
         cnt = np.zeros(6, dtype=np.int64)
         J = torch.empty((nev, self.N), dtype=torch.complex128, device=v0.device) if vectors else None
         nconv = C.c_int32()
-        st = lib().cm_eigs(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
-                           gmres_maxit, gmres_tol, 1 if precond else 0,
-                           _lib.CM_C128 if far == "fp64" else _lib.CM_C64, lam.ctypes.data, res.ctypes.data,
-                           C.c_void_p(J.data_ptr()) if vectors else None, C.byref(nconv), cnt.ctypes.data,
-                           self._stream_ptr(stream))
+        fd = _lib.CM_C128 if far == "fp64" else _lib.CM_C64
+        Jp = C.c_void_p(J.data_ptr()) if vectors else None
+        if route == "X":
+            st = lib().cm_eigs_xinv(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
+                                    gmres_maxit, gmres_tol, fd, lam.ctypes.data, res.ctypes.data, Jp,
+                                    C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
+        elif route == "Z":
+            st = lib().cm_eigs(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
+                               gmres_maxit, gmres_tol, 1 if precond else 0, fd, lam.ctypes.data, res.ctypes.data,
+                               Jp, C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
+        else:
+            raise ValueError("route must be 'Z' or 'X'")
         if st not in (_lib.CM_OK, _lib.CM_E_NOT_CONVERGED):
             check(st)
         return dict(lam=lam[0::2] + 1j * lam[1::2], resid=res, J=(J.T if vectors else None), nconv=int(nconv.value),

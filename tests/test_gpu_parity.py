@@ -649,3 +649,21 @@ def test_jacobi_davidson_plate_matches_qz(torch_cuda):
     print("plate JD", np.sort(r["lam"]), "QZ", lo, "outer", r["outer"], "applies", r["n_matvec"], flush=True)
     assert r["converged"]
     assert np.abs(np.sort(r["lam"]) - lo).max() < 1e-3
+
+
+def test_arnoldi_on_x_inverse_r_matches_qz(torch_cuda, cfg1):
+    """IRA on X^-1 R (the standard problem of eq. (14), inner GMRES solves
+    with X, no preconditioner): the eight smallest |lambda| of the
+    1,920-unknown sphere against dense QZ."""
+    torch = torch_cuda
+    from oracle import modes
+    V, F, Z = cfg1
+    op = _op(V, F, 3, ACC64, max_cols=1)
+    v0 = torch.tensor(workloads.cn01(Z.shape[0], 3), dtype=torch.complex128, device="cuda")
+    r = op.eigs(8, 30, v0, tol=1e-8, maxrestart=30, gmres_tol=1e-10, gmres_maxit=2000, route="X", vectors=False)
+    lo = np.sort(modes.qz_modes(Z.imag, Z.real, nev=8).real)
+    print("X^-1 R IRA", np.sort(r["lam"].real), "QZ", lo, "OP products", r["n_op"], "GMRES", r["gmres_iters"],
+          flush=True)
+    assert r["converged"] and r["inner_failures"] == 0
+    assert np.abs(np.sort(r["lam"].real) - lo).max() < 1e-3
+    assert np.abs(r["lam"].imag).max() < 1e-6
