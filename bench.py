@@ -290,8 +290,9 @@ def jd_vs_ira_plate():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); sharding over several GPUs "
+              "(Morton ranges of leaf boxes, pattern halos per level, a transpose where coarse levels "
+              "split by direction) is not built", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads
