@@ -235,8 +235,10 @@ cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestar
 /* Characteristic modes by Jacobi-Davidson on the pencil X J = lambda R J
    (eq. (6)) with the R-orthonormal search space and the projected correction
    equation of eqs. (28)-(29): no inner solve with Z or X, each correction an
-   approximate solution by inner_steps unpreconditioned GMRES steps (one R and
-   one X apply each).  Finds the nev characteristic values closest to target
+   approximate solution by inner_steps GMRES steps (one R and one X apply
+   each), unpreconditioned, or with precond != 0 right-preconditioned by
+   i P, P the SAI of Z (cm_sai_build first; X - theta R is close to
+   -i (Z - R) for targets near 0).  Finds the nev characteristic values closest to target
    (0 for the significant modes); the search space holds at most mmax vectors
    and restarts from the mmin Ritz vectors nearest the target.  A pair is
    accepted when ||X u - theta R u|| <= tol max(1, |theta|) ||R u||, then
@@ -248,10 +250,11 @@ cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestar
    iterations, inner GMRES steps, operator applies.  Returns
    CM_E_NOT_CONVERGED when fewer than nev were found within maxit outer
    iterations (the first *nconv outputs are valid), CM_E_NUMERIC when an
-   expansion vector has no R-norm (R is singular on it).  Synchronises. */
+   expansion vector has no R-norm (R is singular on it), CM_E_NOT_BUILT for
+   precond without the SAI.  Synchronises. */
 cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t mmax, int32_t maxit, double tol,
-                int32_t inner_steps, const void* v0, cm_dtype far_dtype, double* lambda, double* resid, void* J,
-                int32_t* nconv, int64_t* counters, void* hip_stream);
+                int32_t inner_steps, int32_t precond, const void* v0, cm_dtype far_dtype, double* lambda,
+                double* resid, void* J, int32_t* nconv, int64_t* counters, void* hip_stream);
 
 /* Copy the near-field matrix to host (public unknown order, CSR by row):
    row_ptr (N+1, int64), col (nnz, int32), val (nnz complex128 interleaved).

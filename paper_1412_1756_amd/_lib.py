@@ -68,7 +68,7 @@ def lib():
     L.cm_eigs.restype = C.c_int
     L.cm_eigs_xinv.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
     L.cm_eigs_xinv.restype = C.c_int
-    L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
+    L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
     L.cm_jd.restype = C.c_int
     L.cm_stage_timing.argtypes = [vp, i32]
     L.cm_stage_timing.restype = C.c_int

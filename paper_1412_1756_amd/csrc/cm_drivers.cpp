@@ -460,7 +460,11 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
 //   (I - R Qu Qu^H)(X - theta R)(I - Qu Qu^H R) t = -(X u - theta R u),
 // with Qu = [locked eigenvectors, u], t R-orthogonal to Qu.  Converged pairs
 // are locked (deflation); the space restarts from the mmin Ritz vectors
-// nearest the target when it reaches mmax.
+// nearest the target when it reaches mmax.  With precond the correction is
+// solved right-preconditioned by i P, P the SAI of Z: for targets near 0,
+// X - theta R is close to X = -i (Z - R), and the SAI approximates the
+// inverse of Z's near field (t = i P y; the R-orthogonalisation of the next
+// step removes its components along the locked vectors and u).
 
 // Eigenvalues (ascending) and eigenvectors (columns of S) of a small
 // Hermitian matrix by cyclic complex Jacobi rotations.
@@ -523,14 +527,14 @@ struct JdResult {
 };
 
 static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int maxit, double tol, int inner,
-                   const double2* v0, double2* Jout) {
+                   const double2* v0, double2* Jout, bool precond) {
   const int64_t N = K.N();
   hipStream_t s = K.stream();
   DevBuf Vb((size_t)mmax * N * sizeof(double2)), XVb((size_t)mmax * N * sizeof(double2)),
       RVb((size_t)mmax * N * sizeof(double2)), Tmp((size_t)mmax * N * sizeof(double2)),
       Qb((size_t)(nev + 1) * N * sizeof(double2)), RQb((size_t)(nev + 1) * N * sizeof(double2)),
       t(N * sizeof(double2)), Rt(N * sizeof(double2)), Xt(N * sizeof(double2)), r(N * sizeof(double2)),
-      Xu(N * sizeof(double2)), y(N * sizeof(double2)), Ry(N * sizeof(double2)),
+      Xu(N * sizeof(double2)), y(N * sizeof(double2)), Ry(N * sizeof(double2)), py(N * sizeof(double2)),
       Gb((size_t)(inner + 1) * N * sizeof(double2)), gw(N * sizeof(double2)), hd(1024 * sizeof(double2));
   double2 *V = Vb.d(), *XV = XVb.d(), *RV = RVb.d(), *Q = Qb.d(), *RQ = RQb.d();
   JdResult out;
@@ -648,8 +652,13 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
     // correction equation, fixed number of GMRES steps from t = 0, rhs -r
     const int kq = k + 1;   // Qu = Q[:, 0..k], R Qu = RQ[:, 0..k]
     auto op = [&](const double2* x, double2* z) {
-      copy(x, y.d(), N);
-      project(RQ, Q, kq, y.d());          // y = (I - Qu Qu^H R) x
+      if (precond) {
+        K.precond(x, py.d());
+        K.scale_copy(py.d(), cplx(0, 1), y.d());   // y = i P x
+      } else {
+        copy(x, y.d(), N);
+      }
+      project(RQ, Q, kq, y.d());          // y = (I - Qu Qu^H R) y
       K.apply(1, y.d(), Ry.d());
       K.apply(2, y.d(), z);
       K.axpy(Ry.d(), -theta, z);           // z = (X - theta R) y
@@ -691,6 +700,10 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
       yv[q] = acc / Hg[(size_t)q * (inner + 1) + q];
     }
     K.combine(G, nst, yv, nst, 1, t.d());
+    if (precond) {
+      K.precond(t.d(), py.d());
+      K.scale_copy(py.d(), cplx(0, 1), t.d());
+    }
   }
   out.nconv = k;
   if (Jout && k > 0) copy(Q, Jout, (size_t)k * N);
@@ -728,7 +741,8 @@ extern "C" cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t rest
 }
 
 extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t mmax, int32_t maxit,
-                           double tol, int32_t inner_steps, const void* v0, cm_dtype far_dtype, double* lambda,
+                           double tol, int32_t inner_steps, int32_t precond, const void* v0, cm_dtype far_dtype,
+                           double* lambda,
                            double* resid, void* J, int32_t* nconv, int64_t* counters, void* hip_stream) {
   if (!h || !v0 || !lambda) return cm::driver_fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
@@ -737,9 +751,11 @@ extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmi
     return cm::driver_fail(CM_E_BADARG,
                            "bad Jacobi-Davidson parameters (need 1 <= nev <= 512, 1 <= mmin < mmax <= min(N, 512), "
                            "maxit >= 1, tol > 0, 1 <= inner_steps <= 512)");
+  if (precond && !h->dev.sai_val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
-    cm::JdResult r = cm::jd(K, nev, target, mmin, mmax, maxit, tol, inner_steps, (const double2*)v0, (double2*)J);
+    cm::JdResult r =
+        cm::jd(K, nev, target, mmin, mmax, maxit, tol, inner_steps, (const double2*)v0, (double2*)J, precond != 0);
     for (int i = 0; i < nev; ++i) {
       lambda[i] = i < r.nconv ? r.lam[i] : 0.0;
       if (resid) resid[i] = i < r.nconv ? r.resid[i] : 0.0;

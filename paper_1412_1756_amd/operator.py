@@ -189,12 +189,14 @@ class Operator:
             check(st)
         return x, int(it.value), float(rr.value), st == _lib.CM_OK
 
-    def jd(self, nev, v0, target=0.0, mmin=6, mmax=20, maxit=500, tol=1e-8, inner_steps=10, far="fp64",
-           vectors=True, stream=None):
+    def jd(self, nev, v0, target=0.0, mmin=6, mmax=20, maxit=500, tol=1e-8, inner_steps=10, precond=False,
+           far="fp64", vectors=True, stream=None):
         """Characteristic values closest to target by Jacobi-Davidson on the
         pencil (X, R) (no inner solve with Z).  v0: CUDA complex128 start
-        vector.  Returns dict(lam, resid, J (N x nconv, R-normalised), nconv,
-        outer, inner_steps, n_matvec, converged)."""
+        vector; precond=True solves the corrections right-preconditioned by
+        i P with the SAI P of Z (sai_build first).  Returns dict(lam, resid,
+        J (N x nconv, R-normalised), nconv, outer, inner_steps, n_matvec,
+        converged)."""
         import torch
         v0 = v0.contiguous()
         lam = np.zeros(nev)
@@ -202,7 +204,8 @@ class Operator:
         cnt = np.zeros(3, dtype=np.int64)
         J = torch.empty((nev, self.N), dtype=torch.complex128, device=v0.device) if vectors else None
         nconv = C.c_int32()
-        st = lib().cm_jd(self._h, nev, float(target), mmin, mmax, maxit, tol, inner_steps, C.c_void_p(v0.data_ptr()),
+        st = lib().cm_jd(self._h, nev, float(target), mmin, mmax, maxit, tol, inner_steps, 1 if precond else 0,
+                         C.c_void_p(v0.data_ptr()),
                          _lib.CM_C128 if far == "fp64" else _lib.CM_C64, lam.ctypes.data, res.ctypes.data,
                          C.c_void_p(J.data_ptr()) if vectors else None, C.byref(nconv), cnt.ctypes.data,
                          self._stream_ptr(stream))

@@ -649,6 +649,13 @@ def test_jacobi_davidson_plate_matches_qz(torch_cuda):
     print("plate JD", np.sort(r["lam"]), "QZ", lo, "outer", r["outer"], "applies", r["n_matvec"], flush=True)
     assert r["converged"]
     assert np.abs(np.sort(r["lam"]) - lo).max() < 1e-3
+    # corrections right-preconditioned by i P (SAI of Z): same values, fewer operator applies
+    op.sai_build(0.01, 0.014, 0.18)
+    rp = op.jd(4, v0, target=0.0, mmin=6, mmax=20, maxit=300, tol=1e-8, inner_steps=20, precond=True)
+    print("plate JD with i P", np.sort(rp["lam"]), "outer", rp["outer"], "applies", rp["n_matvec"], flush=True)
+    assert rp["converged"]
+    assert np.abs(np.sort(rp["lam"]) - lo).max() < 1e-3
+    assert rp["n_matvec"] < r["n_matvec"]
 
 
 def test_arnoldi_on_x_inverse_r_matches_qz(torch_cuda, cfg1):
