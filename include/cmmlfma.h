@@ -246,8 +246,10 @@ cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestar
    draws it).  Outputs (host): lambda[nev] real characteristic values in the
    order found; resid[nev] (may be NULL) their relative residuals; J (device,
    may be NULL) the N x nev eigenvectors, column-major, R-normalised
-   (J^H R J = I); *nconv the number found; counters[3] (may be NULL): outer
-   iterations, inner GMRES steps, operator applies.  Returns
+   (J^H R J = I); *nconv the number found; counters[4] (may be NULL): outer
+   iterations, inner GMRES steps, operator applies, 1 if the preconditioner
+   was dropped (no new converged pair within max(50, maxit / 8) outer
+   iterations: the SAI can be nearly singular).  Returns
    CM_E_NOT_CONVERGED when fewer than nev were found within maxit outer
    iterations (the first *nconv outputs are valid), CM_E_NUMERIC when an
    expansion vector has no R-norm (R is singular on it), CM_E_NOT_BUILT for

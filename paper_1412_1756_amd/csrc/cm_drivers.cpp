@@ -464,7 +464,10 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
 // solved right-preconditioned by i P, P the SAI of Z: for targets near 0,
 // X - theta R is close to X = -i (Z - R), and the SAI approximates the
 // inverse of Z's near field (t = i P y; the R-orthogonalisation of the next
-// step removes its components along the locked vectors and u).
+// step removes its components along the locked vectors and u).  Where the
+// SAI is nearly singular (the plate at low frequency) that preconditioner
+// stalls the iteration: after max(50, maxit / 8) outer iterations without a
+// new converged pair it is dropped for the rest of the solve.
 
 // Eigenvalues (ascending) and eigenvectors (columns of S) of a small
 // Hermitian matrix by cyclic complex Jacobi rotations.
@@ -522,7 +525,7 @@ static void herm_eig(Mat A, int n, std::vector<double>& w, Mat& S) {
 
 struct JdResult {
   std::vector<double> lam, resid;
-  int nconv = 0, outer = 0;
+  int nconv = 0, outer = 0, precond_dropped = 0;
   int64_t inner_steps = 0, n_apply = 0;
 };
 
@@ -562,7 +565,8 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
     copy(Tmp.d(), M, (size_t)nc * N);
   };
   copy(v0, t.d(), N);
-  int k = 0, m = 0;
+  int k = 0, m = 0, since_lock = 0;
+  const int stall = std::max(50, maxit / 8);
   Mat H;   // m x m, V^H X V
   std::vector<double> w;
   Mat S;
@@ -622,6 +626,7 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
         out.lam.push_back(theta);
         out.resid.push_back(rn);
         ++k;
+        since_lock = 0;
         if (k == nev) break;
         // deflate: the rest of the Ritz vectors stay
         recombine(V, m, S, 1, m - 1);
@@ -636,6 +641,10 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
       break;
     }
     if (k == nev) break;
+    if (precond && ++since_lock > stall) {
+      precond = false;
+      out.precond_dropped = 1;
+    }
     if (!expand) {   // every Ritz vector locked: expand from the start vector again
       copy(v0, t.d(), N);
       continue;
@@ -765,6 +774,7 @@ extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmi
       counters[0] = r.outer;
       counters[1] = r.inner_steps;
       counters[2] = r.n_apply;
+      counters[3] = r.precond_dropped;
     }
     return r.nconv >= nev ? CM_OK : CM_E_NOT_CONVERGED;
   } catch (const cm::Error& e) {

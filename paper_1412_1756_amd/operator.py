@@ -196,12 +196,13 @@ class Operator:
         vector; precond=True solves the corrections right-preconditioned by
         i P with the SAI P of Z (sai_build first).  Returns dict(lam, resid,
         J (N x nconv, R-normalised), nconv, outer, inner_steps, n_matvec,
-        converged)."""
+        precond_dropped, converged); the preconditioner is dropped after
+        max(50, maxit / 8) outer iterations without a new converged pair."""
         import torch
         v0 = v0.contiguous()
         lam = np.zeros(nev)
         res = np.zeros(nev)
-        cnt = np.zeros(3, dtype=np.int64)
+        cnt = np.zeros(4, dtype=np.int64)
         J = torch.empty((nev, self.N), dtype=torch.complex128, device=v0.device) if vectors else None
         nconv = C.c_int32()
         st = lib().cm_jd(self._h, nev, float(target), mmin, mmax, maxit, tol, inner_steps, 1 if precond else 0,
@@ -213,7 +214,8 @@ class Operator:
             check(st)
         n = int(nconv.value)
         return dict(lam=lam[:n], resid=res[:n], J=(J[:n].T if vectors else None), nconv=n, outer=int(cnt[0]),
-                    inner_steps=int(cnt[1]), n_matvec=int(cnt[2]), converged=(st == _lib.CM_OK))
+                    inner_steps=int(cnt[1]), n_matvec=int(cnt[2]), precond_dropped=bool(cnt[3]),
+                    converged=(st == _lib.CM_OK))
 
     def eigs(self, nev, ncv, v0, tol=1e-8, maxrestart=50, gmres_restart=50, gmres_maxit=1000, gmres_tol=1e-8,
              precond=True, far="fp64", vectors=True, stream=None, route="Z"):

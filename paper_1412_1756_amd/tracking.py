@@ -31,10 +31,13 @@ def real_currents(op, J):
     return Jr / nrm[None, :], RJ / nrm[None, :]
 
 
-def track_modes(make_op, ks, nev, ncv, v0, ntrack=None, sai=(0.01, 0.014, 0.18), **eig_kw):
+def track_modes(make_op, ks, nev, ncv, v0, ntrack=None, sai=(0.01, 0.014, 0.18), solver="ira", **eig_kw):
     """Follow the ntrack (<= nev, default nev) smallest-|lambda| modes of
-    ks[0] through the sweep ks; each Arnoldi solve computes nev modes, the
+    ks[0] through the sweep ks; each eigen-solve computes nev modes, the
     spare ones being candidates for a mode whose |lambda| rank changes.
+    solver: "ira" (Operator.eigs on Z^-1 R, ncv Arnoldi vectors) or "jd"
+    (Operator.jd on the pencil (X, R) with target 0; ncv is unused, eig_kw
+    goes to Operator.jd).
 
     make_op(k) returns an Operator at wavenumber k built with deriv=True and
     max_cols >= nev (the caller chooses mesh, levels and accuracy); v0 is the
@@ -49,7 +52,8 @@ def track_modes(make_op, ks, nev, ncv, v0, ntrack=None, sai=(0.01, 0.014, 0.18),
       index [n_k, ntrack]      column of the Arnoldi result (sorted by
                                |lambda|) each track took
       converged, n_op, inner_retries
-                               per wavenumber (see Operator.eigs)
+                               per wavenumber (Operator.eigs; for "jd" n_op
+                               counts operator applies)
     """
     ks = [float(k) for k in ks]
     n = len(ks)
@@ -66,11 +70,20 @@ def track_modes(make_op, ks, nev, ncv, v0, ntrack=None, sai=(0.01, 0.014, 0.18),
     for i, k in enumerate(ks):
         op = make_op(k)
         op.sai_build(*sai)
-        r = op.eigs(nev, ncv, v0, **eig_kw)
+        if solver == "ira":
+            r = op.eigs(nev, ncv, v0, **eig_kw)
+            nops.append(int(r["n_op"]))
+            retries.append(int(r["inner_retries"]))
+        elif solver == "jd":
+            r = op.jd(nev, v0, **eig_kw)
+            nops.append(int(r["n_matvec"]))
+            retries.append(0)
+            if r["nconv"] < nev:
+                raise RuntimeError(f"Jacobi-Davidson found {r['nconv']} of {nev} modes at k = {k}")
+        else:
+            raise ValueError("solver must be 'ira' or 'jd'")
         conv.append(bool(r["converged"]))
-        nops.append(int(r["n_op"]))
-        retries.append(int(r["inner_retries"]))
-        lam = r["lam"].real
+        lam = np.real(r["lam"])
         order = np.argsort(np.abs(lam))
         lam = lam[order]
         J, RJ = real_currents(op, r["J"][:, order.tolist()])

@@ -532,12 +532,13 @@ def test_dlambda_dk_matches_oracle(torch_cuda, cfg1_deriv):
 
 def test_plate_mode_tracking_matches_oracle(torch_cuda):
     """The paper's plate sweep geometry (1.0 m x 0.6 m PEC plate, 1,085 RWG
-    unknowns, 3 levels) at 280, 300 and 320 MHz: IRA for five modes at each
+    unknowns, 3 levels) at 280, 300 and 320 MHz: five modes solved at each
     frequency and the four smallest-|lambda| modes of 280 MHz followed by
-    tracking.track_modes (IRA, SAI, dZ/dk pass, correlation matching) against
-    the oracle (dense QZ at each frequency, brute-force correlation matching
-    over seven candidates, dense dZ/dk): characteristic values within 1e-3,
-    the same correspondence, d lambda/dk within 1e-3 relative."""
+    tracking.track_modes (SAI, IRA or Jacobi-Davidson with i P corrections,
+    dZ/dk pass, correlation matching) against the oracle (dense QZ at each
+    frequency, brute-force correlation matching over seven candidates, dense
+    dZ/dk): characteristic values within 1e-3, the same correspondence,
+    d lambda/dk within 1e-3 relative."""
     torch = torch_cuda
     from oracle import efie, modes
     from paper_1412_1756_amd import Operator
@@ -546,14 +547,6 @@ def test_plate_mode_tracking_matches_oracle(torch_cuda):
     V, F = workloads.plate(25, 15, 0.04)
     ks = [2 * np.pi * f / c0 for f in (280e6, 300e6, 320e6)]
     nev, ntrack = 5, 4
-
-    def make_op(k):
-        return Operator(V, F, k, nlv=3, max_cols=16, deriv=True, **ACC64)
-
-    N = make_op(ks[0]).N
-    v0 = torch.tensor(workloads.cn01(N, 3), dtype=torch.complex128, device="cuda")
-    t = track_modes(make_op, ks, nev, 20, v0, ntrack=ntrack, tol=1e-8, maxrestart=60, gmres_tol=1e-10)
-    assert all(t["converged"])
     # oracle: QZ at every frequency (two spare modes so a mode may move past the fifth)
     lam_o, d_o = [], []
     Jp = None
@@ -570,11 +563,22 @@ def test_plate_mode_tracking_matches_oracle(torch_cuda):
         d_o.append(modes.dlambda_dk(Jo[:, p], lo[p], dZ.imag, dZ.real, Z.real))
         Jp = Jo[:, p]
     lam_o, d_o = np.array(lam_o), np.array(d_o)
-    print("tracked lambda", t["lam"], "oracle", lam_o, "corr", t["corr"], flush=True)
-    print("dlambda/dk", t["dldk"], "oracle", d_o, flush=True)
-    assert np.abs(t["lam"] - lam_o).max() < 1e-3 * max(1.0, np.abs(lam_o).max())
-    assert np.abs(t["dldk"] - d_o).max() < 1e-3 * np.abs(d_o).max()
-    assert t["corr"].min() > 0.9
+
+    def make_op(k):
+        return Operator(V, F, k, nlv=3, max_cols=16, deriv=True, **ACC64)
+
+    N = make_op(ks[0]).N
+    v0 = torch.tensor(workloads.cn01(N, 3), dtype=torch.complex128, device="cuda")
+    for solver, kw in (("ira", dict(tol=1e-8, maxrestart=60, gmres_tol=1e-10)),
+                       ("jd", dict(target=0.0, mmin=6, mmax=20, maxit=400, tol=1e-8, inner_steps=20,
+                                   precond=True))):
+        t = track_modes(make_op, ks, nev, 20, v0, ntrack=ntrack, solver=solver, **kw)
+        print(solver, "tracked lambda", t["lam"], "oracle", lam_o, "corr", t["corr"], flush=True)
+        print(solver, "dlambda/dk", t["dldk"], "oracle", d_o, flush=True)
+        assert all(t["converged"])
+        assert np.abs(t["lam"] - lam_o).max() < 1e-3 * max(1.0, np.abs(lam_o).max())
+        assert np.abs(t["dldk"] - d_o).max() < 1e-3 * np.abs(d_o).max()
+        assert t["corr"].min() > 0.9
 
 
 def test_plate_low_frequency_eigs_redo_inner_solves_without_sai(torch_cuda):

@@ -5,6 +5,7 @@ complex phases and listed in a shuffled order.  The tracker must reproduce
 the oracle's brute-force correspondence, characteristic values and
 d lambda/dk."""
 import numpy as np
+import pytest
 import torch
 
 import workloads
@@ -37,8 +38,13 @@ class DenseOp:
         Jc = (J * ph[None, :])[:, sh]
         return dict(lam=lam[sh], J=torch.tensor(Jc), converged=True, n_op=0, inner_retries=0)
 
+    def jd(self, nev, v0, **kw):
+        r = self.eigs(nev, 0, v0)
+        return dict(lam=r["lam"].real, J=r["J"], nconv=nev, converged=True, n_matvec=0)
 
-def test_tracker_matches_oracle_on_dense_plate():
+
+@pytest.mark.parametrize("solver", ["ira", "jd"])
+def test_tracker_matches_oracle_on_dense_plate(solver):
     from paper_1412_1756_amd.tracking import track_modes
     V, F = workloads.plate(10, 6, 0.1)
     ks = [2 * np.pi * f / C0 for f in (280e6, 300e6, 320e6)]
@@ -49,7 +55,7 @@ def test_tracker_matches_oracle_on_dense_plate():
         ops[k] = DenseOp(V, F, k, seed=len(ops))
         return ops[k]
 
-    t = track_modes(make_op, ks, nev, 20, None, ntrack=ntrack)
+    t = track_modes(make_op, ks, nev, 20, None, ntrack=ntrack, solver=solver)
     # oracle correspondence, independent of the tracker
     Jp, lam_o, d_o = None, [], []
     for k in ks:
