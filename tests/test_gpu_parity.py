@@ -678,3 +678,44 @@ def test_arnoldi_on_x_inverse_r_matches_qz(torch_cuda, cfg1):
     assert r["converged"] and r["inner_failures"] == 0
     assert np.abs(np.sort(r["lam"].real) - lo).max() < 1e-3
     assert np.abs(r["lam"].imag).max() < 1e-6
+
+
+def test_argument_errors_return_status_before_any_launch(torch_cuda, cfg1):
+    """Bad arguments through the C ABI come back as status codes (no kernel is
+    launched for them): ncols out of [1, max_cols], ld < ncols, aliasing,
+    bad op or dtype, dZ/dk without CM_FLAG_DERIV, k_index out of range, and
+    eigen-solver parameters; the handle stays usable afterwards."""
+    torch = torch_cuda
+    import ctypes as C
+    from paper_1412_1756_amd import _lib
+    L = _lib.lib()
+    V, F, Z = cfg1
+    op = _op(V, F, 3, ACC64, max_cols=4)
+    N = op.N
+    X = torch.zeros((N, 4), dtype=torch.complex128, device="cuda")
+    Y = torch.zeros_like(X)
+    xp, yp = C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr())
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.cm_apply(op._h, 0, xp, yp, 4, 0, None, 1, s) == -1          # ncols = 0
+    assert L.cm_apply(op._h, 0, xp, yp, 8, 5, None, 1, s) == -1          # ncols > max_cols
+    assert L.cm_apply(op._h, 0, xp, yp, 2, 4, None, 1, s) == -1          # ld < ncols
+    assert L.cm_apply(op._h, 0, xp, xp, 4, 4, None, 1, s) == -1          # x aliases y
+    assert L.cm_apply(op._h, 7, xp, yp, 4, 4, None, 1, s) == -1          # bad op
+    assert L.cm_apply(op._h, 0, xp, yp, 4, 4, None, 5, s) == -1          # bad dtype
+    assert L.cm_apply(op._h, 4, xp, yp, 4, 4, None, 1, s) == -5          # dZ/dk not built
+    ki = np.array([0, 0, 1, 0], dtype=np.int32)
+    assert L.cm_apply(op._h, 0, xp, yp, 4, 4, C.c_void_p(ki.ctypes.data), 1, s) == -1   # k_index >= n_k
+    lam = np.zeros(8)
+    nconv = C.c_int32()
+    v0 = C.c_void_p(X.data_ptr())
+    assert L.cm_eigs(op._h, 4, 4, 10, 1e-8, v0, 20, 100, 1e-8, 0, 1, lam.ctypes.data, None, None,
+                     C.byref(nconv), None, s) == -1                      # ncv <= nev
+    assert L.cm_eigs(op._h, 2, 8, 10, 1e-8, v0, 20, 100, 1e-8, 1, 1, lam.ctypes.data, None, None,
+                     C.byref(nconv), None, s) == -5                      # SAI not built
+    assert L.cm_jd(op._h, 2, 0.0, 6, 5, 10, 1e-8, 10, 0, v0, 1, lam.ctypes.data, None, None,
+                   C.byref(nconv), None, s) == -1                        # mmax <= mmin
+    assert L.cm_jd(op._h, 2, 0.0, 6, 20, 10, 1e-8, 10, 1, v0, 1, lam.ctypes.data, None, None,
+                   C.byref(nconv), None, s) == -5                        # i P without the SAI
+    x = workloads.cn01(N, 0)
+    y = op.apply(torch.tensor(x, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    assert relerr(y, Z @ x) < TOL64
