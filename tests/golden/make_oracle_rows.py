@@ -1,5 +1,5 @@
-"""Writes oracle_rows_<workload>.json: sampled rows of the oracle's Z applied
-to the seeded test columns, for GPU parity tests at sizes where filling the
+"""Writes oracle_rows_<workload>.json: sampled rows of the oracle's Z (and of
+its real and imaginary parts R and X) applied to the seeded test columns, for GPU parity tests at sizes where filling the
 rows takes minutes (1,966,080 unknowns: about 40 s per row on one core).
 
 Only oracle/ and the seeded input generators are used.  Rows: seed 2 (without
@@ -30,9 +30,12 @@ def main(name, nrows, ncols):
     X = workloads.cn01_block(N, ncols, 100)
     X[:, 0] = workloads.cn01(N, 0)
     Zr = efie.rows_Z(V, F, spec["k"], rows, geo=efie.Geometry(V, F), rwg=rwg)
-    R = Zr @ X
+    Zx = Zr @ X
+    Rx = Zr.real @ X          # R = Re Z, X = Im Z entry by entry (Z = R + iX)
+    Xx = Zr.imag @ X
     out = {"workload": name, "N": N, "k": spec["k"], "rows": rows.tolist(), "ncols": ncols,
-           "columns": "seeds 100 + j, column 0 = seed 0", "Zx_re": R.real.tolist(), "Zx_im": R.imag.tolist()}
+           "columns": "seeds 100 + j, column 0 = seed 0", "Zx_re": Zx.real.tolist(), "Zx_im": Zx.imag.tolist(),
+           "Rx_re": Rx.real.tolist(), "Rx_im": Rx.imag.tolist(), "Xx_re": Xx.real.tolist(), "Xx_im": Xx.imag.tolist()}
     with open(os.path.join(HERE, f"oracle_rows_{name}.json"), "w") as f:
         json.dump(out, f, indent=1)
 
