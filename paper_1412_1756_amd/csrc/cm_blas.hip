@@ -141,6 +141,17 @@ void blas_multidot(const double2* V, int64_t ldv, const double2* w, int64_t N, i
 void blas_gemv_sub(const double2* V, int64_t ldv, const double2* h, int nk, double2* w, int64_t N, hipStream_t s) {
   if (nk > 0) hipLaunchKernelGGL(k_gemv_sub, g1(N), dim3(256), 0, s, V, ldv, h, nk, w, N);
 }
+// y <- alpha y in place
+__global__ void __launch_bounds__(256) k_scale(double2* y, double2 alpha, int64_t N) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double2 a = y[i];
+  y[i] = make_double2(alpha.x * a.x - alpha.y * a.y, alpha.x * a.y + alpha.y * a.x);
+}
+
+void blas_scale(double2* y, double2 alpha, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, g1(N), dim3(256), 0, s, y, alpha, N);
+}
 void blas_axpby(const double2* x, double2 alpha, double2* y, int64_t N, int accumulate, hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, g1(N), dim3(256), 0, s, x, alpha, y, N, accumulate);
 }

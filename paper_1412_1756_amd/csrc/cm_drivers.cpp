@@ -20,6 +20,7 @@ namespace cm {
 void blas_multidot(const double2* V, int64_t ldv, const double2* w, int64_t N, int nk, double2* h, hipStream_t s);
 void blas_gemv_sub(const double2* V, int64_t ldv, const double2* h, int nk, double2* w, int64_t N, hipStream_t s);
 void blas_axpby(const double2* x, double2 alpha, double2* y, int64_t N, int accumulate, hipStream_t s);
+void blas_scale(double2* y, double2 alpha, int64_t N, hipStream_t s);
 void blas_basis_update(const double2* V, int64_t ldv, const double2* Q, int ldq, int nk, int nc, double2* Vout,
                        int64_t N, hipStream_t s);
 void blas_to_c64(const double2* x, float2* y, int64_t N, hipStream_t s);
@@ -95,6 +96,31 @@ class KrylovCtx {
     return norm(w);
   }
 
+  // The new Krylov vector w = V[:, j] orthogonalised in place against
+  // V[0..j): classical Gram-Schmidt with w^H w taken in the same reduction,
+  // so one host round trip per pass; ||w|| afterwards from Pythagoras unless
+  // cancellation occurred, when a second pass follows (DGKS, as in orth).
+  double orth_next(double2* V, int j, std::vector<cplx>& h) {
+    double2* w = V + (size_t)j * N_;
+    h.assign(j, cplx(0));
+    std::vector<double2> hh(j + 1);
+    for (int pass = 0; pass < 2; ++pass) {
+      blas_multidot(V, N_, w, N_, j + 1, hdev_.d(), s_);   // V[0..j]^H w; the last entry is w^H w
+      if (j > 0) blas_gemv_sub(V, N_, hdev_.d(), j, w, N_, s_);
+      chk_d(hipMemcpyAsync(hh.data(), hdev_.p, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, s_), "orth");
+      chk_d(hipStreamSynchronize(s_), "orth");
+      const double ww = hh[j].x;
+      double hs = 0;
+      for (int k = 0; k < j; ++k) {
+        h[k] += cplx(hh[k].x, hh[k].y);
+        hs += hh[k].x * hh[k].x + hh[k].y * hh[k].y;
+      }
+      const double r2 = ww - hs;
+      if (j == 0 || r2 > 0.514 * ww) return std::sqrt(std::max(r2, 0.0));   // 0.514 = 0.717^2
+    }
+    return norm(w);
+  }
+
   void scale_copy(const double2* x, cplx a, double2* y) {
     blas_axpby(x, make_double2(a.real(), a.imag()), y, N_, 0, s_);
   }
@@ -155,16 +181,17 @@ static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int 
     int jend = -1;
     for (int j = 0; j < m && res.iters < maxit; ++j) {
       const double2* vj = V + (size_t)j * N;
+      double2* vn = V + (size_t)(j + 1) * N;   // the new vector is built in its slot
       if (precond) {
         K.precond(vj, z.d());
-        K.apply(aop, z.d(), w.d());
+        K.apply(aop, z.d(), vn);
       } else {
-        K.apply(aop, vj, w.d());
+        K.apply(aop, vj, vn);
       }
-      double hn = K.orth(V, j + 1, w.d(), h);
+      double hn = K.orth_next(V, j + 1, h);
       for (int k = 0; k <= j; ++k) H[(size_t)j * (m + 1) + k] = h[k];
       H[(size_t)j * (m + 1) + j + 1] = hn;
-      if (hn > 0) K.scale_copy(w.d(), 1.0 / hn, V + (size_t)(j + 1) * N);
+      if (hn > 0) blas_scale(vn, make_double2(1.0 / hn, 0.0), N, K.stream());
       // previous rotations on column j
       cplx* col = &H[(size_t)j * (m + 1)];
       for (int k = 0; k < j; ++k) {
@@ -538,7 +565,7 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
       Qb((size_t)(nev + 1) * N * sizeof(double2)), RQb((size_t)(nev + 1) * N * sizeof(double2)),
       t(N * sizeof(double2)), Rt(N * sizeof(double2)), Xt(N * sizeof(double2)), r(N * sizeof(double2)),
       Xu(N * sizeof(double2)), y(N * sizeof(double2)), Ry(N * sizeof(double2)), py(N * sizeof(double2)),
-      Gb((size_t)(inner + 1) * N * sizeof(double2)), gw(N * sizeof(double2)), hd(1024 * sizeof(double2));
+      Gb((size_t)(inner + 1) * N * sizeof(double2)), hd(1024 * sizeof(double2));
   double2 *V = Vb.d(), *XV = XVb.d(), *RV = RVb.d(), *Q = Qb.d(), *RQ = RQb.d();
   JdResult out;
   std::vector<double2> hh(1024);
@@ -680,12 +707,13 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
     g[0] = bn;
     int nst = 0;
     for (int j = 0; j < inner; ++j) {
-      op(G + (size_t)j * N, gw.d());
-      double hn = K.orth(G, j + 1, gw.d(), h);
+      double2* gn = G + (size_t)(j + 1) * N;   // the new vector is built in its slot
+      op(G + (size_t)j * N, gn);
+      double hn = K.orth_next(G, j + 1, h);
       cplx* col = &Hg[(size_t)j * (inner + 1)];
       for (int q = 0; q <= j; ++q) col[q] = h[q];
       col[j + 1] = hn;
-      if (hn > 0) K.scale_copy(gw.d(), 1.0 / hn, G + (size_t)(j + 1) * N);
+      if (hn > 0) blas_scale(gn, make_double2(1.0 / hn, 0.0), N, s);
       for (int q = 0; q < j; ++q) {
         cplx a = col[q], b = col[q + 1];
         col[q] = std::conj(cs[q]) * a + std::conj(sn[q]) * b;
@@ -792,7 +820,8 @@ extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t max
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (nev < 1 || ncv <= nev || ncv > 1000 || ncv > h->dev.N || maxrestart < 0 || !(tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
-  if (gmres_restart < 1 || gmres_maxit < 1 || !(gmres_tol > 0)) return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters");
+  if (gmres_restart < 1 || gmres_restart > 1000 || gmres_maxit < 1 || !(gmres_tol > 0))
+    return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters (need 1 <= gmres_restart <= 1000)");
   if (precond && !h->dev.sai_val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
@@ -830,7 +859,8 @@ extern "C" cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (nev < 1 || ncv <= nev || ncv > 1000 || ncv > h->dev.N || maxrestart < 0 || !(tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
-  if (gmres_restart < 1 || gmres_maxit < 1 || !(gmres_tol > 0)) return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters");
+  if (gmres_restart < 1 || gmres_restart > 1000 || gmres_maxit < 1 || !(gmres_tol > 0))
+    return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters (need 1 <= gmres_restart <= 1000)");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
     cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
