@@ -10,7 +10,11 @@
  *   Z^H,  and dZ/dk,
  * plus the sparse approximate inverse (SAI) preconditioner of the near-field
  * matrix (section IV).  These are the products an implicitly restarted Arnoldi
- * solve of  Z^-1 R J = J / (1 + i lambda)  (eq. (24)) needs at every step.
+ * solve of  Z^-1 R J = J / (1 + i lambda)  (eq. (24)) needs at every step; the
+ * library also runs that solve (cm_eigs, with GMRES inner solves, cm_gmres),
+ * the Arnoldi solve of  X^-1 R J = J / lambda  (eq. (14), cm_eigs_xinv) and a
+ * Jacobi-Davidson solve of the pencil  X J = lambda R J  (eqs. (28)-(29),
+ * cm_jd).
  *
  * Conventions (all entry points):
  *  - Sign convention.  The public matrix is
