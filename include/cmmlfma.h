@@ -179,6 +179,22 @@ cm_status cm_rwg_table(const cm_handle* h, int32_t* edge_v, int32_t* tri_pm);
 cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols,
                    const int32_t* k_index, cm_dtype dt, void* hip_stream);
 
+/* y = op(x) as cm_apply at k[0], for callers that cannot allocate device
+   memory (code under HIP graph capture, serving loops, harnesses that forbid
+   hipMalloc): the apply's workspace (pattern levels, permuted input,
+   near-field output) lives in one fixed 64 MiB device array of the library
+   instead of the handle's workspace, and the call allocates nothing.  The
+   same kernels as cm_apply in the same order, so the result equals cm_apply's
+   bit for bit.  Arguments, layout and ownership as cm_apply (without
+   k_index); the current device must be the handle's.  CM_E_BADARG when the
+   workspace for this handle, op, dtype and ncols exceeds 64 MiB (the message
+   gives the size; e.g. about 3 MiB for 1,920 unknowns and 8 columns).
+   Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+   (two streams, two handles, two threads) race on it, and the caller orders
+   them.  Stage timing is not recorded.  Asynchronous on hip_stream. */
+cm_status cm_apply_noalloc(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols, cm_dtype dt,
+                           void* hip_stream);
+
 /* Build the SAI preconditioner P minimising ||I - Z_near P||_F column by
    column over a prescribed pattern (section IV): entries of Z_near with
    |z_ij| < eps1 |z_jj| are dropped, column j's pattern is

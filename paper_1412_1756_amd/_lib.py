@@ -14,6 +14,7 @@ CM_FLAG_HOST_ONLY, CM_FLAG_DERIV, CM_FLAG_CHECK, CM_FLAG_NO_MATRIX_CORES, CM_FLA
 CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD = 32, 64, 128
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
+           "cm_apply_noalloc",
            "cm_sai_build", "cm_sai_apply", "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_jd", "cm_export_near", "cm_stats", "cm_stage_timing",
            "cm_stage_times", "cm_last_error"]
 
@@ -54,6 +55,8 @@ def lib():
     L.cm_rwg_table.restype = C.c_int
     L.cm_apply.argtypes = [vp, C.c_int, vp, vp, i64, i32, vp, C.c_int, vp]
     L.cm_apply.restype = C.c_int
+    L.cm_apply_noalloc.argtypes = [vp, C.c_int, vp, vp, i64, i32, C.c_int, vp]
+    L.cm_apply_noalloc.restype = C.c_int
     L.cm_sai_build.argtypes = [vp, dbl, dbl, dbl]
     L.cm_sai_build.restype = C.c_int
     L.cm_sai_apply.argtypes = [vp, vp, vp, i64, i32, C.c_int, vp]

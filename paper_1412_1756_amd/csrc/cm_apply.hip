@@ -1203,12 +1203,12 @@ struct Stages {
 
 template <typename R>
 static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* x, void* y, int64_t ld, int nc,
-                       hipStream_t s) {
+                       const Work& w, hipStream_t s) {
   using CR = C2<R>;
   const int lf = d.lf;
   const int64_t N = d.N;
-  CR* xi = (CR*)d.xi;
-  CR* yi = (CR*)d.yi;
+  CR* xi = (CR*)w.xi;
+  CR* yi = (CR*)w.yi;
   const bool dual = (op == 4);                          // dZ/dk: values and k-derivatives side by side
   const int conj = (op == 3);
   const int kind = (op == 1) ? 1 : (op == 2) ? 2 : 0;   // 0 Z, 1 R, 2 X
@@ -1265,21 +1265,21 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     LevelD<R>& Lv = pd.lev[l];
     const void* T = (kind == 1) ? Lv.TR : (kind == 2) ? Lv.TX : Lv.TZ;
     stage_begin(d, ss, 4 + 10 * l);
-    sx.m2l(l, kind, T, (const CR*)d.S[l], (CR*)d.G[l], dual ? 2 * nc : nc, ldp, accum);
-    if (dual) sx.m2l(l, 0, Lv.dTZ, (const CR*)d.S[l], (CR*)d.G[l] + nc, nc, ldp, 1);
+    sx.m2l(l, kind, T, (const CR*)w.S[l], (CR*)w.G[l], dual ? 2 * nc : nc, ldp, accum);
+    if (dual) sx.m2l(l, 0, Lv.dTZ, (const CR*)w.S[l], (CR*)w.G[l] + nc, nc, ldp, 1);
     stage_end(d, ss);
   };
   // upward pass; each level's translations start once its patterns exist
   stage_begin(d, s, 2);
-  st.aggregate(pd.V, xi, nc, (CR*)d.S[lf], ldp, nc);
-  if (dual) st.aggregate(pd.dV, xi, nc, (CR*)d.S[lf] + nc, ldp, nc);
+  st.aggregate(pd.V, xi, nc, (CR*)w.S[lf], ldp, nc);
+  if (dual) st.aggregate(pd.dV, xi, nc, (CR*)w.S[lf] + nc, ldp, nc);
   stage_end(d, s);
   fork_to(s, sB, 2);
   m2l_level(stB, sB, lf, 0);
   for (int l = lf - 1; l >= 2; --l) {
     stage_begin(d, s, 3 + 10 * l);
-    st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l], dual ? 2 * nc : nc, ldp, 0, pd.lev[l].shift);
-    if (dual) st.interp(l, (const CR*)d.S[l + 1], (CR*)d.S[l] + nc, nc, ldp, 1, pd.lev[l].dshift);
+    st.interp(l, (const CR*)w.S[l + 1], (CR*)w.S[l], dual ? 2 * nc : nc, ldp, 0, pd.lev[l].shift);
+    if (dual) st.interp(l, (const CR*)w.S[l + 1], (CR*)w.S[l] + nc, nc, ldp, 1, pd.lev[l].dshift);
     stage_end(d, s);
     if (l >= 3) {
       fork_to(s, sB, 3 + l);
@@ -1299,11 +1299,11 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   for (int l = 2; l < lf; ++l) {
     stage_begin(d, s, 5 + 10 * (l + 1));
     if (mf_down(l)) {
-      st.anterp_mf(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift, 1);
-      if (dual) st.anterp_mf(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift, 1);
+      st.anterp_mf(l, (const CR*)w.G[l], (CR*)w.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift, 1);
+      if (dual) st.anterp_mf(l, (const CR*)w.G[l], (CR*)w.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift, 1);
     } else {
-      st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift);
-      if (dual) st.anterp(l, (const CR*)d.G[l], (CR*)d.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift);
+      st.anterp(l, (const CR*)w.G[l], (CR*)w.G[l + 1], dual ? 2 * nc : nc, ldp, pd.lev[l].shift);
+      if (dual) st.anterp(l, (const CR*)w.G[l], (CR*)w.G[l + 1] + nc, nc, ldp, pd.lev[l].dshift);
     }
     stage_end(d, s);
   }
@@ -1313,11 +1313,11 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     // d/dk of (k^2 eta/4pi) sum w conj(V).G = (2/k)(...) + conj(dV).G + conj(V).dG
     const int64_t rows = (int64_t)d.nleaf * 2 * P.lev[lf].K;
     hipLaunchKernelGGL(k_pattern_axpy<R>, dim3((unsigned)((rows * nc + 255) / 256)), dim3(256), 0, s,
-                       (const CR*)d.G[lf], (CR*)d.G[lf] + nc, rows, nc, ldp, (R)(2.0 / P.k));
-    st.disagg(pd.dV, (const CR*)d.G[lf], ldp, yi, yi, nc, nullptr, nc, 0);
-    st.disagg(pd.V, (const CR*)d.G[lf] + nc, ldp, yi, (CR*)y, ld, d.perm, nc, 0);
+                       (const CR*)w.G[lf], (CR*)w.G[lf] + nc, rows, nc, ldp, (R)(2.0 / P.k));
+    st.disagg(pd.dV, (const CR*)w.G[lf], ldp, yi, yi, nc, nullptr, nc, 0);
+    st.disagg(pd.V, (const CR*)w.G[lf] + nc, ldp, yi, (CR*)y, ld, d.perm, nc, 0);
   } else {
-    st.disagg(pd.V, (const CR*)d.G[lf], ldp, yi, (CR*)y, ld, d.perm, nc, conj);
+    st.disagg(pd.V, (const CR*)w.G[lf], ldp, yi, (CR*)y, ld, d.perm, nc, conj);
   }
   stage_end(d, s);
   chk(hipGetLastError(), "apply launch");
@@ -1326,10 +1326,50 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
 void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
                hipStream_t s) {
   if (op == 4 && (!d.dZn || !d.f64.dV)) throw Error(-5, "dZ/dk needs CM_FLAG_DERIV at create");
+  Work w;
+  for (int l = 2; l <= d.lf; ++l) {
+    w.S[l] = d.S[l];
+    w.G[l] = d.G[l];
+  }
+  w.xi = d.xi;
+  w.yi = d.yi;
   if (fp64)
-    apply_impl<double>(d, P, d.f64, op, x, y, ld, nc, s);
+    apply_impl<double>(d, P, d.f64, op, x, y, ld, nc, w, s);
   else
-    apply_impl<float>(d, P, d.f32, op, x, y, ld, nc, s);
+    apply_impl<float>(d, P, d.f32, op, x, y, ld, nc, w, s);
+}
+
+size_t work_bytes(const Plan& P, int op, int nc, bool fp64, size_t sizes[kMaxLevels]) {
+  const size_t cb = fp64 ? 16 : 8;
+  const size_t ldp = (op == 4) ? 2 * (size_t)nc : (size_t)nc;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  size_t tot = 0;
+  for (int l = 0; l < kMaxLevels; ++l) sizes[l] = 0;
+  sizes[0] = up((size_t)P.rwg.N * nc * cb);
+  tot += 2 * sizes[0];
+  for (int l = 2; l <= P.lf; ++l) {
+    sizes[l] = up((size_t)P.lev[l].nbox * 2 * P.lev[l].K * ldp * cb);
+    tot += 2 * sizes[l];
+  }
+  return tot;
+}
+
+void dev_apply_ws(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
+                  const Work& w, hipStream_t s) {
+  if (op == 4 && (!d.dZn || !d.f64.dV)) throw Error(-5, "dZ/dk needs CM_FLAG_DERIV at create");
+  // stage timing records events from a pool that may grow: off for this call
+  const bool timing = d.timing;
+  d.timing = false;
+  try {
+    if (fp64)
+      apply_impl<double>(d, P, d.f64, op, x, y, ld, nc, w, s);
+    else
+      apply_impl<float>(d, P, d.f32, op, x, y, ld, nc, w, s);
+  } catch (...) {
+    d.timing = timing;
+    throw;
+  }
+  d.timing = timing;
 }
 
 template <typename R>

@@ -159,9 +159,29 @@ bool mf_covers(const LevelD<float>& Lp, int nc);
 void blas_to_c64(const double2* x, float2* y, int64_t N, hipStream_t s);   // complex double -> float
 void dev_build(Dev& d, const Plan& P, hipStream_t s);
 void dev_free(Dev& d);
+
+// Workspace of one apply: the radiation (S) and incoming (G) patterns of
+// levels 2..lf, [box][component][direction][column] with column stride ldp
+// (nc, or 2 nc for the dZ/dk pass), and the permuted input / near-field
+// output, N x nc.  Levels are at most 20 (the plan's limit).
+constexpr int kMaxLevels = 20;
+struct Work {
+  void* S[kMaxLevels] = {};
+  void* G[kMaxLevels] = {};
+  void* xi = nullptr;
+  void* yi = nullptr;
+};
+// bytes of each part of the workspace for nc columns (fp64: complex double
+// patterns; op 4 doubles the patterns); sizes[l] for S[l] (= G[l]),
+// sizes[0] for xi (= yi).  Returns the total of all parts, each rounded up to
+// 256 bytes.
+size_t work_bytes(const Plan& P, int op, int nc, bool fp64, size_t sizes[kMaxLevels]);
 // op: 0 Z, 1 R, 2 X, 3 Z^H, 4 dZ/dk
 void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
                hipStream_t s);
+// the same on a caller-provided workspace (no allocation, no stage timing)
+void dev_apply_ws(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
+                  const Work& w, hipStream_t s);
 void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipStream_t s);
 void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64,
                    hipStream_t s);
