@@ -139,10 +139,19 @@ typedef struct {
   double eta;        /* wave impedance; <= 0 selects 376.730313668 ohm          */
   uint32_t flags;    /* CM_FLAG_*                                               */
   int32_t max_cols;  /* largest ncols any apply will use (1..64)                */
+  double k_sampling; /* wavenumber at which eq. (30) sets L and hence the
+                        angular sampling of every level; <= 0: each
+                        handle's (or sweep point's) own k.  A common value
+                        freezes L, the directions and the interpolation
+                        tables across handles at nearby wavenumbers, so
+                        that they differ only in the k-dependent values
+                        (translators, phases, patterns, near field): the
+                        discretisation whose k-derivative CM_OP_DZDK
+                        applies, e.g. for finite differences in k       */
 } cm_opts;
 
 /* Fill opts with defaults: nlv = 0 (must be set), d0 = 3, interp_p = 6,
-   eta = 376.730313668, flags = 0, max_cols = 32. */
+   eta = 376.730313668, flags = 0, max_cols = 32, k_sampling = 0. */
 void cm_default_opts(cm_opts* o);
 
 /* Build a handle.  xyz: host, n_vert x 3 float64 (wavelength units are the
@@ -195,16 +204,71 @@ cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, i
 cm_status cm_apply_noalloc(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols, cm_dtype dt,
                            void* hip_stream);
 
-/* Build the SAI preconditioner P minimising ||I - Z_near P||_F column by
-   column over a prescribed pattern (section IV): entries of Z_near with
-   |z_ij| < eps1 |z_jj| are dropped, column j's pattern is
-   {i : |z_ij| >= eps2 |z_jj|}, and entries of the solution with
-   |p_ij| < eps3 max_i |p_ij| are dropped afterwards.  Blocks. */
-cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3);
+/* Build the SAI preconditioner P minimising ||I - A P||_F column by column
+   over a prescribed pattern (section IV), for A = Z_near (part = CM_OP_Z, the
+   preconditioner of the inner solves with Z) or A = X_near = Im Z_near
+   (part = CM_OP_X, a real matrix: the preconditioner of the inner solves
+   with X in cm_eigs_xinv, an extension of this library; the paper documents
+   no preconditioner for X), at the wavenumber k[k_index] of the handle (a
+   sweep handle keeps one SAI of each part per wavenumber).  Entries of A
+   with |a_ij| < eps1 |a_jj| are dropped, column j's pattern is
+   {i : |a_ij| >= eps2 |a_jj|}, and entries of the solution with
+   |p_ij| < eps3 max_i |p_ij| are dropped afterwards.  CM_E_BADARG for a
+   threshold outside [0, 1], k_index outside [0, n_k) or another part.
+   Rebuilding replaces the previous P of that part and wavenumber.  Blocks. */
+cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3, int32_t k_index, cm_op part);
 
-/* y = P x (same vector conventions as cm_apply).  Asynchronous. */
-cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols,
-                       cm_dtype dt, void* hip_stream);
+/* y = P x for the SAI of part (CM_OP_Z or CM_OP_X); vector conventions and
+   k_index (per column, NULL = all at k[0]) as cm_apply.  CM_E_NOT_BUILT if
+   that SAI was not built for a wavenumber a column uses.  Asynchronous. */
+cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols, const int32_t* k_index,
+                       cm_op part, cm_dtype dt, void* hip_stream);
+
+/* out = sum_{i < N, c < ncols} conj(x[i*ld + c]) y[i*ld + c]: the complex
+   inner product of two N x ncols blocks (CM_C64 or CM_C128, accumulated in
+   FP64), written to out (DEVICE pointer, one complex128).  With y =
+   (dZ/dk) x this is the wavenumber gradient Re(g^H dZ/dk x) of the backward
+   pass (take the real part).  The sum is formed in a fixed order (partial sums
+   per block in the handle's reduction buffer, then the blocks in order), so
+   it is reproducible; calls that overlap on one handle race on that buffer.
+   Asynchronous on hip_stream. */
+cm_status cm_vdot(cm_handle* h, const void* x, const void* y, int64_t ld, int32_t ncols, cm_dtype dt, void* out,
+                  void* hip_stream);
+
+/* Real characteristic currents (section V): for each of the m complex128
+   columns of J (device, N x m row-major, row stride ldj; e.g. Ritz vectors,
+   each a real vector times a complex number), the phase that makes
+   sum_i J_i^2 real and positive is removed, the real part kept (Jr, with zero
+   imaginary parts) and scaled so that Jr^T R Jr = 1; RJr receives R Jr.  Jr
+   and RJr: device, N x m complex128, row stride ldo, caller-owned, not
+   aliasing J or each other.  All N-vector work on the device (FP64 R
+   products and reductions).  CM_E_NUMERIC if a column has no positive R-norm.
+   Synchronises with hip_stream. */
+cm_status cm_real_currents(cm_handle* h, const void* J, int64_t ldj, int32_t m, void* Jr, void* RJr, int64_t ldo,
+                           void* hip_stream);
+
+/* Modal correlation of two sets of currents through R at this handle's
+   wavenumber k[0] (the mode correspondence of a frequency sweep, section V):
+   C[a*mb + b] = |Ja_a^T R Jb_b| / sqrt(|Ja_a^T R Ja_a| |Jb_b^T R Jb_b|) for the
+   ma columns of Ja (device, N x ma complex128, row stride lda) and the mb
+   columns of Jb (row stride ldb); C: host, ma x mb.  FP64 R products and
+   device reductions.  Synchronises with hip_stream. */
+cm_status cm_modal_correlation(cm_handle* h, const void* Ja, int64_t lda, int32_t ma, const void* Jb, int64_t ldb,
+                               int32_t mb, double* C, void* hip_stream);
+
+/* d lambda/dk of one characteristic value lambda (real) or of one
+   (near-)degenerate cluster of m values around it, from the characteristic
+   equation X J = lambda R J differentiated at fixed tree and sampling:
+     d lambda/dk = eig( Q^T (X' - lambda R') Q ),   Q^T R Q = I,
+   with X' = Im dZ/dk, R' = Re dZ/dk (the dZ/dk pass, CM_FLAG_DERIV) and Q a
+   real R-orthonormal basis of the cluster (the m dominant directions of the
+   real span of J's real and imaginary parts); for m = 1 this is
+   J^T (X' - lambda R') J / J^T R J.  J: device, N x m complex128, row stride
+   ldj (1 <= m <= 256).  dldk: host, m values, ascending.  CM_E_NOT_BUILT
+   without CM_FLAG_DERIV, CM_E_NUMERIC if the span has no positive R-norm.
+   Synchronises with hip_stream. */
+cm_status cm_dlambda_dk(cm_handle* h, double lambda, const void* J, int64_t ldj, int32_t m, double* dldk,
+                        void* hip_stream);
 
 /* Right-preconditioned GMRES(restart) for Z x = b (the inner solves
    Z^-1 u of section IV), x = P u with the SAI P when precond != 0 (needs
@@ -241,16 +305,19 @@ cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, do
 
 /* Characteristic modes by the implicitly restarted Arnoldi method on
    OP = X^-1 R (the standard eigenvalue problem of eq. (14)): mu = 1/lambda,
-   so the nev largest |mu| are the smallest |lambda|.  Arguments, outputs and
-   counters[6] as cm_eigs, with unpreconditioned inner GMRES solves with X
-   (the paper notes that no efficient preconditioner for X is documented;
-   counters[4] is 0).  The cos-kernel expansion of X degrades on boxes small
-   against the wavelength, so this route suits trees whose leaves are not
-   far below 0.25 wavelength.  Synchronises. */
+   so the nev largest |mu| are the smallest |lambda|, well separated in
+   magnitude even where Z^-1 R (whose mu = 1/(1 + i lambda) crowd near 1)
+   clusters them.  Arguments, outputs and counters[6] as cm_eigs, with inner
+   GMRES solves with X, right-preconditioned when precond != 0 by the SAI of
+   X_near (cm_sai_build with part CM_OP_X; the paper notes that no efficient
+   preconditioner for X is documented: this one is the library's own).  The
+   cos-kernel expansion of X degrades on boxes small against the wavelength,
+   so this route suits trees whose leaves are not far below 0.25 wavelength.
+   Synchronises. */
 cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
-                       int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, cm_dtype far_dtype,
-                       double* lambda, double* ritz_resid, void* J, int32_t* nconv, int64_t* counters,
-                       void* hip_stream);
+                       int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond,
+                       cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
+                       int64_t* counters, void* hip_stream);
 
 /* Characteristic modes by Jacobi-Davidson on the pencil X J = lambda R J
    (eq. (6)) with the R-orthonormal search space and the projected correction
@@ -281,7 +348,7 @@ cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t 
 /* Copy the near-field matrix to host (public unknown order, CSR by row):
    row_ptr (N+1, int64), col (nnz, int32), val (nnz complex128 interleaved).
    Pass NULLs to query *nnz only.  which = 0: Z_near, 1: dZ_near/dk,
-   2: the SAI matrix P. */
+   2: the SAI matrix of Z_near, 3: the SAI matrix of X_near (at k[0]). */
 cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_t* row_ptr,
                          int32_t* col, double* val);
 

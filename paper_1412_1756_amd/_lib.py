@@ -15,13 +15,14 @@ CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD = 32, 64, 128
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
            "cm_apply_noalloc",
-           "cm_sai_build", "cm_sai_apply", "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_jd", "cm_export_near", "cm_stats", "cm_stage_timing",
+           "cm_sai_build", "cm_sai_apply", "cm_vdot", "cm_real_currents", "cm_modal_correlation", "cm_dlambda_dk",
+           "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_jd", "cm_export_near", "cm_stats", "cm_stage_timing",
            "cm_stage_times", "cm_last_error"]
 
 
 class cm_opts(C.Structure):
     _fields_ = [("nlv", C.c_int32), ("d0", C.c_double), ("interp_p", C.c_int32), ("eta", C.c_double),
-                ("flags", C.c_uint32), ("max_cols", C.c_int32)]
+                ("flags", C.c_uint32), ("max_cols", C.c_int32), ("k_sampling", C.c_double)]
 
 
 class CmError(RuntimeError):
@@ -57,10 +58,18 @@ def lib():
     L.cm_apply.restype = C.c_int
     L.cm_apply_noalloc.argtypes = [vp, C.c_int, vp, vp, i64, i32, C.c_int, vp]
     L.cm_apply_noalloc.restype = C.c_int
-    L.cm_sai_build.argtypes = [vp, dbl, dbl, dbl]
+    L.cm_sai_build.argtypes = [vp, dbl, dbl, dbl, i32, C.c_int]
     L.cm_sai_build.restype = C.c_int
-    L.cm_sai_apply.argtypes = [vp, vp, vp, i64, i32, C.c_int, vp]
+    L.cm_sai_apply.argtypes = [vp, vp, vp, i64, i32, vp, C.c_int, C.c_int, vp]
     L.cm_sai_apply.restype = C.c_int
+    L.cm_vdot.argtypes = [vp, vp, vp, i64, i32, C.c_int, vp, vp]
+    L.cm_vdot.restype = C.c_int
+    L.cm_real_currents.argtypes = [vp, vp, i64, i32, vp, vp, i64, vp]
+    L.cm_real_currents.restype = C.c_int
+    L.cm_modal_correlation.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, vp]
+    L.cm_modal_correlation.restype = C.c_int
+    L.cm_dlambda_dk.argtypes = [vp, dbl, vp, i64, i32, vp, vp]
+    L.cm_dlambda_dk.restype = C.c_int
     L.cm_export_near.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp]
     L.cm_export_near.restype = C.c_int
     L.cm_stats.argtypes = [vp, C.c_char_p, i64, C.POINTER(i64)]
@@ -69,7 +78,8 @@ def lib():
     L.cm_gmres.restype = C.c_int
     L.cm_eigs.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, i32, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
     L.cm_eigs.restype = C.c_int
-    L.cm_eigs_xinv.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
+    L.cm_eigs_xinv.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, i32, C.c_int, vp, vp, vp, C.POINTER(i32), vp,
+                               vp]
     L.cm_eigs_xinv.restype = C.c_int
     L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
     L.cm_jd.restype = C.c_int

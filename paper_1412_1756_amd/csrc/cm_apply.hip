@@ -1373,26 +1373,28 @@ void dev_apply_ws(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t
 }
 
 template <typename R>
-static void sai_apply_impl(Dev& d, const void* x, void* y, int64_t ld, int nc, hipStream_t s) {
+static void sai_apply_impl(Dev& d, const SaiD& q, const void* x, void* y, int64_t ld, int nc, hipStream_t s) {
   using CR = C2<R>;
   const int64_t N = d.N;
   int64_t tot = N * nc;
   hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
                      d.perm, (CR*)d.xi, N, 0);
   stage_begin(d, s, 7);
-  hipLaunchKernelGGL(k_sai_apply<R>, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, d.sai_ptr, d.sai_col,
-                     (const double2*)d.sai_val, (const CR*)d.xi, d.perm, (CR*)y, ld, N, nc);
+  hipLaunchKernelGGL(k_sai_apply<R>, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, q.ptr, q.col,
+                     (const double2*)q.val, (const CR*)d.xi, d.perm, (CR*)y, ld, N, nc);
   stage_end(d, s);
   chk(hipGetLastError(), "sai apply launch");
 }
 
-void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64, hipStream_t s) {
+void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64, int part,
+                   hipStream_t s) {
   (void)P;
-  if (!d.sai_val) throw Error(-5, "SAI preconditioner not built");
+  const SaiD& q = d.sai[part];
+  if (!q.val) throw Error(-5, "SAI preconditioner not built");
   if (fp64)
-    sai_apply_impl<double>(d, x, y, ld, nc, s);
+    sai_apply_impl<double>(d, q, x, y, ld, nc, s);
   else
-    sai_apply_impl<float>(d, x, y, ld, nc, s);
+    sai_apply_impl<float>(d, q, x, y, ld, nc, s);
 }
 
 }  // namespace cm

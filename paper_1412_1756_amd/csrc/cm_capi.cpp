@@ -15,6 +15,9 @@ namespace cm {
 void set_quadrature_constants();
 void launch_near_fill(double k, double eta, const Dev& d, int nbox, hipStream_t s);
 void launch_leaf_patterns(double k, const Dev& d, hipStream_t s);
+int blas_vdot_blocks();
+void blas_vdot(const void* x, const void* y, int64_t ld, int nc, int64_t N, bool fp64, double2* part, double2* out,
+               hipStream_t s);
 
 static void chk(hipError_t e, const char* what) {
   if (e != hipSuccess) {
@@ -290,6 +293,7 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   }
   d.xi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
   d.yi = dmalloc(d, (size_t)d.N * d.max_cols * sizeof(double2));
+  d.red = (double2*)dmalloc(d, (size_t)blas_vdot_blocks() * sizeof(double2));
   // streams and events of the concurrent apply
   for (auto& a : d.aux) chk(hipStreamCreateWithFlags(&a, hipStreamNonBlocking), "hipStreamCreateWithFlags");
   d.fork_ev.assign(4 + lf, nullptr);
@@ -311,12 +315,12 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
 void dev_free(Dev& d) {
   for (void* p : d.allocs) (void)hipFree(p);
   d.allocs.clear();
-  if (d.sai_ptr) (void)hipFree(d.sai_ptr);
-  if (d.sai_col) (void)hipFree(d.sai_col);
-  if (d.sai_val) (void)hipFree(d.sai_val);
-  d.sai_ptr = nullptr;
-  d.sai_col = nullptr;
-  d.sai_val = nullptr;
+  for (SaiD& q : d.sai) {
+    if (q.ptr) (void)hipFree(q.ptr);
+    if (q.col) (void)hipFree(q.col);
+    if (q.val) (void)hipFree(q.val);
+    q = SaiD();
+  }
   for (auto& m : d.marks) {
     (void)hipEventDestroy(m.a);
     (void)hipEventDestroy(m.b);
@@ -333,7 +337,6 @@ void dev_free(Dev& d) {
   d.event_pool.clear();
 }
 
-void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipStream_t s);
 
 }  // namespace cm
 
@@ -369,6 +372,7 @@ void cm_default_opts(cm_opts* o) {
   o->eta = 376.730313668;
   o->flags = 0;
   o->max_cols = 32;
+  o->k_sampling = 0;
 }
 
 static void destroy_handle(cm_handle* h) {
@@ -416,6 +420,7 @@ cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64
     op.eta = (o->eta > 0) ? o->eta : 376.730313668;
     op.flags = o->flags;
     op.max_cols = o->max_cols;
+    op.k_sampling = o->k_sampling;
     cm_handle* h = build_handle(xyz, n_vert, tri, n_tri, k[0], op, o->flags, (hipStream_t)hip_stream);
     try {
       for (int i = 1; i < n_k; ++i)
@@ -468,6 +473,59 @@ static cm_status check_vec_args(const cm_handle* h, const void* x, const void* y
   return CM_OK;
 }
 
+}  // extern "C"
+
+// Run per_k(t, x, y, ld, ncols, stream) for the columns of each wavenumber:
+// in place when every column has the same wavenumber, otherwise the columns
+// of each wavenumber are gathered into that wavenumber's staging block
+// (padded with zero columns to a multiple of 8 where the buffers allow it, so
+// that the batch takes the matrix-core kernels), processed on that
+// wavenumber's stream (forked from and joined to the caller's stream by
+// events) and scattered back.
+template <typename F>
+static void by_wavenumber(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols, const int32_t* k_index,
+                          bool fp64, hipStream_t s, F per_k) {
+  auto at = [&](int kk) { return kk == 0 ? h : h->sub[kk - 1]; };
+  const int nk = 1 + (int)h->sub.size();
+  bool one = true;
+  for (int j = 1; k_index && j < ncols; ++j) one = one && k_index[j] == k_index[0];
+  if (one) {
+    per_k(at(k_index ? k_index[0] : 0), x, y, ld, ncols, s);
+    return;
+  }
+  auto ok = [](hipError_t e) {
+    if (e != hipSuccess) throw cm::Error(CM_E_HIP, std::string("sweep: ") + hipGetErrorString(e));
+  };
+  ok(hipEventRecord(h->ks_in, s));
+  for (int kk = 0; kk < nk; ++kk) {
+    cm::ColList cl;
+    cl.n = 0;
+    for (int j = 0; j < ncols; ++j)
+      if (k_index[j] == kk) cl.c[cl.n++] = j;
+    if (cl.n == 0) continue;
+    cm_handle* t = at(kk);
+    const int w8 = (cl.n + 7) / 8 * 8;
+    const int ws = (w8 <= h->dev.max_cols) ? w8 : cl.n;
+    ok(hipStreamWaitEvent(t->ks, h->ks_in, 0));
+    cm::blas_gather_cols(x, ld, cl, ws, t->xs, h->dev.N, fp64, t->ks);
+    per_k(t, t->xs, t->ys, ws, ws, t->ks);
+    cm::blas_scatter_cols(t->ys, ws, cl, y, ld, h->dev.N, fp64, t->ks);
+    ok(hipEventRecord(t->ks_out, t->ks));
+    ok(hipStreamWaitEvent(s, t->ks_out, 0));
+  }
+  if (hipGetLastError() != hipSuccess) throw cm::Error(CM_E_HIP, "sweep gather/scatter launch");
+}
+
+extern "C" {
+
+static cm_status check_k_index(const cm_handle* h, const int32_t* k_index, int32_t ncols) {
+  const int nk = 1 + (int)h->sub.size();
+  if (k_index)
+    for (int j = 0; j < ncols; ++j)
+      if (k_index[j] < 0 || k_index[j] >= nk) return fail(CM_E_BADARG, "k_index out of range [0, n_k)");
+  return CM_OK;
+}
+
 cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols,
                    const int32_t* k_index, cm_dtype dt, void* hip_stream) {
   g_err.clear();
@@ -476,70 +534,66 @@ cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, i
   if ((int)op < 0 || (int)op > 4) return fail(CM_E_BADARG, "bad op");
   if (op == CM_OP_DZDK && !(h->plan.opt.flags & CM_FLAG_DERIV))
     return fail(CM_E_NOT_BUILT, "dZ/dk needs CM_FLAG_DERIV at create");
-  const int nk = 1 + (int)h->sub.size();
-  if (k_index)
-    for (int j = 0; j < ncols; ++j)
-      if (k_index[j] < 0 || k_index[j] >= nk) return fail(CM_E_BADARG, "k_index out of range [0, n_k)");
+  if ((st = check_k_index(h, k_index, ncols)) != CM_OK) return st;
   const bool fp64 = dt == CM_C128;
-  hipStream_t s = (hipStream_t)hip_stream;
-  auto at = [&](int kk) { return kk == 0 ? h : h->sub[kk - 1]; };
   CM_TRY({
-    bool one = true;   // every column at the same wavenumber: in place
-    for (int j = 1; k_index && j < ncols; ++j) one = one && k_index[j] == k_index[0];
-    if (one) {
-      cm_handle* t = at(k_index ? k_index[0] : 0);
-      cm::dev_apply(t->dev, t->plan, (int)op, x, y, ld, ncols, fp64, s);
-      return CM_OK;
-    }
-    // gather the columns of each wavenumber into that wavenumber's staging
-    // block, apply and scatter back, each wavenumber on its own stream (forked
-    // from and joined to the caller's stream by events)
-    auto ok = [](hipError_t e) {
-      if (e != hipSuccess) throw cm::Error(CM_E_HIP, std::string("sweep: ") + hipGetErrorString(e));
-    };
-    ok(hipEventRecord(h->ks_in, s));
-    for (int kk = 0; kk < nk; ++kk) {
-      cm::ColList cl;
-      cl.n = 0;
-      for (int j = 0; j < ncols; ++j)
-        if (k_index[j] == kk) cl.c[cl.n++] = j;
-      if (cl.n == 0) continue;
-      cm_handle* t = at(kk);
-      // staging width padded with zero columns to a multiple of 8 where the
-      // buffers allow it, so the batch takes the matrix-core kernels
-      const int w8 = (cl.n + 7) / 8 * 8;
-      const int ws = (w8 <= h->dev.max_cols) ? w8 : cl.n;
-      ok(hipStreamWaitEvent(t->ks, h->ks_in, 0));
-      cm::blas_gather_cols(x, ld, cl, ws, t->xs, h->dev.N, fp64, t->ks);
-      cm::dev_apply(t->dev, t->plan, (int)op, t->xs, t->ys, ws, ws, fp64, t->ks);
-      cm::blas_scatter_cols(t->ys, ws, cl, y, ld, h->dev.N, fp64, t->ks);
-      ok(hipEventRecord(t->ks_out, t->ks));
-      ok(hipStreamWaitEvent(s, t->ks_out, 0));
-    }
-    if (hipGetLastError() != hipSuccess) throw cm::Error(CM_E_HIP, "sweep gather/scatter launch");
+    by_wavenumber(h, x, y, ld, ncols, k_index, fp64, (hipStream_t)hip_stream,
+                  [&](cm_handle* t, const void* xx, void* yy, int64_t l, int n, hipStream_t ss) {
+                    cm::dev_apply(t->dev, t->plan, (int)op, xx, yy, l, n, fp64, ss);
+                  });
     return CM_OK;
   })
 }
 
-cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3) {
+static int sai_part(cm_op part) { return part == CM_OP_X ? 1 : part == CM_OP_Z ? 0 : -1; }
+
+cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3, int32_t k_index, cm_op part) {
   g_err.clear();
   if (!h) return fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (!(eps1 >= 0) || !(eps2 >= 0) || !(eps3 >= 0) || eps1 > 1 || eps2 > 1 || eps3 > 1)
     return fail(CM_E_BADARG, "thresholds must be in [0, 1]");
+  if (k_index < 0 || k_index > (int)h->sub.size()) return fail(CM_E_BADARG, "k_index out of range [0, n_k)");
+  if (sai_part(part) < 0) return fail(CM_E_BADARG, "part must be CM_OP_Z or CM_OP_X");
+  cm_handle* t = k_index == 0 ? h : h->sub[k_index - 1];
   CM_TRY({
-    cm::dev_sai_build(h->dev, h->plan, eps1, eps2, eps3, nullptr);
+    cm::dev_sai_build(t->dev, t->plan, eps1, eps2, eps3, sai_part(part), nullptr);
     return CM_OK;
   })
 }
 
-cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols, cm_dtype dt,
-                       void* hip_stream) {
+cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols, const int32_t* k_index,
+                       cm_op part, cm_dtype dt, void* hip_stream) {
   g_err.clear();
   cm_status st = check_vec_args(h, x, y, ld, ncols, dt);
   if (st != CM_OK) return st;
+  if ((st = check_k_index(h, k_index, ncols)) != CM_OK) return st;
+  const int pt = sai_part(part);
+  if (pt < 0) return fail(CM_E_BADARG, "part must be CM_OP_Z or CM_OP_X");
+  for (int j = 0; j < (k_index ? ncols : 1); ++j) {
+    const cm_handle* t = (!k_index || k_index[j] == 0) ? h : h->sub[k_index[j] - 1];
+    if (!t->dev.sai[pt].val) return fail(CM_E_NOT_BUILT, "SAI not built for this wavenumber and part");
+  }
+  const bool fp64 = dt == CM_C128;
   CM_TRY({
-    cm::dev_sai_apply(h->dev, h->plan, x, y, ld, ncols, dt == CM_C128, (hipStream_t)hip_stream);
+    by_wavenumber(h, x, y, ld, ncols, k_index, fp64, (hipStream_t)hip_stream,
+                  [&](cm_handle* t, const void* xx, void* yy, int64_t l, int n, hipStream_t ss) {
+                    cm::dev_sai_apply(t->dev, t->plan, xx, yy, l, n, fp64, pt, ss);
+                  });
+    return CM_OK;
+  })
+}
+
+cm_status cm_vdot(cm_handle* h, const void* x, const void* y, int64_t ld, int32_t ncols, cm_dtype dt, void* out,
+                  void* hip_stream) {
+  g_err.clear();
+  if (!h || !x || !y || !out) return fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (ncols < 1 || ld < ncols) return fail(CM_E_BADARG, "need ncols >= 1 and ld >= ncols");
+  if (dt != CM_C64 && dt != CM_C128) return fail(CM_E_BADARG, "bad dtype");
+  CM_TRY({
+    cm::blas_vdot(x, y, ld, ncols, h->dev.N, dt == CM_C128, h->dev.red, (double2*)out, (hipStream_t)hip_stream);
+    if (hipGetLastError() != hipSuccess) throw cm::Error(CM_E_HIP, "vdot launch");
     return CM_OK;
   })
 }
@@ -580,19 +634,20 @@ cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_
       return CM_OK;
     })
   }
-  if (which == 2) {
-    if (!d.sai_val) return fail(CM_E_NOT_BUILT, "SAI not built");
-    *nnz = d.sai_nnz;
+  if (which == 2 || which == 3) {
+    const cm::SaiD& q = d.sai[which - 2];
+    if (!q.val) return fail(CM_E_NOT_BUILT, "SAI not built");
+    *nnz = q.nnz;
     if (!row_ptr && !col && !val) return CM_OK;
     if (!row_ptr || !col || !val) return fail(CM_E_BADARG, "null output array");
     CM_TRY({
       const int64_t N = P.rwg.N;
       std::vector<int64_t> ptr(N + 1);
-      std::vector<int32_t> c(d.sai_nnz);
-      std::vector<double2> v(d.sai_nnz);
-      cm::chk(hipMemcpy(ptr.data(), d.sai_ptr, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost), "export");
-      cm::chk(hipMemcpy(c.data(), d.sai_col, d.sai_nnz * sizeof(int32_t), hipMemcpyDeviceToHost), "export");
-      cm::chk(hipMemcpy(v.data(), d.sai_val, d.sai_nnz * sizeof(double2), hipMemcpyDeviceToHost), "export");
+      std::vector<int32_t> c(q.nnz);
+      std::vector<double2> v(q.nnz);
+      cm::chk(hipMemcpy(ptr.data(), q.ptr, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost), "export");
+      cm::chk(hipMemcpy(c.data(), q.col, q.nnz * sizeof(int32_t), hipMemcpyDeviceToHost), "export");
+      cm::chk(hipMemcpy(v.data(), q.val, q.nnz * sizeof(double2), hipMemcpyDeviceToHost), "export");
       row_ptr[0] = 0;
       for (int64_t m = 0; m < N; ++m) {
         int64_t i = P.iperm[m];
@@ -610,7 +665,7 @@ cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_
       return CM_OK;
     })
   }
-  return fail(CM_E_BADARG, "which must be 0, 1 or 2");
+  return fail(CM_E_BADARG, "which must be 0, 1, 2 or 3");
 }
 
 cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* needed) {

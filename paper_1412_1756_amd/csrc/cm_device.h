@@ -74,6 +74,14 @@ struct PrecD {
   std::vector<LevelD<R>> lev;
 };
 
+// A sparse approximate inverse in CSR by internal rows (internal column indices).
+struct SaiD {
+  int64_t nnz = 0;
+  int64_t* ptr = nullptr;                   // N + 1
+  int32_t* col = nullptr;
+  double2* val = nullptr;
+};
+
 struct Dev {
   int device = 0;
   int64_t N = 0, nnz = 0;
@@ -94,11 +102,9 @@ struct Dev {
   // workspace (sized for max_cols, complex double; reused as complex float)
   std::vector<void*> S, G, dS, dG;          // per level
   void *xi = nullptr, *yi = nullptr, *dxi = nullptr;
-  // SAI
-  int64_t sai_nnz = 0;
-  int64_t* sai_ptr = nullptr;               // internal rows of P (N+1)
-  int32_t* sai_col = nullptr;               // internal column indices
-  double2* sai_val = nullptr;
+  // SAI preconditioners: sai[0] of Z_near, sai[1] of X_near = Im Z_near
+  SaiD sai[2];
+  double2* red = nullptr;                   // partial sums of cm_vdot (blas_vdot_blocks() entries)
   std::vector<void*> allocs;
   // optional per-stage timing (HIP events on the apply stream)
   bool timing = false;
@@ -182,11 +188,22 @@ void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld
 // the same on a caller-provided workspace (no allocation, no stage timing)
 void dev_apply_ws(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
                   const Work& w, hipStream_t s);
-void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipStream_t s);
-void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64,
+// SAI of Z_near (part 0) or X_near (part 1)
+void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, int part, hipStream_t s);
+void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64, int part,
                    hipStream_t s);
 
 }  // namespace cm
+
+// Device state of a device-resident GMRES cycle (k_gmres_step).
+struct GmState {
+  int need2;       // the current column needs the second Gram-Schmidt pass
+  int stop;        // breakdown: the Krylov space is invariant
+  int nvalid;      // columns formed in this cycle
+  int pad;
+  double inv_hn;   // 1 / ||w|| of the last column (0 on breakdown)
+  double res;      // |g[j+1]|: the residual norm estimate after the last column
+};
 
 // gather / scatter of up to 64 columns (by index) of an N x ld complex array
 namespace cm {

@@ -17,8 +17,14 @@
 
 namespace cm {
 
-void blas_multidot(const double2* V, int64_t ldv, const double2* w, int64_t N, int nk, double2* h, hipStream_t s);
-void blas_gemv_sub(const double2* V, int64_t ldv, const double2* h, int nk, double2* w, int64_t N, hipStream_t s);
+int blas_multidot_blocks(int64_t N);
+void blas_multidot_wide(const double2* V, int64_t ldv, const double2* w, int64_t N, int nk, double2* part,
+                        double2* h, const int* flag, hipStream_t s);
+void blas_gemv_sub(const double2* V, int64_t ldv, const double2* h, int nk, double2* w, int64_t N, hipStream_t s,
+                   const int* flag = nullptr);
+void blas_gmres_step(int j, int m, const double2* hc, double2* col, double2* H, double2* g, double2* cs, double2* sn,
+                     GmState* st, int pass, hipStream_t s);
+void blas_scale_by_state(double2* y, const GmState* st, int64_t N, hipStream_t s);
 void blas_axpby(const double2* x, double2 alpha, double2* y, int64_t N, int accumulate, hipStream_t s);
 void blas_scale(double2* y, double2 alpha, int64_t N, hipStream_t s);
 void blas_basis_update(const double2* V, int64_t ldv, const double2* Q, int ldq, int nk, int nc, double2* Vout,
@@ -48,9 +54,34 @@ struct DevBuf {
 // orthogonalisation of w against V[0..j).
 class KrylovCtx {
  public:
-  KrylovCtx(Dev& d, const Plan& P, bool far64, hipStream_t s)
-      : d_(d), P_(P), far64_(far64), s_(s), N_(d.N), t32a_(d.N * sizeof(float2)), t32b_(d.N * sizeof(float2)),
-        hdev_(1024 * sizeof(double2)) {}
+  // sai_part: the SAI that precond() applies (0: of Z_near, 1: of X_near)
+  KrylovCtx(Dev& d, const Plan& P, bool far64, hipStream_t s, int sai_part = 0)
+      : d_(d), P_(P), far64_(far64), s_(s), N_(d.N), sai_part_(sai_part), t32a_(d.N * sizeof(float2)),
+        t32b_(d.N * sizeof(float2)), hdev_(1025 * sizeof(double2)),
+        part_((size_t)1025 * blas_multidot_blocks(d.N) * sizeof(double2)) {
+    chk_d(hipHostMalloc((void**)&pin_, kRing * sizeof(double), hipHostMallocDefault), "pinned residuals");
+    for (auto& e : ev_) {
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        release();
+        throw Error(-4, "hipEventCreateWithFlags");
+      }
+    }
+  }
+  ~KrylovCtx() { release(); }
+  KrylovCtx(const KrylovCtx&) = delete;
+  KrylovCtx& operator=(const KrylovCtx&) = delete;
+
+  // residual estimate of device GMRES iteration j: copied to pinned host
+  // memory behind the iteration's work (post_residual) and read once its
+  // event has completed (residual); a ring of kRing slots
+  void post_residual(int j, const double* dres) {
+    chk_d(hipMemcpyAsync(pin_ + j % kRing, dres, sizeof(double), hipMemcpyDeviceToHost, s_), "residual copy");
+    chk_d(hipEventRecord(ev_[j % kRing], s_), "residual event");
+  }
+  double residual(int j) {
+    chk_d(hipEventSynchronize(ev_[j % kRing]), "residual event");
+    return pin_[j % kRing];
+  }
 
   int64_t N() const { return N_; }
   hipStream_t stream() const { return s_; }
@@ -66,10 +97,16 @@ class KrylovCtx {
       blas_to_c128((const float2*)t32b_.p, y, N_, s_);
     }
   }
-  void precond(const double2* x, double2* y) { dev_sai_apply(d_, P_, x, y, 1, 1, true, s_); }
+  void precond(const double2* x, double2* y) { dev_sai_apply(d_, P_, x, y, 1, 1, true, sai_part_, s_); }
+
+  // h[k] = V[k]^H w, k < nk <= 1025 (device output), over all CUs
+  void multidot(const double2* V, int nk, const double2* w, double2* h) {
+    if (nk > 1025) throw Error(-1, "multidot: more than 1025 vectors");
+    blas_multidot_wide(V, N_, w, N_, nk, part_.d(), h, nullptr, s_);
+  }
 
   double norm(const double2* w) {
-    blas_multidot(w, N_, w, N_, 1, hdev_.d(), s_);
+    multidot(w, 1, w, hdev_.d());
     double2 h;
     chk_d(hipMemcpyAsync(&h, hdev_.p, sizeof h, hipMemcpyDeviceToHost, s_), "norm");
     chk_d(hipStreamSynchronize(s_), "norm");
@@ -84,7 +121,7 @@ class KrylovCtx {
     if (j == 0) return before;
     std::vector<double2> hh(j);
     for (int pass = 0; pass < 2; ++pass) {
-      blas_multidot(V, N_, w, N_, j, hdev_.d(), s_);
+      multidot(V, j, w, hdev_.d());
       blas_gemv_sub(V, N_, hdev_.d(), j, w, N_, s_);
       chk_d(hipMemcpyAsync(hh.data(), hdev_.p, j * sizeof(double2), hipMemcpyDeviceToHost, s_), "orth");
       chk_d(hipStreamSynchronize(s_), "orth");
@@ -105,7 +142,7 @@ class KrylovCtx {
     h.assign(j, cplx(0));
     std::vector<double2> hh(j + 1);
     for (int pass = 0; pass < 2; ++pass) {
-      blas_multidot(V, N_, w, N_, j + 1, hdev_.d(), s_);   // V[0..j]^H w; the last entry is w^H w
+      multidot(V, j + 1, w, hdev_.d());   // V[0..j]^H w; the last entry is w^H w
       if (j > 0) blas_gemv_sub(V, N_, hdev_.d(), j, w, N_, s_);
       chk_d(hipMemcpyAsync(hh.data(), hdev_.p, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, s_), "orth");
       chk_d(hipStreamSynchronize(s_), "orth");
@@ -144,7 +181,20 @@ class KrylovCtx {
   bool far64_;
   hipStream_t s_;
   int64_t N_;
-  DevBuf t32a_, t32b_, hdev_;
+  int sai_part_;
+  DevBuf t32a_, t32b_, hdev_, part_;
+  static constexpr int kRing = 8;
+  double* pin_ = nullptr;
+  hipEvent_t ev_[kRing] = {};
+  void release() {
+    for (auto& e : ev_)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+    if (pin_) (void)hipHostFree(pin_);
+    pin_ = nullptr;
+  }
 };
 
 // ---------------------------------------------------------------- GMRES
@@ -155,31 +205,56 @@ struct GmresResult {
 };
 
 // Solve A x = b, right-preconditioned by the SAI P (x = P u) when precond;
-// A = Z (aop 0) or X (aop 2, the route of eq. (14); no preconditioner).
+// A = Z (aop 0) or X (aop 2, the route of eq. (14)), P the SAI that the
+// context's precond() applies (of Z_near or of X_near).
+//
+// Each iteration is enqueued without a host round trip: the Gram-Schmidt
+// coefficients come from an all-CU multidot, the Hessenberg column, its
+// Givens rotation and the residual estimate from k_gmres_step, and the
+// conditional second (DGKS) pass runs or skips on a device flag.  The host
+// reads the residual estimate of the iteration two behind the one it has just
+// enqueued (pinned memory, one event per iteration), so the GPU always has
+// work queued; a cycle that converges may therefore take up to two more
+// columns, which only lowers the residual.  The small triangular solve at the
+// end of a cycle runs on the host.
 static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int maxit, double tol, bool precond,
                          int aop = 0) {
   const int64_t N = K.N();
+  hipStream_t s = K.stream();
+  const int nblk = blas_multidot_blocks(N);
   DevBuf Vb((size_t)(m + 1) * N * sizeof(double2)), w(N * sizeof(double2)), z(N * sizeof(double2)),
-      u(N * sizeof(double2));
+      u(N * sizeof(double2)), part((size_t)(m + 2) * nblk * sizeof(double2)),
+      small((size_t)((m + 1) * m + (m + 1) + 2 * m + 2 * (m + 2)) * sizeof(double2) + sizeof(GmState));
   double2* V = Vb.d();
+  double2* Hd = small.d();
+  double2* gd = Hd + (size_t)(m + 1) * m;
+  double2* csd = gd + (m + 1);
+  double2* snd = csd + m;
+  double2* hc = snd + m;
+  double2* col = hc + (m + 2);
+  GmState* st = reinterpret_cast<GmState*>(col + (m + 2));
+  constexpr int kLag = 2;
   GmresResult res;
-  chk_d(hipMemsetAsync(x, 0, N * sizeof(double2), K.stream()), "gmres");
+  chk_d(hipMemsetAsync(x, 0, N * sizeof(double2), s), "gmres");
   const double bn = K.norm(b);
   if (bn == 0) {
     res.converged = true;
     return res;
   }
-  // r = b (x0 = 0)
-  K.scale_copy(b, 1.0, w.d());
+  K.scale_copy(b, 1.0, w.d());   // r = b (x0 = 0)
   double beta = bn;
-  std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), h;
+  std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1);
+  std::vector<double2> Hh((size_t)(m + 1) * m), gh(m + 1);
   while (res.iters < maxit) {
     K.scale_copy(w.d(), 1.0 / beta, V);
-    std::fill(H.begin(), H.end(), cplx(0));
-    std::fill(g.begin(), g.end(), cplx(0));
-    g[0] = beta;
-    int jend = -1;
-    for (int j = 0; j < m && res.iters < maxit; ++j) {
+    GmState s0{};
+    std::vector<double2> g0(m + 1, make_double2(0.0, 0.0));
+    g0[0] = make_double2(beta, 0.0);
+    chk_d(hipMemcpyAsync(gd, g0.data(), (m + 1) * sizeof(double2), hipMemcpyHostToDevice, s), "gmres");
+    chk_d(hipMemcpyAsync(st, &s0, sizeof s0, hipMemcpyHostToDevice, s), "gmres");
+    const int jmax = std::min(m, maxit - res.iters);
+    int j = 0;
+    for (; j < jmax; ++j) {
       const double2* vj = V + (size_t)j * N;
       double2* vn = V + (size_t)(j + 1) * N;   // the new vector is built in its slot
       if (precond) {
@@ -188,41 +263,37 @@ static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int 
       } else {
         K.apply(aop, vj, vn);
       }
-      double hn = K.orth_next(V, j + 1, h);
-      for (int k = 0; k <= j; ++k) H[(size_t)j * (m + 1) + k] = h[k];
-      H[(size_t)j * (m + 1) + j + 1] = hn;
-      if (hn > 0) blas_scale(vn, make_double2(1.0 / hn, 0.0), N, K.stream());
-      // previous rotations on column j
-      cplx* col = &H[(size_t)j * (m + 1)];
-      for (int k = 0; k < j; ++k) {
-        cplx a = col[k], c2 = col[k + 1];
-        col[k] = std::conj(cs[k]) * a + std::conj(sn[k]) * c2;
-        col[k + 1] = -sn[k] * a + cs[k] * c2;
+      blas_multidot_wide(V, N, vn, N, j + 2, part.d(), hc, nullptr, s);   // V[0..j]^H w and w^H w
+      blas_gemv_sub(V, N, hc, j + 1, vn, N, s);
+      blas_gmres_step(j, m, hc, col, Hd, gd, csd, snd, st, 0, s);
+      blas_multidot_wide(V, N, vn, N, j + 2, part.d(), hc, &st->need2, s);   // second pass, if requested
+      blas_gemv_sub(V, N, hc, j + 1, vn, N, s, &st->need2);
+      blas_gmres_step(j, m, hc, col, Hd, gd, csd, snd, st, 1, s);
+      blas_scale_by_state(vn, st, N, s);
+      K.post_residual(j, &st->res);
+      if (j >= kLag && K.residual(j - kLag) <= tol * bn) {
+        ++j;
+        break;
       }
-      // new rotation zeroing col[j+1]
-      double r = std::hypot(std::abs(col[j]), std::abs(col[j + 1]));
-      if (r == 0) {
-        cs[j] = 1;
-        sn[j] = 0;
-      } else {
-        cs[j] = col[j] / r;
-        sn[j] = col[j + 1] / r;
-      }
-      col[j] = r;
-      col[j + 1] = 0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = std::conj(cs[j]) * g[j];
-      ++res.iters;
-      jend = j;
-      if (std::abs(g[j + 1]) / bn <= tol || hn == 0) break;
     }
-    // y = H^-1 g (upper triangular), u = V y, x += P u
-    const int n = jend + 1;
+    chk_d(hipStreamSynchronize(s), "gmres cycle");
+    GmState sh;
+    chk_d(hipMemcpy(&sh, st, sizeof sh, hipMemcpyDeviceToHost), "gmres state");
+    const int n = sh.nvalid;
+    res.iters += n;
+    if (n == 0) break;
+    chk_d(hipMemcpy(Hh.data(), Hd, (size_t)(m + 1) * n * sizeof(double2), hipMemcpyDeviceToHost), "gmres H");
+    chk_d(hipMemcpy(gh.data(), gd, (size_t)(n + 1) * sizeof(double2), hipMemcpyDeviceToHost), "gmres g");
+    // y = R^-1 g (upper triangular), u = V y, x += P u
     std::vector<cplx> y(n);
     for (int k = n - 1; k >= 0; --k) {
-      cplx s = g[k];
-      for (int c = k + 1; c < n; ++c) s -= H[(size_t)c * (m + 1) + k] * y[c];
-      y[k] = s / H[(size_t)k * (m + 1) + k];
+      cplx sacc(gh[k].x, gh[k].y);
+      for (int c = k + 1; c < n; ++c) {
+        const double2 hv = Hh[(size_t)c * (m + 1) + k];
+        sacc -= cplx(hv.x, hv.y) * y[c];
+      }
+      const double2 d = Hh[(size_t)k * (m + 1) + k];
+      y[k] = sacc / cplx(d.x, d.y);
     }
     K.combine(V, n, y, n, 1, u.d());
     if (precond) {
@@ -241,6 +312,7 @@ static GmresResult gmres(KrylovCtx& K, const double2* b, double2* x, int m, int 
       res.converged = true;
       break;
     }
+    if (sh.stop) break;   // invariant Krylov space: x is as good as this operator allows
   }
   return res;
 }
@@ -498,7 +570,7 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
 
 // Eigenvalues (ascending) and eigenvectors (columns of S) of a small
 // Hermitian matrix by cyclic complex Jacobi rotations.
-static void herm_eig(Mat A, int n, std::vector<double>& w, Mat& S) {
+void herm_eig(Mat A, int n, std::vector<double>& w, Mat& S) {
   S.assign((size_t)n * n, cplx(0));
   for (int i = 0; i < n; ++i) at(S, n, i, i) = 1;
   for (int sweep = 0; sweep < 100; ++sweep) {
@@ -570,14 +642,14 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
   JdResult out;
   std::vector<double2> hh(1024);
   auto dots = [&](const double2* A, int nk, const double2* w) {   // A^H w, nk <= 1024, on the host
-    blas_multidot(A, N, w, N, nk, hd.d(), s);
+    K.multidot(A, nk, w, hd.d());
     chk_d(hipMemcpyAsync(hh.data(), hd.p, nk * sizeof(double2), hipMemcpyDeviceToHost, s), "jd dots");
     chk_d(hipStreamSynchronize(s), "jd dots");
   };
   // w -= B (A^H w) for the nk columns of A, B
   auto project = [&](const double2* A, const double2* B, int nk, double2* w) {
     if (nk == 0) return;
-    blas_multidot(A, N, w, N, nk, hd.d(), s);
+    K.multidot(A, nk, w, hd.d());
     blas_gemv_sub(B, N, hd.d(), nk, w, N, s);
   };
   auto copy = [&](const double2* x, double2* z, size_t n) {
@@ -762,7 +834,7 @@ extern "C" cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t rest
   if (!h || !b || !x) return cm::driver_fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (restart < 1 || restart > 1000 || maxit < 1 || !(tol > 0)) return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters");
-  if (precond && !h->dev.sai_val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (precond && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
   if (b == x) return cm::driver_fail(CM_E_BADARG, "b and x must not alias");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
@@ -788,7 +860,7 @@ extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmi
     return cm::driver_fail(CM_E_BADARG,
                            "bad Jacobi-Davidson parameters (need 1 <= nev <= 512, 1 <= mmin < mmax <= min(N, 512), "
                            "maxit >= 1, tol > 0, 1 <= inner_steps <= 512)");
-  if (precond && !h->dev.sai_val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (precond && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
     cm::JdResult r =
@@ -822,7 +894,7 @@ extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t max
     return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
   if (gmres_restart < 1 || gmres_restart > 1000 || gmres_maxit < 1 || !(gmres_tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters (need 1 <= gmres_restart <= 1000)");
-  if (precond && !h->dev.sai_val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (precond && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
     cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
@@ -853,18 +925,19 @@ extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t max
 
 extern "C" cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol,
                                   const void* v0, int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol,
-                                  cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
-                                  int64_t* counters, void* hip_stream) {
+                                  int32_t precond, cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J,
+                                  int32_t* nconv, int64_t* counters, void* hip_stream) {
   if (!h || !v0 || !lambda) return cm::driver_fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (nev < 1 || ncv <= nev || ncv > 1000 || ncv > h->dev.N || maxrestart < 0 || !(tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
   if (gmres_restart < 1 || gmres_restart > 1000 || gmres_maxit < 1 || !(gmres_tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters (need 1 <= gmres_restart <= 1000)");
+  if (precond && !h->dev.sai[1].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI of X not built");
   try {
-    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream, 1);
     cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
-                                gmres_tol, false, (double2*)J, 2);
+                                gmres_tol, precond != 0, (double2*)J, 2);
     for (int i = 0; i < nev; ++i) {
       // X^-1 R J = mu J  <=>  X J = (1 / mu) R J
       cm::cplx lam = 1.0 / r.mu[i];
@@ -878,7 +951,7 @@ extern "C" cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_
       counters[1] = r.gmres_iters;
       counters[2] = r.n_matvec;
       counters[3] = r.restarts;
-      counters[4] = 0;
+      counters[4] = r.inner_retries;
       counters[5] = r.inner_failures;
     }
     return (r.nconv >= nev && r.inner_failures == 0) ? CM_OK : CM_E_NOT_CONVERGED;

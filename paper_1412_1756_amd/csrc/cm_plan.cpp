@@ -274,6 +274,8 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
   if (o.nlv < 3 || o.nlv > 20) throw Error(-1, "nlv must be in [3, 20]");
   if (o.p < 2 || o.p > 12 || (o.p & 1)) throw Error(-1, "interp_p must be even in [2, 12]");
   if (!(o.d0 > 0) || o.d0 > 20) throw Error(-1, "d0 must be in (0, 20]");
+  if (!(o.k_sampling <= 0 || (std::isfinite(o.k_sampling) && o.k_sampling < 1e6)))
+    throw Error(-1, "k_sampling must be finite");
   if (o.max_cols < 1 || o.max_cols > 64) throw Error(-1, "max_cols must be in [1, 64]");
   nv = n_vert;
   nt = n_tri;
@@ -594,7 +596,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
   qw.assign(lf + 1, {});
   for (int l = 2; l <= lf; ++l) {
     Level& Lv = lev[l];
-    double kd = k * std::sqrt(3.0) * Lv.a;
+    const double kd = (o.k_sampling > 0 ? o.k_sampling : k) * std::sqrt(3.0) * Lv.a;
     Lv.L = (int)std::ceil(kd + 1.8 * std::pow(o.d0, 2.0 / 3.0) * std::cbrt(kd));
     Lv.nt = Lv.L + 1;
     Lv.np = 2 * (Lv.L + 1);
@@ -874,7 +876,7 @@ std::string Plan::stats_json() const {
   std::ostringstream s;
   s.precision(17);
   s << "{\"N\": " << rwg.N << ", \"n_tri\": " << nt << ", \"k\": " << k << ", \"nlv\": " << nlv
-    << ", \"d0\": " << opt.d0 << ", \"interp_p\": " << opt.p << ", \"wide_near\": " << ((opt.flags & 32u) ? 1 : 0) << ", \"r_lists\": \"" << ((opt.flags & 128u) ? "standard" : "siblings") << "\"" << ", \"root_side\": " << side
+    << ", \"d0\": " << opt.d0 << ", \"k_sampling\": " << (opt.k_sampling > 0 ? opt.k_sampling : k) << ", \"interp_p\": " << opt.p << ", \"wide_near\": " << ((opt.flags & 32u) ? 1 : 0) << ", \"r_lists\": \"" << ((opt.flags & 128u) ? "standard" : "siblings") << "\"" << ", \"root_side\": " << side
     << ", \"nnz_near\": " << nnz << ", \"near_cols_total\": " << bcol.size()
     << ", \"n_leaf\": " << lev[lf].nbox << ", \"levels\": [";
   for (int l = 0; l <= lf; ++l) {

@@ -92,6 +92,7 @@ struct Opts {
   double eta = 376.730313668;
   uint32_t flags = 0;
   int max_cols = 32;
+  double k_sampling = 0;   // wavenumber of the truncation rule and sampling (<= 0: k)
 };
 
 // Offsets between boxes at one level (each component in -5..5, enough for

@@ -3,7 +3,9 @@
 // them): Z~ drops entries |z_ij| < eps1 |z_jj| of column j; column j of P lives
 // on J_j = {i : |z_ij| >= eps2 |z_jj|}; the rows taking part are the nonzero
 // rows of Z~(:, J_j); entries |p_ij| < eps3 max_i |p_ij| are dropped after the
-// solve.  Set-up work on the host: the near field is copied down once, every
+// solve.  The same construction serves the near field of X = Im Z (a real
+// matrix) for the inner solves with X.  Set-up work on the host: the near
+// field is copied down once, every
 // column's small least-squares problem is solved by Householder QR in FP64,
 // and P is uploaded in CSR by rows for the device apply.
 #include <hip/hip_runtime.h>
@@ -11,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <exception>
 #include <thread>
 #include <vector>
 
@@ -61,11 +64,14 @@ static void lsq_householder(int m, int n, std::vector<cplx>& A, std::vector<cplx
   }
 }
 
-void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipStream_t s) {
+void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, int part, hipStream_t s) {
   const int64_t N = d.N;
   std::vector<double2> zn(P.nnz);
-  chk_s(hipMemcpy(zn.data(), d.Zn, P.nnz * sizeof(double2), hipMemcpyDeviceToHost), "SAI: copy near field");
-  (void)s;
+  chk_s(hipMemcpyAsync(zn.data(), d.Zn, P.nnz * sizeof(double2), hipMemcpyDeviceToHost, s), "SAI: copy near field");
+  chk_s(hipStreamSynchronize(s), "SAI: copy near field");
+  // part 1: the near field of X = Im Z (a real matrix)
+  if (part == 1)
+    for (auto& z : zn) z = make_double2(z.y, 0.0);
   // row i of Z_near (internal order) = column i (Z_near is symmetric)
   auto row_cols = [&](int64_t i, const int32_t*& cols, const double2*& vals, int& n) {
     int b = P.box_of[i];
@@ -86,8 +92,12 @@ void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipSt
   std::vector<std::vector<std::pair<int32_t, cplx>>> colP(N);
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::thread> th;
+  // an exception in a worker (e.g. std::bad_alloc) is kept and rethrown after
+  // the join, so that the C ABI returns a status instead of terminating
+  std::vector<std::exception_ptr> err(nth);
   for (unsigned t = 0; t < nth; ++t)
     th.emplace_back([&, t]() {
+     try {
       std::vector<int32_t> J, I;
       std::vector<cplx> A, b, p;
       for (int64_t j = t; j < N; j += nth) {
@@ -133,8 +143,13 @@ void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipSt
         for (int c = 0; c < n; ++c)
           if (std::abs(p[c]) >= e3 * pm && std::abs(p[c]) > 0) colP[j].push_back({J[c], p[c]});
       }
+     } catch (...) {
+      err[t] = std::current_exception();
+     }
     });
   for (auto& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
   // transpose to CSR by rows (internal indices)
   std::vector<int64_t> ptr(N + 1, 0);
   for (int64_t j = 0; j < N; ++j)
@@ -150,23 +165,22 @@ void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, hipSt
       col[at] = (int32_t)j;
       val[at] = make_double2(e.second.real(), e.second.imag());
     }
-  if (d.sai_ptr) {
-    (void)hipFree(d.sai_ptr);
-    (void)hipFree(d.sai_col);
-    (void)hipFree(d.sai_val);
-    d.sai_ptr = nullptr;
-    d.sai_col = nullptr;
-    d.sai_val = nullptr;
+  SaiD& q = d.sai[part];
+  if (q.ptr) {
+    (void)hipFree(q.ptr);
+    (void)hipFree(q.col);
+    (void)hipFree(q.val);
+    q = SaiD();
   }
-  chk_s(hipMalloc(&d.sai_ptr, (N + 1) * sizeof(int64_t)), "SAI alloc");
-  chk_s(hipMalloc(&d.sai_col, std::max<int64_t>(1, nnz) * sizeof(int32_t)), "SAI alloc");
-  chk_s(hipMalloc(&d.sai_val, std::max<int64_t>(1, nnz) * sizeof(double2)), "SAI alloc");
-  chk_s(hipMemcpy(d.sai_ptr, ptr.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice), "SAI upload");
+  chk_s(hipMalloc(&q.ptr, (N + 1) * sizeof(int64_t)), "SAI alloc");
+  chk_s(hipMalloc(&q.col, std::max<int64_t>(1, nnz) * sizeof(int32_t)), "SAI alloc");
+  chk_s(hipMalloc(&q.val, std::max<int64_t>(1, nnz) * sizeof(double2)), "SAI alloc");
+  chk_s(hipMemcpy(q.ptr, ptr.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice), "SAI upload");
   if (nnz) {
-    chk_s(hipMemcpy(d.sai_col, col.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice), "SAI upload");
-    chk_s(hipMemcpy(d.sai_val, val.data(), nnz * sizeof(double2), hipMemcpyHostToDevice), "SAI upload");
+    chk_s(hipMemcpy(q.col, col.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice), "SAI upload");
+    chk_s(hipMemcpy(q.val, val.data(), nnz * sizeof(double2), hipMemcpyHostToDevice), "SAI upload");
   }
-  d.sai_nnz = nnz;
+  q.nnz = nnz;
 }
 
 }  // namespace cm

@@ -19,14 +19,15 @@ class Operator:
     autotune=True times the matrix-core interpolation variants per level at
     create and keeps the fastest (CM_FLAG_AUTOTUNE); r_standard=True gives
     R x the standard MLFMA lists instead of the sibling bookkeeping
-    (CM_FLAG_R_STANDARD).  k may
-    be a sequence of wavenumbers (a sweep; apply's k_index picks one per
-    column).
+    (CM_FLAG_R_STANDARD); k_sampling: the wavenumber at which the
+    truncation rule sets L and the sampling (None: k itself; a common value
+    freezes the discretisation across handles at nearby k).  k may be a
+    sequence of wavenumbers (a sweep; apply's k_index picks one per column).
     """
 
     def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
                  deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, wide_near=False,
-                 autotune=False, r_standard=False, stream=None):
+                 autotune=False, r_standard=False, k_sampling=None, stream=None):
         L = lib()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -38,6 +39,7 @@ class Operator:
         if eta is not None:
             o.eta = float(eta)
         o.max_cols = int(max_cols)
+        o.k_sampling = float(k_sampling) if k_sampling else 0.0
         o.flags = ((_lib.CM_FLAG_HOST_ONLY if host_only else 0) | (_lib.CM_FLAG_DERIV if deriv else 0)
                    | (_lib.CM_FLAG_CHECK if check_coverage else 0)
                    | (0 if matrix_cores else _lib.CM_FLAG_NO_MATRIX_CORES)
@@ -118,7 +120,13 @@ class Operator:
         return sp.csr_matrix((val[0::2] + 1j * val[1::2], col, ptr), shape=(self.N, self.N))
 
     # ------------------------------------------------------------ device applies
+    def _device(self):
+        import torch
+        return torch.device("cuda", torch.cuda.current_device())
+
     def _vec_args(self, x, out):
+        """x as a row-major (N, ncols) view with unit column stride, and an
+        output of the same dtype, shape, device and row stride."""
         import torch
         if not isinstance(x, torch.Tensor) or not x.is_cuda:
             raise TypeError("x must be a CUDA (HIP) torch tensor")
@@ -126,49 +134,145 @@ class Operator:
             raise TypeError("x must be complex64 or complex128")
         squeeze = x.dim() == 1
         X = x.reshape(-1, 1) if squeeze else x
+        if X.dim() != 2:
+            raise ValueError("x must have shape (N,) or (N, ncols)")
         if X.shape[0] != self.N:
             raise ValueError(f"x has {X.shape[0]} rows, operator has N={self.N}")
-        if X.stride(1) != 1:
+        if X.stride(1) != 1 or X.stride(0) < X.shape[1]:
             X = X.contiguous()
         if out is None:
-            out = torch.empty((self.N, X.shape[1]), dtype=X.dtype, device=X.device)
-        elif out.dim() == 1:
-            out = out.reshape(-1, 1)
-        if out.stride(1) != 1 or out.stride(0) != X.stride(0):
-            raise ValueError("out must be row-major with the same row stride as x")
+            # same row stride as X (a column slice of a wider tensor keeps its stride)
+            out = torch.empty_strided(X.shape, (X.stride(0), 1), dtype=X.dtype, device=X.device)
+        else:
+            if not isinstance(out, torch.Tensor) or not out.is_cuda:
+                raise TypeError("out must be a CUDA (HIP) torch tensor")
+            if out.dim() == 1:
+                out = out.reshape(-1, 1)
+            if out.dtype != X.dtype:
+                raise TypeError(f"out has dtype {out.dtype}, x has {X.dtype}")
+            if tuple(out.shape) != tuple(X.shape):
+                raise ValueError(f"out has shape {tuple(out.shape)}, x has {tuple(X.shape)}")
+            if out.device != X.device:
+                raise ValueError("out and x are on different devices")
+            if out.stride(1) != 1 or out.stride(0) != X.stride(0):
+                raise ValueError("out must be row-major with the same row stride as x")
         dt = _lib.CM_C128 if X.dtype == torch.complex128 else _lib.CM_C64
         return X, out, dt, squeeze
+
+    def _start_vector(self, v0):
+        """v0 checked for the Krylov drivers: complex128, N entries, CUDA."""
+        import torch
+        if not isinstance(v0, torch.Tensor) or not v0.is_cuda:
+            raise TypeError("v0 must be a CUDA (HIP) torch tensor")
+        if v0.dtype != torch.complex128:
+            raise TypeError("v0 must be complex128")
+        if v0.numel() != self.N:
+            raise ValueError(f"v0 has {v0.numel()} entries, operator has N={self.N}")
+        return v0.reshape(-1).contiguous()
+
+    @staticmethod
+    def _k_index(k_index, ncols):
+        if k_index is None:
+            return None
+        ki = np.ascontiguousarray(np.asarray(k_index, dtype=np.int32).reshape(-1))
+        if ki.size != ncols:
+            raise ValueError("k_index needs one entry per column")
+        return ki
 
     def apply(self, x, op="Z", out=None, stream=None, k_index=None):
         """y = op(x) for x of shape (N,) or (N, ncols) on the GPU; k_index: one
         index into the handle's wavenumbers per column (None: all at k[0])."""
         X, Y, dt, squeeze = self._vec_args(x, out)
-        ki = None
-        if k_index is not None:
-            ki = np.ascontiguousarray(np.asarray(k_index, dtype=np.int32).reshape(-1))
-            if ki.size != X.shape[1]:
-                raise ValueError("k_index needs one entry per column")
+        ki = self._k_index(k_index, X.shape[1])
         st = lib().cm_apply(self._h, _lib.OPS[op], C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
                             X.stride(0), X.shape[1], None if ki is None else C.c_void_p(ki.ctypes.data),
                             dt, self._stream_ptr(stream))
         check(st)
         return Y.reshape(-1) if squeeze else Y
 
-    def sai_build(self, eps1=0.01, eps2=0.014, eps3=0.18):
-        check(lib().cm_sai_build(self._h, eps1, eps2, eps3))
+    _PARTS = {"Z": 0, "X": 2}
 
-    def sai_nnz(self):
-        """Stored entries of the SAI matrix (after sai_build)."""
+    def sai_build(self, eps1=0.01, eps2=0.014, eps3=0.18, k_index=0, part="Z"):
+        """SAI of the near field of Z (part="Z") or of X (part="X") at the
+        wavenumber ks[k_index]."""
+        check(lib().cm_sai_build(self._h, eps1, eps2, eps3, int(k_index), self._PARTS[part]))
+
+    def sai_nnz(self, part="Z"):
+        """Stored entries of the SAI matrix (after sai_build; at k[0])."""
         nnz = C.c_int64()
-        check(lib().cm_export_near(self._h, 2, C.byref(nnz), None, None, None))
+        check(lib().cm_export_near(self._h, 2 if part == "Z" else 3, C.byref(nnz), None, None, None))
         return int(nnz.value)
 
-    def sai_apply(self, x, out=None, stream=None):
+    def sai_apply(self, x, out=None, stream=None, k_index=None, part="Z"):
         X, Y, dt, squeeze = self._vec_args(x, out)
+        ki = self._k_index(k_index, X.shape[1])
         st = lib().cm_sai_apply(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.stride(0),
-                                X.shape[1], dt, self._stream_ptr(stream))
+                                X.shape[1], None if ki is None else C.c_void_p(ki.ctypes.data), self._PARTS[part],
+                                dt, self._stream_ptr(stream))
         check(st)
         return Y.reshape(-1) if squeeze else Y
+
+    def vdot(self, x, y, stream=None):
+        """sum conj(x) * y over all entries of two (N,) or (N, ncols) CUDA
+        tensors of one dtype, as a complex128 scalar tensor on the device
+        (formed in the library in a fixed order; asynchronous)."""
+        import torch
+        X, _, dt, _ = self._vec_args(x, None)
+        Y, _, dt2, _ = self._vec_args(y, None)
+        if dt != dt2 or tuple(X.shape) != tuple(Y.shape):
+            raise ValueError("x and y need the same dtype and shape")
+        if Y.stride(0) != X.stride(0):
+            X, Y = X.contiguous(), Y.contiguous()
+        out = torch.empty((), dtype=torch.complex128, device=X.device)
+        check(lib().cm_vdot(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.stride(0), X.shape[1],
+                            dt, C.c_void_p(out.data_ptr()), self._stream_ptr(stream)))
+        return out
+
+    def _modes_arg(self, J):
+        import torch
+        if not isinstance(J, torch.Tensor) or not J.is_cuda or J.dtype != torch.complex128:
+            raise TypeError("J must be a complex128 CUDA tensor")
+        J = J.reshape(-1, 1) if J.dim() == 1 else J
+        if J.dim() != 2 or J.shape[0] != self.N:
+            raise ValueError(f"J must have shape (N,) or (N, m) with N={self.N}")
+        if J.stride(1) != 1 or J.stride(0) < J.shape[1]:
+            J = J.contiguous()
+        return J
+
+    def real_currents(self, J, stream=None):
+        """(Jr, R Jr): the real, R-normalised currents (Jr^T R Jr = 1) of the
+        columns of J (complex128, (N, m)), as complex128 CUDA tensors with
+        zero imaginary parts."""
+        import torch
+        J = self._modes_arg(J)
+        m = J.shape[1]
+        Jr = torch.empty((self.N, m), dtype=torch.complex128, device=J.device)
+        RJ = torch.empty_like(Jr)
+        check(lib().cm_real_currents(self._h, C.c_void_p(J.data_ptr()), J.stride(0), m, C.c_void_p(Jr.data_ptr()),
+                                     C.c_void_p(RJ.data_ptr()), m, self._stream_ptr(stream)))
+        return Jr, RJ
+
+    def modal_correlation(self, Ja, Jb, stream=None):
+        """|Ja^T R Jb| normalised by the R-norms of both (numpy, ma x mb), R at
+        this operator's wavenumber."""
+        Ja = self._modes_arg(Ja)
+        Jb = self._modes_arg(Jb)
+        Cm = np.zeros((Ja.shape[1], Jb.shape[1]))
+        check(lib().cm_modal_correlation(self._h, C.c_void_p(Ja.data_ptr()), Ja.stride(0), Ja.shape[1],
+                                         C.c_void_p(Jb.data_ptr()), Jb.stride(0), Jb.shape[1], Cm.ctypes.data,
+                                         self._stream_ptr(stream)))
+        return Cm
+
+    def dlambda_dk(self, lam, J, stream=None):
+        """d lambda/dk of a characteristic value (or of a degenerate cluster
+        around it) from its vectors J ((N,) or (N, m) complex128); returns m
+        values, ascending (cm_dlambda_dk)."""
+        J = self._modes_arg(J)
+        m = J.shape[1]
+        d = np.zeros(m)
+        check(lib().cm_dlambda_dk(self._h, float(lam), C.c_void_p(J.data_ptr()), J.stride(0), m, d.ctypes.data,
+                                  self._stream_ptr(stream)))
+        return d
 
     # ------------------------------------------------------------ Krylov drivers
     def gmres(self, b, restart=50, maxit=500, tol=1e-6, precond=True, far="fp64", stream=None,
@@ -176,9 +280,9 @@ class Operator:
         """Solve Z x = b (b: CUDA complex128 tensor of N).  Returns
         (x, iterations, final relative residual, converged)."""
         import torch
-        b = b.contiguous()
-        if b.dtype != torch.complex128 or b.numel() != self.N:
+        if not isinstance(b, torch.Tensor) or not b.is_cuda or b.dtype != torch.complex128 or b.numel() != self.N:
             raise TypeError("b must be a complex128 CUDA tensor of N entries")
+        b = b.reshape(-1).contiguous()
         x = torch.empty_like(b)
         it = C.c_int32()
         rr = C.c_double()
@@ -199,7 +303,7 @@ class Operator:
         precond_dropped, converged); the preconditioner is dropped after
         max(50, maxit / 8) outer iterations without a new converged pair."""
         import torch
-        v0 = v0.contiguous()
+        v0 = self._start_vector(v0)
         lam = np.zeros(nev)
         res = np.zeros(nev)
         cnt = np.zeros(4, dtype=np.int64)
@@ -218,16 +322,17 @@ class Operator:
                     converged=(st == _lib.CM_OK))
 
     def eigs(self, nev, ncv, v0, tol=1e-8, maxrestart=50, gmres_restart=50, gmres_maxit=1000, gmres_tol=1e-8,
-             precond=True, far="fp64", vectors=True, stream=None, route="Z"):
+             precond=None, far="fp64", vectors=True, stream=None, route="Z"):
         """Characteristic values by implicitly restarted Arnoldi on Z^-1 R.
         v0: CUDA complex128 start vector.  Returns dict(lam, resid, J, nconv,
         n_op, gmres_iters, n_matvec, restarts, inner_retries, inner_failures,
         converged); converged is False when fewer than nev Ritz values
         converged or when an inner GMRES solve missed gmres_tol.  route="X":
-        IRA on X^-1 R (eq. (14), unpreconditioned inner solves with X;
-        precond is ignored) instead of Z^-1 R."""
+        IRA on X^-1 R (eq. (14)) instead of Z^-1 R, its inner solves with X
+        preconditioned by the SAI of X_near when precond (sai_build(part="X")
+        first).  precond=None: True for route "Z", False for route "X"."""
         import torch
-        v0 = v0.contiguous()
+        v0 = self._start_vector(v0)
         lam = np.zeros(2 * nev)
         res = np.zeros(nev)
         cnt = np.zeros(6, dtype=np.int64)
@@ -235,10 +340,12 @@ class Operator:
         nconv = C.c_int32()
         fd = _lib.CM_C128 if far == "fp64" else _lib.CM_C64
         Jp = C.c_void_p(J.data_ptr()) if vectors else None
+        if precond is None:
+            precond = route == "Z"
         if route == "X":
             st = lib().cm_eigs_xinv(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
-                                    gmres_maxit, gmres_tol, fd, lam.ctypes.data, res.ctypes.data, Jp,
-                                    C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
+                                    gmres_maxit, gmres_tol, 1 if precond else 0, fd, lam.ctypes.data,
+                                    res.ctypes.data, Jp, C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
         elif route == "Z":
             st = lib().cm_eigs(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
                                gmres_maxit, gmres_tol, 1 if precond else 0, fd, lam.ctypes.data, res.ctypes.data,

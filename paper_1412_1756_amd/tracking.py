@@ -1,34 +1,28 @@
 """Characteristic modes followed over a wavenumber sweep (the plate sweep of
 section V, where each characteristic value is plotted against frequency).
 
-At every wavenumber: the SAI build, the implicitly restarted Arnoldi solve
-(cm_eigs), real R-normalised currents and d lambda/dk per mode from the dZ/dk
-pass.  Between consecutive wavenumbers the modes are matched by modal
-correlation |J_a(k_i)^T R(k_{i+1}) J_b(k_{i+1})| of R-normalised real
-currents, maximised over all one-to-one correspondences (a linear assignment
-of an nev x nev matrix).  Every product with Z, R and dZ/dk runs in the
-library; the host handles the nev x nev matrices and N x nev dot products.
-Modes are assumed non-degenerate (inside a degenerate cluster the
-correspondence is arbitrary).
+At every wavenumber: the SAI build, the eigen-solve (IRA, cm_eigs, or
+Jacobi-Davidson, cm_jd), real R-normalised currents (cm_real_currents) and
+d lambda/dk per mode from the dZ/dk pass (cm_dlambda_dk).  Between
+consecutive wavenumbers the modes are matched by modal correlation
+|J_a(k_i)^T R(k_{i+1}) J_b(k_{i+1})| of R-normalised real currents
+(cm_modal_correlation), maximised over all one-to-one correspondences (a
+linear assignment of an nev x nev matrix on the host).  Every product and
+every N-vector reduction runs in the library; the host handles only the
+nev x nev matrices.  Modes are assumed non-degenerate (inside a degenerate
+cluster the correspondence is arbitrary).
 """
 import numpy as np
-import torch
 from scipy.optimize import linear_sum_assignment
-
-from .autograd import dlambda_dk
 
 
 def real_currents(op, J):
-    """Real currents J^T R J = 1 from IRA eigenvectors (N x m complex128 CUDA
+    """Real currents J^T R J = 1 from eigenvectors (N x m complex128 CUDA
     tensor; each column a real vector times a complex scalar): the column is
     turned by the phase that makes sum_i J_i^2 real and positive, its real
-    part kept and scaled.  Returns (J, R J) as N x m complex128 CUDA tensors
-    with zero imaginary parts."""
-    ph = torch.exp(-0.5j * torch.angle((J * J).sum(0)))
-    Jr = (J * ph[None, :]).real.to(torch.complex128).contiguous()
-    RJ = op.apply(Jr, "R")
-    nrm = torch.sqrt((Jr.real * RJ.real).sum(0))
-    return Jr / nrm[None, :], RJ / nrm[None, :]
+    part kept and scaled (cm_real_currents).  Returns (J, R J) as N x m
+    complex128 CUDA tensors with zero imaginary parts."""
+    return op.real_currents(J)
 
 
 def track_modes(make_op, ks, nev, ncv, v0, ntrack=None, sai=(0.01, 0.014, 0.18), solver="ira", **eig_kw):
@@ -87,15 +81,13 @@ def track_modes(make_op, ks, nev, ncv, v0, ntrack=None, sai=(0.01, 0.014, 0.18),
         order = np.argsort(np.abs(lam))
         lam = lam[order]
         J, RJ = real_currents(op, r["J"][:, order.tolist()])
-        d = np.array([dlambda_dk(op, lam[j], J[:, j])[0] for j in range(nev)])
+        d = np.array([op.dlambda_dk(lam[j], J[:, j])[0] for j in range(nev)])
         if Jprev is None:
             perm = np.arange(m)
         else:
-            # correlations with R at this wavenumber; the new currents are
-            # R-normalised here, the previous ones are normalised by R J_prev
-            RJp = op.apply(Jprev, "R").real.cpu().numpy()
-            Jp = Jprev.real.cpu().numpy()
-            C = np.abs(Jp.T @ RJ.real.cpu().numpy()) / np.sqrt(np.sum(Jp * RJp, axis=0))[:, None]
+            # correlations with R at this wavenumber (both sets normalised by
+            # their R-norms at this wavenumber)
+            C = op.modal_correlation(Jprev, J)
             rows, cols = linear_sum_assignment(-C)          # m x nev, m <= nev
             perm = cols[np.argsort(rows)]
             corr[i - 1] = C[np.arange(m), perm]

@@ -42,6 +42,28 @@ class DenseOp:
         r = self.eigs(nev, 0, v0)
         return dict(lam=r["lam"].real, J=r["J"], nconv=nev, converged=True, n_matvec=0)
 
+    # the library's mode post-processing, written out densely from its
+    # definitions (cm_real_currents, cm_modal_correlation, cm_dlambda_dk)
+    def real_currents(self, J):
+        Jn = J.numpy()
+        ph = np.exp(-0.5j * np.angle((Jn * Jn).sum(0)))
+        Jr = (Jn * ph[None, :]).real
+        RJ = self.Z.real @ Jr
+        nrm = np.sqrt((Jr * RJ).sum(0))
+        return (torch.tensor(Jr / nrm[None, :], dtype=torch.complex128),
+                torch.tensor(RJ / nrm[None, :], dtype=torch.complex128))
+
+    def modal_correlation(self, Ja, Jb):
+        A, B = Ja.numpy(), Jb.numpy()
+        R = self.Z.real
+        na = np.abs(np.einsum("ia,ia->a", A, R @ A))
+        nb = np.abs(np.einsum("ib,ib->b", B, R @ B))
+        return np.abs(A.T @ (R @ B)) / np.sqrt(na[:, None] * nb[None, :])
+
+    def dlambda_dk(self, lam, J):
+        j = J.numpy().real.reshape(self.N, -1)
+        return np.atleast_1d(modes.dlambda_dk(j, np.atleast_1d(lam), self.dZ.imag, self.dZ.real, self.Z.real))
+
 
 @pytest.mark.parametrize("solver", ["ira", "jd"])
 def test_tracker_matches_oracle_on_dense_plate(solver):
