@@ -118,8 +118,12 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
                                   interpolation and anterpolation kernels of
                                   each level at the batch width (largest
                                   multiple of 8 up to max_cols, at most 64)
-                                  and keep the fastest (reported by
-                                  cm_stats under "autotune").  Changes only
+                                  and keep the fastest, and likewise the
+                                  translation kernel of each level (16-box
+                                  tiles or 64-box tiles whose waves share
+                                  their sources through LDS; these give the
+                                  same bits) (reported by cm_stats under
+                                  "autotune").  Changes only
                                   the summation grouping: results differ
                                   from an untuned handle by FP32 rounding,
                                   and the choice may differ between handles */
@@ -130,6 +134,16 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
                                   recommends for R after eq. (22); same
                                   operator, several times more leaf
                                   translations                               */
+
+#define CM_FLAG_M2L_TILE16 512u /* keep the autotuner (CM_FLAG_AUTOTUNE) from
+                                  trying the 64-box shared-source translation
+                                  kernels: FP32 batched translations always
+                                  use receiver tiles of 16 boxes (the
+                                  default without the autotuner; the kernels
+                                  give the same bits)                        */
+#define CM_FLAG_VERBOSE   256u /* the eigen-solvers print one progress line to
+                                  stderr per Arnoldi restart (cm_eigs,
+                                  cm_eigs_xinv) or converged pair (cm_jd) */
 
 typedef struct {
   int32_t nlv;       /* number of octree levels including level 0 (>= 3)        */
@@ -205,24 +219,28 @@ cm_status cm_apply_noalloc(cm_handle* h, cm_op op, const void* x, void* y, int64
                            void* hip_stream);
 
 /* Build the SAI preconditioner P minimising ||I - A P||_F column by column
-   over a prescribed pattern (section IV), for A = Z_near (part = CM_OP_Z, the
-   preconditioner of the inner solves with Z) or A = X_near = Im Z_near
-   (part = CM_OP_X, a real matrix: the preconditioner of the inner solves
-   with X in cm_eigs_xinv, an extension of this library; the paper documents
-   no preconditioner for X), at the wavenumber k[k_index] of the handle (a
-   sweep handle keeps one SAI of each part per wavenumber).  Entries of A
-   with |a_ij| < eps1 |a_jj| are dropped, column j's pattern is
+   over a prescribed pattern (section IV), for the near field A of the
+   operator tau R + i X: tau = 1 gives A = Z_near (the paper's preconditioner
+   of the inner solves with Z); other tau > 0 give tau Re Z_near + i Im Z_near
+   (the inner solves of cm_eigs with that shift); tau = 0 gives the real
+   matrix X_near = Im Z_near (the inner solves with X of cm_eigs_xinv).  The
+   shifted operators and their preconditioners are an extension of this
+   library (the paper documents no preconditioner for X).  At the wavenumber
+   k[k_index] of the handle: a sweep handle keeps, per wavenumber, one SAI of
+   Z_near and one of the most recent other tau.  Entries of A with
+   |a_ij| < eps1 |a_jj| are dropped, column j's pattern is
    {i : |a_ij| >= eps2 |a_jj|}, and entries of the solution with
    |p_ij| < eps3 max_i |p_ij| are dropped afterwards.  CM_E_BADARG for a
-   threshold outside [0, 1], k_index outside [0, n_k) or another part.
-   Rebuilding replaces the previous P of that part and wavenumber.  Blocks. */
-cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3, int32_t k_index, cm_op part);
+   threshold outside [0, 1], k_index outside [0, n_k) or tau outside
+   [0, 1e6].  Rebuilding replaces the previous P of that slot and
+   wavenumber.  Blocks. */
+cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3, int32_t k_index, double tau);
 
-/* y = P x for the SAI of part (CM_OP_Z or CM_OP_X); vector conventions and
+/* y = P x for the SAI built with tau (1: of Z_near); vector conventions and
    k_index (per column, NULL = all at k[0]) as cm_apply.  CM_E_NOT_BUILT if
    that SAI was not built for a wavenumber a column uses.  Asynchronous. */
 cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols, const int32_t* k_index,
-                       cm_op part, cm_dtype dt, void* hip_stream);
+                       double tau, cm_dtype dt, void* hip_stream);
 
 /* out = sum_{i < N, c < ncols} conj(x[i*ld + c]) y[i*ld + c]: the complex
    inner product of two N x ncols blocks (CM_C64 or CM_C128, accumulated in
@@ -282,24 +300,32 @@ cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t restart, int32_
                    int32_t precond, cm_dtype far_dtype, int32_t* iters, double* relres, void* hip_stream);
 
 /* Characteristic modes by the implicitly restarted Arnoldi method on
-   OP = Z^-1 R (eq. (24)): the nev eigenvalues mu of largest magnitude, with
-   exact-shift restarts of an ncv-vector factorisation (nev < ncv <= N), each
-   OP product one R apply and one GMRES solve (gmres_restart, gmres_maxit,
-   gmres_tol, precond as in cm_gmres).  v0: device start vector (N complex128,
-   nonzero; the caller draws it).  Outputs (host): lambda[2*nev] interleaved
-   complex characteristic values lambda = i (1 - 1/mu), largest |mu| (smallest
-   |lambda|) first; ritz_resid[nev] (may be NULL) the relative Ritz residual
-   estimates; J (device, may be NULL) the N x nev Ritz vectors, column-major,
-   unit 2-norm; *nconv the number with residual <= tol; counters[6] (may be
-   NULL): OP products, GMRES iterations, operator applies, restarts, inner
-   solves redone without the preconditioner, inner solves that missed
-   gmres_tol.  A preconditioned inner solve that misses gmres_tol within
-   gmres_maxit is redone once without the SAI (which can be nearly singular).
-   Returns CM_E_NOT_CONVERGED if fewer than nev converged within maxrestart
+   OP = (tau R + i X)^-1 R: tau = 1 is OP = Z^-1 R of eq. (24), whose
+   eigenvalues mu = 1/(1 + i lambda) crowd at 1 when many modes have
+   |lambda| << 1 (large bodies); a smaller shift tau > 0 (an extension of
+   this library) maps them to mu = 1/(tau + i lambda), spread around a circle
+   of diameter 1/tau, so that the modes with |lambda| up to about tau are
+   well separated (each inner product then costs an R and an X apply).  The
+   nev eigenvalues mu of largest magnitude (smallest |tau + i lambda|) of an
+   ncv-vector factorisation with exact-shift restarts (nev < ncv <= N), each
+   OP product one R apply and one GMRES solve with tau R + i X
+   (gmres_restart, gmres_maxit, gmres_tol), right-preconditioned when
+   precond != 0 by the SAI built with the same tau (cm_sai_build).  v0:
+   device start vector (N complex128, nonzero; the caller draws it).
+   Outputs (host): lambda[2*nev] interleaved complex characteristic values
+   lambda = i (tau - 1/mu), smallest |tau + i lambda| first; ritz_resid[nev]
+   (may be NULL) the relative Ritz residual estimates; J (device, may be
+   NULL) the N x nev Ritz vectors, column-major, unit 2-norm; *nconv the
+   number with residual <= tol; counters[6] (may be NULL): OP products,
+   GMRES iterations, operator applies, restarts, inner solves redone without
+   the preconditioner, inner solves that missed gmres_tol.  A preconditioned
+   inner solve that misses gmres_tol within gmres_maxit is redone once
+   without the SAI (which can be nearly singular).  Returns
+   CM_E_NOT_CONVERGED if fewer than nev converged within maxrestart
    restarts, or if any inner solve missed gmres_tol (the Ritz values then
    belong to an inexact OP).  Synchronises. */
 cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
-                  int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond,
+                  int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond, double tau,
                   cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
                   int64_t* counters, void* hip_stream);
 
@@ -309,7 +335,7 @@ cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, do
    magnitude even where Z^-1 R (whose mu = 1/(1 + i lambda) crowd near 1)
    clusters them.  Arguments, outputs and counters[6] as cm_eigs, with inner
    GMRES solves with X, right-preconditioned when precond != 0 by the SAI of
-   X_near (cm_sai_build with part CM_OP_X; the paper notes that no efficient
+   X_near (cm_sai_build with tau = 0; the paper notes that no efficient
    preconditioner for X is documented: this one is the library's own).  The
    cos-kernel expansion of X degrades on boxes small against the wavelength,
    so this route suits trees whose leaves are not far below 0.25 wavelength.
@@ -323,32 +349,39 @@ cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestar
    (eq. (6)) with the R-orthonormal search space and the projected correction
    equation of eqs. (28)-(29): no inner solve with Z or X, each correction an
    approximate solution by inner_steps GMRES steps (one R and one X apply
-   each), unpreconditioned, or with precond != 0 right-preconditioned by
-   i P, P the SAI of Z (cm_sai_build first; X - theta R is close to
-   -i (Z - R) for targets near 0).  Finds the nev characteristic values closest to target
-   (0 for the significant modes); the search space holds at most mmax vectors
-   and restarts from the mmin Ritz vectors nearest the target.  A pair is
-   accepted when ||X u - theta R u|| <= tol max(1, |theta|) ||R u||, then
-   locked (deflated).  v0: device start vector (N complex128; the caller
-   draws it).  Outputs (host): lambda[nev] real characteristic values in the
-   order found; resid[nev] (may be NULL) their relative residuals; J (device,
-   may be NULL) the N x nev eigenvectors, column-major, R-normalised
-   (J^H R J = I); *nconv the number found; counters[4] (may be NULL): outer
-   iterations, inner GMRES steps, operator applies, 1 if the preconditioner
-   was dropped (no new converged pair within max(50, maxit / 8) outer
-   iterations: the SAI can be nearly singular).  Returns
-   CM_E_NOT_CONVERGED when fewer than nev were found within maxit outer
-   iterations (the first *nconv outputs are valid), CM_E_NUMERIC when an
-   expansion vector has no R-norm (R is singular on it), CM_E_NOT_BUILT for
-   precond without the SAI.  Synchronises. */
+   each), unpreconditioned (precond 0), right-preconditioned by i P with P the
+   SAI of Z_near (precond 1; X - theta R is close to -i (Z - R) for targets
+   near 0) or by P the SAI of X_near (precond 2, cm_sai_build with tau = 0;
+   X - theta R is close to X near theta = 0).  harmonic = 0 selects the Ritz
+   pairs of V^H X V nearest the target; harmonic != 0 the harmonic Ritz pairs
+   for the target (W^H (X - theta R) V s = 0 with W = (X - target R) V, the
+   smallest |theta - target| first, with the Rayleigh quotient as the value),
+   which converge where the target lies inside a dense part of the spectrum
+   (an extension of this library).  Finds the nev characteristic values
+   closest to target (0 for the significant modes); the search space holds
+   at most mmax vectors and restarts from the mmin (harmonic) Ritz vectors
+   nearest the target.  A pair is accepted when
+   ||X u - theta R u|| <= tol max(1, |theta|) ||R u||, then locked
+   (deflated).  v0: device start vector (N complex128; the caller draws it).
+   Outputs (host): lambda[nev] real characteristic values in the order found;
+   resid[nev] (may be NULL) their relative residuals; J (device, may be NULL)
+   the N x nev eigenvectors, column-major, R-normalised (J^H R J = I); *nconv
+   the number found; counters[4] (may be NULL): outer iterations, inner GMRES
+   steps, operator applies, 1 if the preconditioner was dropped (no new
+   converged pair within max(50, maxit / 8) outer iterations: the SAI can be
+   nearly singular).  Returns CM_E_NOT_CONVERGED when fewer than nev were
+   found within maxit outer iterations (the first *nconv outputs are valid),
+   CM_E_NUMERIC when an expansion vector has no R-norm (R is singular on it),
+   CM_E_NOT_BUILT for a preconditioner whose SAI was not built.  Synchronises. */
 cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t mmax, int32_t maxit, double tol,
-                int32_t inner_steps, int32_t precond, const void* v0, cm_dtype far_dtype, double* lambda,
-                double* resid, void* J, int32_t* nconv, int64_t* counters, void* hip_stream);
+                int32_t inner_steps, int32_t precond, int32_t harmonic, const void* v0, cm_dtype far_dtype,
+                double* lambda, double* resid, void* J, int32_t* nconv, int64_t* counters, void* hip_stream);
 
 /* Copy the near-field matrix to host (public unknown order, CSR by row):
    row_ptr (N+1, int64), col (nnz, int32), val (nnz complex128 interleaved).
    Pass NULLs to query *nnz only.  which = 0: Z_near, 1: dZ_near/dk,
-   2: the SAI matrix of Z_near, 3: the SAI matrix of X_near (at k[0]). */
+   2: the SAI matrix of Z_near, 3: the SAI matrix of the other tau (at
+   k[0]; tau = 0: of X_near). */
 cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_t* row_ptr,
                          int32_t* col, double* val);
 
@@ -356,6 +389,17 @@ cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_
    algorithmic bytes / flops per apply stage, NUL-terminated into buf.
    Returns CM_E_BADARG if buf_len is too small (needed size in *needed). */
 cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* needed);
+
+/* Pin the translation kernel of the FP32 batched applies on every level (of
+   every wavenumber of a sweep handle), overriding the default and the
+   autotuner's choice: 1 receiver tiles of 16 boxes, each block loading its
+   own sources (the default); 2 tiles of 64 boxes whose four waves share
+   their sources through LDS, two directions per thread, chunks of 8
+   sources; 3 the same with chunks of 4 at three waves per SIMD; 4 one
+   direction per thread.  All give the same bits; on the 122,880-unknown
+   sphere at 32 columns the 16-box tiles are the fastest.  CM_E_BADARG for
+   another value. */
+cm_status cm_set_translation_kernel(cm_handle* h, int32_t variant);
 
 /* Per-stage timing of applies: with enable != 0, every later cm_apply /
    cm_sai_apply on this handle brackets each kernel stage with HIP events

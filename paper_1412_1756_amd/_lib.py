@@ -11,12 +11,13 @@ CM_E_NOT_CONVERGED = -8
 OPS = {"Z": 0, "R": 1, "X": 2, "ZH": 3, "DZDK": 4}
 CM_C64, CM_C128 = 0, 1
 CM_FLAG_HOST_ONLY, CM_FLAG_DERIV, CM_FLAG_CHECK, CM_FLAG_NO_MATRIX_CORES, CM_FLAG_NEAR_FP32 = 1, 2, 4, 8, 16
-CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD = 32, 64, 128
+CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD, CM_FLAG_VERBOSE, CM_FLAG_M2L_TILE16 = 32, 64, 128, 256, 512
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
            "cm_apply_noalloc",
            "cm_sai_build", "cm_sai_apply", "cm_vdot", "cm_real_currents", "cm_modal_correlation", "cm_dlambda_dk",
-           "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_jd", "cm_export_near", "cm_stats", "cm_stage_timing",
+           "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_jd", "cm_export_near", "cm_stats", "cm_set_translation_kernel",
+           "cm_stage_timing",
            "cm_stage_times", "cm_last_error"]
 
 
@@ -58,9 +59,9 @@ def lib():
     L.cm_apply.restype = C.c_int
     L.cm_apply_noalloc.argtypes = [vp, C.c_int, vp, vp, i64, i32, C.c_int, vp]
     L.cm_apply_noalloc.restype = C.c_int
-    L.cm_sai_build.argtypes = [vp, dbl, dbl, dbl, i32, C.c_int]
+    L.cm_sai_build.argtypes = [vp, dbl, dbl, dbl, i32, dbl]
     L.cm_sai_build.restype = C.c_int
-    L.cm_sai_apply.argtypes = [vp, vp, vp, i64, i32, vp, C.c_int, C.c_int, vp]
+    L.cm_sai_apply.argtypes = [vp, vp, vp, i64, i32, vp, dbl, C.c_int, vp]
     L.cm_sai_apply.restype = C.c_int
     L.cm_vdot.argtypes = [vp, vp, vp, i64, i32, C.c_int, vp, vp]
     L.cm_vdot.restype = C.c_int
@@ -76,13 +77,17 @@ def lib():
     L.cm_stats.restype = C.c_int
     L.cm_gmres.argtypes = [vp, vp, vp, i32, i32, dbl, i32, C.c_int, C.POINTER(i32), C.POINTER(dbl), vp]
     L.cm_gmres.restype = C.c_int
-    L.cm_eigs.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, i32, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
+    L.cm_eigs.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, i32, dbl, C.c_int, vp, vp, vp, C.POINTER(i32), vp,
+                          vp]
     L.cm_eigs.restype = C.c_int
     L.cm_eigs_xinv.argtypes = [vp, i32, i32, i32, dbl, vp, i32, i32, dbl, i32, C.c_int, vp, vp, vp, C.POINTER(i32), vp,
                                vp]
     L.cm_eigs_xinv.restype = C.c_int
-    L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp, vp]
+    L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, i32, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp,
+                        vp]
     L.cm_jd.restype = C.c_int
+    L.cm_set_translation_kernel.argtypes = [vp, i32]
+    L.cm_set_translation_kernel.restype = C.c_int
     L.cm_stage_timing.argtypes = [vp, i32]
     L.cm_stage_timing.restype = C.c_int
     L.cm_stage_times.argtypes = [vp, C.c_char_p, i64, C.POINTER(i64)]

@@ -10,6 +10,10 @@
 // sides shares every translator, interpolation weight and leaf pattern load.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <string>
+#include <vector>
+
 #include "cm_device.h"
 
 namespace cm {
@@ -447,6 +451,146 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
             g0 = a0[u][r];
             g1 = a1[u][r];
           }
+        }
+      }
+    }
+  }
+}
+
+// Translation for FP32 batches with receiver tiles of kTile64 boxes: the
+// four waves of a block own 16 receivers each and share the tile's sources,
+// which the block stages through LDS in chunks of kCH64 sources (one global
+// load per element per block, double-buffered: the next chunk's loads are in
+// flight while the current chunk is applied).  Each wave walks the staged
+// sources in order and applies each to those of its receivers that list it
+// (register accumulators), so every receiver sums its sources in increasing
+// source order, as the 16-box tiles of k_m2l do: the two kernels give the
+// same bits.  Thread = (direction row, column) of the block's slab of
+// qspan = QPT * 64 / cw directions and cw columns.  kCH64 sources per
+// staged chunk; MINW: the waves per SIMD the register allocation aims at
+// (3 spills a few registers, 2 does not: the autotuner picks per level).
+template <int QPT, int kCH64, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_m2l64(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tsrc,
+                                               const int32_t* __restrict__ toff, const C2<float>* __restrict__ T,
+                                               int n_off, const C2<float>* __restrict__ S, C2<float>* __restrict__ G,
+                                               int nbox, int ntile, int K, int nc, int cw, int ldp, int accum) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int SLAB = 2 * QPT * 64;                 // complex values of one staged source
+  constexpr int PER = kCH64 * SLAB / 256;            // staged values per thread and chunk
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int qw = 64 / cw, qspan = qw * QPT;
+  C2<float>* Ts = reinterpret_cast<C2<float>*>(smem_raw);   // [n_off][qspan]
+  C2<float>* Sb = Ts + n_off * qspan;                    // [2][kCH64][2 comps][qspan][cw]
+  const int per_xcd = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (tile >= ntile) return;
+  const int q0 = blockIdx.y * qspan, c0 = blockIdx.z * cw;
+  for (int e = threadIdx.x; e < n_off * qspan; e += blockDim.x) {
+    const int f = e / qspan, qq = q0 + e % qspan;
+    Ts[e] = (qq < K) ? T[(int64_t)f * K + qq] : mk<float>(0.f, 0.f);
+  }
+  const int cl = lane % cw, ql = lane / cw;
+  const int c = c0 + cl;
+  const int64_t bstride = (int64_t)2 * K * ldp, cstride = (int64_t)K * ldp;
+  const int e0 = tptr[tile], e1 = tptr[tile + 1];
+  // staging: thread t stages value t % SLAB of sources t / SLAB, t / SLAB +
+  // 256 / SLAB, ... of a chunk (pre[i]); its (component, direction, column)
+  // is fixed for the whole block
+  static_assert(256 % SLAB == 0 && (kCH64 * SLAB) % 256 == 0, "whole sources per pass of the block");
+  constexpr int SPP = 256 / SLAB;                    // sources per pass of the block
+  const int sub = threadIdx.x / SLAB;
+  int64_t my_off;
+  bool my_ok;
+  {
+    const int v = threadIdx.x % SLAB;
+    const int comp = v / (QPT * 64), r2 = v % (QPT * 64);
+    const int qq = q0 + r2 / cw, cc = c0 + r2 % cw;
+    my_ok = qq < K && cc < nc;
+    my_off = comp * cstride + (int64_t)qq * ldp + cc;
+  }
+  C2<float> pre[PER];
+  auto fetch = [&](int cs) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int src = cs + SPP * i + sub;
+      pre[i] = (src < e1 && my_ok) ? S[tsrc[src] * bstride + my_off] : mk<float>(0.f, 0.f);
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) Sb[buf * kCH64 * SLAB + threadIdx.x + 256 * i] = pre[i];
+  };
+  C2<float> a0[QPT][16], a1[QPT][16];
+#pragma unroll
+  for (int u = 0; u < QPT; ++u)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a0[u][r] = a1[u][r] = mk<float>(0.f, 0.f);
+  if (e0 < e1) {
+    fetch(e0);
+    commit(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int cs = e0; cs < e1; cs += kCH64) {
+    const bool more = cs + kCH64 < e1;
+    if (more) fetch(cs + kCH64);
+    const int n = min(kCH64, e1 - cs);
+    const C2<float>* sb = Sb + buf * kCH64 * SLAB;
+    for (int s = 0; s < n; ++s) {
+      // this wave's 16 translator ids for the source (uniform scalar loads)
+      const int4* of4 = reinterpret_cast<const int4*>(toff + (int64_t)(cs + s) * kTile64 + 16 * w);
+      int f[16];
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int4 v = of4[r4];
+        f[4 * r4 + 0] = v.x;
+        f[4 * r4 + 1] = v.y;
+        f[4 * r4 + 2] = v.z;
+        f[4 * r4 + 3] = v.w;
+      }
+      int all = f[0];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) all &= f[r];
+      if (all < 0) continue;   // none of this wave's receivers lists the source
+      C2<float> s0[QPT], s1[QPT];
+#pragma unroll
+      for (int u = 0; u < QPT; ++u) {   // (u qw + ql) cw + cl = 64 u + lane
+        s0[u] = sb[s * SLAB + 64 * u + lane];
+        s1[u] = sb[s * SLAB + QPT * 64 + 64 * u + lane];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (f[r] >= 0) {
+#pragma unroll
+          for (int u = 0; u < QPT; ++u) {
+            const C2<float> t = Ts[f[r] * qspan + u * qw + ql];
+            a0[u][r] = cfma(a0[u][r], t, s0[u]);
+            a1[u][r] = cfma(a1[u][r], t, s1[u]);
+          }
+        }
+      }
+    }
+    if (more) commit(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int u = 0; u < QPT; ++u) {
+    const int q = q0 + u * qw + ql;
+    if (q >= K || c >= nc) continue;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = tile * kTile64 + 16 * w + r;
+      if (m < nbox) {
+        C2<float>* gp = G + m * bstride + (int64_t)q * ldp + c;
+        if (accum) {
+          gp[0].x += a0[u][r].x;
+          gp[0].y += a0[u][r].y;
+          gp[cstride].x += a1[u][r].x;
+          gp[cstride].y += a1[u][r].y;
+        } else {
+          gp[0] = a0[u][r];
+          gp[cstride] = a1[u][r];
         }
       }
     }
@@ -1088,6 +1232,35 @@ struct Stages {
     const int gx = (Lv.ntile + 7) / 8 * 8;              // multiple of 8 for the XCD-aware tile order
     const size_t sh2 = (size_t)Lv.n_off * qb * 2 * sizeof(CR);
     if constexpr (sizeof(R) == 4)
+      if (cw >= 8 && (cw & (cw - 1)) == 0 && !(P.opt.flags & CM_FLAG_M2L_TILE16) && Lv.tile64_ptr &&
+          Lv.m2l_variant >= 2) {
+        // FP32 batched: 64-box tiles sharing their sources through LDS
+        // (variant 2: two directions per thread, chunks of 8 sources; 3: the
+        // same with chunks of 4 at three waves per SIMD; 4: one direction
+        // per thread, chunks of 8, four waves per SIMD)
+        const int v = Lv.m2l_variant;
+        const int qpt = v == 4 ? 1 : 2, ch = v == 3 ? 4 : 8;
+        const int qspan = qpt * 64 / cw;
+        const size_t sh = (size_t)Lv.n_off * qspan * sizeof(CR) + (size_t)2 * ch * 2 * qpt * 64 * sizeof(CR);
+        if (sh <= 64 * 1024) {
+          const int32_t* p64 = (kind == 1) ? Lv.tileR64_ptr : Lv.tile64_ptr;
+          const int32_t* s64 = (kind == 1) ? Lv.tileR64_src : Lv.tile64_src;
+          const int32_t* o64 = (kind == 1) ? Lv.tileR64_off : Lv.tile64_off;
+          dim3 grid((Lv.ntile64 + 7) / 8 * 8, (Lv.K + qspan - 1) / qspan, (nc + cw - 1) / cw);
+#define CM_M2L64(Q, CH, W)                                                                                     \
+  hipLaunchKernelGGL((k_m2l64<Q, CH, W>), grid, dim3(256), sh, s, p64, s64, o64, (const C2<float>*)T, Lv.n_off, \
+                     (const C2<float>*)S, (C2<float>*)G, Lv.nbox, Lv.ntile64, Lv.K, nc, cw, ldp, accum)
+          if (v == 3)
+            CM_M2L64(2, 4, 3);
+          else if (v == 4)
+            CM_M2L64(1, 8, 4);
+          else
+            CM_M2L64(2, 8, 2);
+#undef CM_M2L64
+          return;
+        }
+      }
+    if constexpr (sizeof(R) == 4)
       if (cw >= 8 && sh2 <= 64 * 1024) {
         // FP32 batched: two directions per thread share the translator ids
         dim3 grid(gx, (Lv.K + 2 * qb - 1) / (2 * qb), (nc + cw - 1) / cw);
@@ -1321,6 +1494,60 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   }
   stage_end(d, s);
   chk(hipGetLastError(), "apply launch");
+}
+
+// Autotuning of the FP32 batched translation at nc columns: for every level
+// the 16-box-tile kernel and the two 64-box shared-source variants are timed
+// on the workspace (one untimed and three timed launches, HIP events on the
+// stream) and the fastest is kept.  All variants sum every receiver's
+// sources in the same order, so the choice does not change the result.
+// Returns the choices as JSON array entries (without brackets).
+std::string m2l_autotune(Dev& d, const Plan& P, const std::vector<void*>& S, const std::vector<void*>& G, int nc,
+                         hipStream_t s) {
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  chk(hipEventCreate(&ev.a), "hipEventCreate (autotune)");
+  chk(hipEventCreate(&ev.b), "hipEventCreate (autotune)");
+  Stages<float> st{d, P, d.f32, s};
+  std::string js;
+  for (int l = 2; l <= d.lf; ++l) {
+    LevelD<float>& Lv = d.f32.lev[l];
+    float best = 1e30f, base = -1.f, vms[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    int best_v = 0;
+    for (int v : {1, 2, 3, 4}) {
+      Lv.m2l_variant = v;
+      auto launch = [&] { st.m2l(l, 0, Lv.TZ, (const C2<float>*)S[l], (C2<float>*)G[l], nc, nc, 0); };
+      launch();
+      chk(hipEventRecord(ev.a, s), "hipEventRecord (autotune)");
+      for (int i = 0; i < 3; ++i) launch();
+      chk(hipEventRecord(ev.b, s), "hipEventRecord (autotune)");
+      chk(hipEventSynchronize(ev.b), "autotune timing");
+      float ms = 0.f;
+      chk(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime (autotune)");
+      ms /= 3.f;
+      vms[v] = ms;
+      if (v == 1) base = ms;
+      if (ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    Lv.m2l_variant = best_v;
+    char item[256];
+    std::snprintf(item, sizeof item,
+                  "%s{\"stage\": \"m2l_l%d\", \"tile\": %d, \"chunk\": %d, \"ms\": %.6g, \"tile16_ms\": %.6g, "
+                  "\"tile64_chunk8_ms\": %.6g, \"tile64_chunk4_ms\": %.6g, \"tile64_one_direction_ms\": %.6g}",
+                  js.empty() ? "" : ", ", l, best_v == 1 ? 16 : 64, best_v == 3 ? 4 : (best_v == 1 ? 0 : 8), best,
+                  base, vms[2], vms[3], vms[4]);
+    js += item;
+  }
+  chk(hipGetLastError(), "autotune launches");
+  return js;
 }
 
 void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,

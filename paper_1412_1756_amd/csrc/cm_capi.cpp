@@ -130,6 +130,15 @@ static void build_prec(Dev& d, const Plan& P, PrecD<R>& pd, const std::vector<in
     D.tileR_ptr = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 3];
     D.tileR_src = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 4];
     D.tileR_off = lists[8 * (lf + 1) + (lf + 1) + 6 * l + 5];
+    if constexpr (sizeof(R) == 4) {
+      D.ntile64 = (Lv.nbox + kTile64 - 1) / kTile64;
+      D.tile64_ptr = upload(d, Lv.tile64_ptr, s);
+      D.tile64_src = upload(d, Lv.tile64_src, s);
+      D.tile64_off = upload(d, Lv.tile64_off, s);
+      D.tileR64_ptr = upload(d, Lv.tileR64_ptr, s);
+      D.tileR64_src = upload(d, Lv.tileR64_src, s);
+      D.tileR64_off = upload(d, Lv.tileR64_off, s);
+    }
     D.TZ = upload_complex<R>(d, P.TZ[l], s);
     D.TR = upload_complex<R>(d, P.TR[l], s);
     D.TX = upload_complex<R>(d, P.TX[l], s);
@@ -306,8 +315,14 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
       chk(hipMemsetAsync(d.S[l], 0, b, s), "hipMemsetAsync");
       chk(hipMemsetAsync(d.G[l], 0, b, s), "hipMemsetAsync");
     }
-    d.tune_json = mf_autotune(d.f32, lf, d.S, d.G, std::min(64, d.max_cols / 8 * 8), s);
+    const int tnc = std::min(64, d.max_cols / 8 * 8);
+    d.tune_json = mf_autotune(d.f32, lf, d.S, d.G, tnc, s);
     chk(hipGetLastError(), "autotune launches");
+    if (!(P.opt.flags & CM_FLAG_M2L_TILE16)) {
+      const std::string m = m2l_autotune(d, P, d.S, d.G, tnc, s);
+      if (!m.empty()) d.tune_json = d.tune_json.substr(0, d.tune_json.size() - 1) +
+                                    (d.tune_json.size() > 2 ? ", " : "") + m + "]";
+    }
   }
   chk(hipStreamSynchronize(s), "device set-up");
 }
@@ -545,40 +560,45 @@ cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, i
   })
 }
 
-static int sai_part(cm_op part) { return part == CM_OP_X ? 1 : part == CM_OP_Z ? 0 : -1; }
+static cm_status check_tau(double tau) {
+  if (!(tau >= 0) || !(tau <= 1e6)) return fail(CM_E_BADARG, "tau must be in [0, 1e6]");
+  return CM_OK;
+}
 
-cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3, int32_t k_index, cm_op part) {
+cm_status cm_sai_build(cm_handle* h, double eps1, double eps2, double eps3, int32_t k_index, double tau) {
   g_err.clear();
   if (!h) return fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (!(eps1 >= 0) || !(eps2 >= 0) || !(eps3 >= 0) || eps1 > 1 || eps2 > 1 || eps3 > 1)
     return fail(CM_E_BADARG, "thresholds must be in [0, 1]");
   if (k_index < 0 || k_index > (int)h->sub.size()) return fail(CM_E_BADARG, "k_index out of range [0, n_k)");
-  if (sai_part(part) < 0) return fail(CM_E_BADARG, "part must be CM_OP_Z or CM_OP_X");
+  cm_status st = check_tau(tau);
+  if (st != CM_OK) return st;
   cm_handle* t = k_index == 0 ? h : h->sub[k_index - 1];
   CM_TRY({
-    cm::dev_sai_build(t->dev, t->plan, eps1, eps2, eps3, sai_part(part), nullptr);
+    cm::dev_sai_build(t->dev, t->plan, eps1, eps2, eps3, tau, nullptr);
     return CM_OK;
   })
 }
 
 cm_status cm_sai_apply(cm_handle* h, const void* x, void* y, int64_t ld, int32_t ncols, const int32_t* k_index,
-                       cm_op part, cm_dtype dt, void* hip_stream) {
+                       double tau, cm_dtype dt, void* hip_stream) {
   g_err.clear();
   cm_status st = check_vec_args(h, x, y, ld, ncols, dt);
   if (st != CM_OK) return st;
   if ((st = check_k_index(h, k_index, ncols)) != CM_OK) return st;
-  const int pt = sai_part(part);
-  if (pt < 0) return fail(CM_E_BADARG, "part must be CM_OP_Z or CM_OP_X");
+  if ((st = check_tau(tau)) != CM_OK) return st;
+  const int slot = cm::sai_slot(tau);
   for (int j = 0; j < (k_index ? ncols : 1); ++j) {
     const cm_handle* t = (!k_index || k_index[j] == 0) ? h : h->sub[k_index[j] - 1];
-    if (!t->dev.sai[pt].val) return fail(CM_E_NOT_BUILT, "SAI not built for this wavenumber and part");
+    if (!t->dev.sai[slot].val || (slot == 1 && t->dev.sai_tau1 != tau))
+      return fail(CM_E_NOT_BUILT, "SAI not built for this wavenumber and tau");
   }
   const bool fp64 = dt == CM_C128;
   CM_TRY({
     by_wavenumber(h, x, y, ld, ncols, k_index, fp64, (hipStream_t)hip_stream,
                   [&](cm_handle* t, const void* xx, void* yy, int64_t l, int n, hipStream_t ss) {
-                    cm::dev_sai_apply(t->dev, t->plan, xx, yy, l, n, fp64, pt, ss);
+                    cm::dev_sai_apply(t->dev, t->plan, xx, yy, l, n, fp64, slot, ss);
                   });
     return CM_OK;
   })
@@ -676,6 +696,19 @@ cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* need
   if (needed) *needed = (int64_t)s.size() + 1;
   if (!buf || buf_len < (int64_t)s.size() + 1) return fail(CM_E_BADARG, "buffer too small");
   std::memcpy(buf, s.c_str(), s.size() + 1);
+  return CM_OK;
+}
+
+cm_status cm_set_translation_kernel(cm_handle* h, int32_t variant) {
+  g_err.clear();
+  if (!h) return fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (variant < 1 || variant > 4) return fail(CM_E_BADARG, "variant must be in 1..4");
+  auto pin = [&](cm_handle* t) {
+    for (auto& L : t->dev.f32.lev) L.m2l_variant = variant;
+  };
+  pin(h);
+  for (cm_handle* u : h->sub) pin(u);
   return CM_OK;
 }
 

@@ -45,6 +45,11 @@ struct LevelD {
   int ntile = 0;
   int32_t *tile_ptr = nullptr, *tile_src = nullptr, *tileR_ptr = nullptr, *tileR_src = nullptr;
   int32_t *tile_off = nullptr, *tileR_off = nullptr;
+  int ntile64 = 0;                          // tiles of kTile64 receivers (FP32 shared-source translation)
+  int m2l_variant = 0;                      // FP32 batched translation kernel (0, 1: 16-box tiles, 2-4:
+                                            // 64-box shared-source tiles, only where the autotuner picks them)
+  int32_t *tile64_ptr = nullptr, *tile64_src = nullptr, *tile64_off = nullptr;
+  int32_t *tileR64_ptr = nullptr, *tileR64_src = nullptr, *tileR64_off = nullptr;
   // interpolation from level l+1 into this level (l = 2..lf-1)
   int p = 0, ntc = 0, npc = 0;
   int32_t *th_idx = nullptr, *th_ref = nullptr, *ph_idx = nullptr;
@@ -102,8 +107,10 @@ struct Dev {
   // workspace (sized for max_cols, complex double; reused as complex float)
   std::vector<void*> S, G, dS, dG;          // per level
   void *xi = nullptr, *yi = nullptr, *dxi = nullptr;
-  // SAI preconditioners: sai[0] of Z_near, sai[1] of X_near = Im Z_near
+  // SAI preconditioners: sai[0] of Z_near; sai[1] of the near field of the
+  // shifted operator tau R + i X for sai_tau1 (tau 0: the real X_near)
   SaiD sai[2];
+  double sai_tau1 = -1;
   double2* red = nullptr;                   // partial sums of cm_vdot (blas_vdot_blocks() entries)
   std::vector<void*> allocs;
   // optional per-stage timing (HIP events on the apply stream)
@@ -159,6 +166,10 @@ bool mf_near32(const int64_t* row_ptr, const int32_t* box_start, const int32_t* 
 // the workspace at nc columns and keep the fastest; returns the choices (JSON).
 std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, const std::vector<void*>& G, int nc,
                         hipStream_t s);
+// Time the FP32 batched translation kernels of every level at nc columns on
+// the workspace and keep the fastest; returns JSON array entries.
+std::string m2l_autotune(Dev& d, const Plan& P, const std::vector<void*>& S, const std::vector<void*>& G, int nc,
+                         hipStream_t s);
 // whether mf_anterp takes the anterpolation from level Lp for nc columns
 bool mf_covers(const LevelD<float>& Lp, int nc);
 
@@ -188,9 +199,11 @@ void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld
 // the same on a caller-provided workspace (no allocation, no stage timing)
 void dev_apply_ws(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
                   const Work& w, hipStream_t s);
-// SAI of Z_near (part 0) or X_near (part 1)
-void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, int part, hipStream_t s);
-void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64, int part,
+// SAI of the near field of tau R + i X: tau = 1 is Z_near (slot 0); any
+// other tau goes to slot 1, tau = 0 meaning the real matrix X_near
+void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, double tau, hipStream_t s);
+inline int sai_slot(double tau) { return tau == 1.0 ? 0 : 1; }
+void dev_sai_apply(Dev& d, const Plan& P, const void* x, void* y, int64_t ld, int nc, bool fp64, int slot,
                    hipStream_t s);
 
 }  // namespace cm

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <numeric>
 #include <vector>
 
@@ -41,7 +42,11 @@ static void chk_d(hipError_t e, const char* what) {
 
 struct DevBuf {
   void* p = nullptr;
-  explicit DevBuf(size_t bytes) { chk_d(hipMalloc(&p, std::max<size_t>(bytes, 16)), "driver workspace"); }
+  // bytes == 0: empty until alloc()
+  explicit DevBuf(size_t bytes) {
+    if (bytes) alloc(bytes);
+  }
+  void alloc(size_t bytes) { chk_d(hipMalloc(&p, std::max<size_t>(bytes, 16)), "driver workspace"); }
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
@@ -54,9 +59,10 @@ struct DevBuf {
 // orthogonalisation of w against V[0..j).
 class KrylovCtx {
  public:
-  // sai_part: the SAI that precond() applies (0: of Z_near, 1: of X_near)
-  KrylovCtx(Dev& d, const Plan& P, bool far64, hipStream_t s, int sai_part = 0)
-      : d_(d), P_(P), far64_(far64), s_(s), N_(d.N), sai_part_(sai_part), t32a_(d.N * sizeof(float2)),
+  // sai_part: the SAI slot that precond() applies (0: of Z_near, 1: of the
+  // shifted operator's near field); tau: the shift of op 5, y = tau R x + i X x
+  KrylovCtx(Dev& d, const Plan& P, bool far64, hipStream_t s, int sai_part = 0, double tau = 1.0)
+      : d_(d), P_(P), far64_(far64), s_(s), N_(d.N), sai_part_(sai_part), tau_(tau), t32a_(d.N * sizeof(float2)),
         t32b_(d.N * sizeof(float2)), hdev_(1025 * sizeof(double2)),
         part_((size_t)1025 * blas_multidot_blocks(d.N) * sizeof(double2)) {
     chk_d(hipHostMalloc((void**)&pin_, kRing * sizeof(double), hipHostMallocDefault), "pinned residuals");
@@ -85,9 +91,19 @@ class KrylovCtx {
 
   int64_t N() const { return N_; }
   hipStream_t stream() const { return s_; }
+  bool verbose() const { return (P_.opt.flags & CM_FLAG_VERBOSE) != 0; }
 
-  // y = op(x), op 0 = Z, 1 = R; far field in FP64 or FP32
+  // y = op(x), op 0 = Z, 1 = R, 2 = X, 5 = tau R + i X (an R and an X
+  // apply); far field in FP64 or FP32
   void apply(int op, const double2* x, double2* y) {
+    if (op == 5) {
+      if (!tsh_.p) tsh_.alloc((size_t)N_ * sizeof(double2));
+      apply(1, x, tsh_.d());
+      apply(2, x, y);
+      blas_scale(y, make_double2(0.0, 1.0), N_, s_);
+      blas_axpby(tsh_.d(), make_double2(tau_, 0.0), y, N_, 1, s_);
+      return;
+    }
     ++n_apply;
     if (far64_) {
       dev_apply(d_, P_, op, x, y, 1, 1, true, s_);
@@ -182,7 +198,8 @@ class KrylovCtx {
   hipStream_t s_;
   int64_t N_;
   int sai_part_;
-  DevBuf t32a_, t32b_, hdev_, part_;
+  double tau_;
+  DevBuf t32a_, t32b_, hdev_, part_, tsh_{0};
   static constexpr int kRing = 8;
   double* pin_ = nullptr;
   hipEvent_t ev_[kRing] = {};
@@ -205,8 +222,8 @@ struct GmresResult {
 };
 
 // Solve A x = b, right-preconditioned by the SAI P (x = P u) when precond;
-// A = Z (aop 0) or X (aop 2, the route of eq. (14)), P the SAI that the
-// context's precond() applies (of Z_near or of X_near).
+// A = Z (aop 0), X (aop 2, the route of eq. (14)) or tau R + i X (aop 5), P
+// the SAI that the context's precond() applies (of the matching near field).
 //
 // Each iteration is enqueued without a host round trip: the Gram-Schmidt
 // coefficients come from an all-CU multidot, the Hessenberg column, its
@@ -434,6 +451,90 @@ static void schur_vectors(const Mat& T, const Mat& Z, int n, Mat& Y) {
   }
 }
 
+// Reduction of a general n x n complex matrix to upper Hessenberg form by
+// Householder reflections: A <- Qh^H A Qh (A becomes Hessenberg), Qh unitary.
+static void hess_reduce(Mat& A, int n, Mat& Qh) {
+  Qh.assign((size_t)n * n, cplx(0));
+  for (int i = 0; i < n; ++i) at(Qh, n, i, i) = 1;
+  std::vector<cplx> v(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    double nx = 0;
+    for (int i = k + 1; i < n; ++i) nx += std::norm(at(A, n, i, k));
+    nx = std::sqrt(nx);
+    if (nx == 0) continue;
+    const cplx x0 = at(A, n, k + 1, k);
+    const cplx ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cplx(1);
+    std::fill(v.begin(), v.end(), cplx(0));
+    for (int i = k + 1; i < n; ++i) v[i] = at(A, n, i, k);
+    v[k + 1] += ph * nx;
+    double nv = 0;
+    for (int i = k + 1; i < n; ++i) nv += std::norm(v[i]);
+    nv = std::sqrt(nv);
+    if (nv == 0) continue;
+    for (int i = k + 1; i < n; ++i) v[i] /= nv;
+    // A <- (I - 2 v v^H) A (I - 2 v v^H), Qh <- Qh (I - 2 v v^H)
+    for (int c = 0; c < n; ++c) {
+      cplx sacc = 0;
+      for (int i = k + 1; i < n; ++i) sacc += std::conj(v[i]) * at(A, n, i, c);
+      for (int i = k + 1; i < n; ++i) at(A, n, i, c) -= 2.0 * v[i] * sacc;
+    }
+    for (int r = 0; r < n; ++r) {
+      cplx sacc = 0, sq = 0;
+      for (int i = k + 1; i < n; ++i) {
+        sacc += at(A, n, r, i) * v[i];
+        sq += at(Qh, n, r, i) * v[i];
+      }
+      for (int i = k + 1; i < n; ++i) {
+        at(A, n, r, i) -= 2.0 * sacc * std::conj(v[i]);
+        at(Qh, n, r, i) -= 2.0 * sq * std::conj(v[i]);
+      }
+    }
+    for (int i = k + 2; i < n; ++i) at(A, n, i, k) = 0;
+  }
+}
+
+// Eigenvalues ev and unit eigenvectors (columns of Y) of a general complex
+// n x n matrix: Hessenberg reduction, complex Schur form, back substitution.
+static bool gen_eig(Mat A, int n, std::vector<cplx>& ev, Mat& Y) {
+  Mat Qh, Z;
+  hess_reduce(A, n, Qh);
+  if (!schur(A, n, Z)) return false;
+  Mat QZ((size_t)n * n, cplx(0));
+  for (int c = 0; c < n; ++c)
+    for (int r = 0; r < n; ++r) {
+      cplx sacc = 0;
+      for (int k = 0; k < n; ++k) sacc += at(Qh, n, r, k) * at(Z, n, k, c);
+      at(QZ, n, r, c) = sacc;
+    }
+  schur_vectors(A, QZ, n, Y);
+  ev.resize(n);
+  for (int i = 0; i < n; ++i) ev[i] = at(A, n, i, i);
+  return true;
+}
+
+// Orthonormal columns (standard inner product, two modified Gram-Schmidt
+// passes) spanning the first nc columns of S (m rows); columns that vanish
+// are dropped.  Returns the number kept.
+static int orthonormal_columns(const Mat& S, int m, int nc, Mat& Qo) {
+  Qo.assign((size_t)m * nc, cplx(0));
+  int kept = 0;
+  for (int c = 0; c < nc; ++c) {
+    std::vector<cplx> v(S.begin() + (size_t)c * m, S.begin() + (size_t)(c + 1) * m);
+    const double n0 = std::sqrt(std::accumulate(v.begin(), v.end(), 0.0, [](double a, cplx z) { return a + std::norm(z); }));
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q < kept; ++q) {
+        cplx d = 0;
+        for (int r = 0; r < m; ++r) d += std::conj(Qo[(size_t)q * m + r]) * v[r];
+        for (int r = 0; r < m; ++r) v[r] -= d * Qo[(size_t)q * m + r];
+      }
+    const double nv = std::sqrt(std::accumulate(v.begin(), v.end(), 0.0, [](double a, cplx z) { return a + std::norm(z); }));
+    if (!(nv > 1e-10 * n0) || nv == 0) continue;
+    for (int r = 0; r < m; ++r) Qo[(size_t)kept * m + r] = v[r] / nv;
+    ++kept;
+  }
+  return kept;
+}
+
 // ---------------------------------------------------------------- implicitly restarted Arnoldi
 struct EigsResult {
   int nconv = 0, restarts = 0;
@@ -444,8 +545,10 @@ struct EigsResult {
   std::vector<double> resid;  // Ritz residual estimates |beta e_m^T y| / |mu|
 };
 
-// aop: the matrix inverted by the inner solves, Z (0: OP = Z^-1 R, eq. (24))
-// or X (2: OP = X^-1 R, eq. (14), unpreconditioned)
+// aop: the matrix inverted by the inner solves, Z (0: OP = Z^-1 R, eq. (24)),
+// X (2: OP = X^-1 R, eq. (14)) or tau R + i X (5: OP = (tau R + i X)^-1 R,
+// whose eigenvalues mu = 1/(tau + i lambda) spread the modes with |lambda|
+// near or below tau around a circle of diameter 1/tau)
 static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double tol, const double2* v0, int gm_m,
                        int gm_maxit, double gm_tol, bool precond, double2* Xout, int aop = 0) {
   const int64_t N = K.N();
@@ -481,6 +584,11 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
       // an inexact OP product makes the Ritz residual estimates meaningless
       if (!g.converged) ++out.inner_failures;
       ++out.n_op;
+      if (K.verbose()) {
+        std::fprintf(stderr, "cm_eigs: OP product %lld: %d GMRES iterations (%lld in all)%s\n", (long long)out.n_op,
+                     g.iters, (long long)out.gmres_iters, g.converged ? "" : ", missed the tolerance");
+        std::fflush(stderr);
+      }
       double hn = K.orth(V, j + 1, f.d(), h);
       for (int k = 0; k <= j; ++k) at(H, ncv, k, j) = h[k];
       if (j + 1 < ncv) {
@@ -512,6 +620,11 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
     }
     out.nconv = nconv;
     out.restarts = rs;
+    if (K.verbose()) {
+      std::fprintf(stderr, "cm_eigs: restart %d: %d of %d converged, %lld OP products, %lld GMRES iterations\n", rs,
+                   nconv, nev, (long long)out.n_op, (long long)out.gmres_iters);
+      std::fflush(stderr);
+    }
     if (nconv >= nev || rs >= maxrestart) break;
     // implicit restart: the ncv - kkeep unwanted Ritz values are the shifts
     Mat Q((size_t)ncv * ncv, cplx(0));
@@ -628,8 +741,11 @@ struct JdResult {
   int64_t inner_steps = 0, n_apply = 0;
 };
 
+// precond: 0 none, 1 i P with P the SAI of Z_near, 2 P the SAI of X_near
+// (the context's SAI slot).  harmonic: select harmonic Ritz pairs for the
+// target instead of Ritz pairs (interior eigenvalues, see below).
 static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int maxit, double tol, int inner,
-                   const double2* v0, double2* Jout, bool precond) {
+                   const double2* v0, double2* Jout, int precond, bool harmonic) {
   const int64_t N = K.N();
   hipStream_t s = K.stream();
   DevBuf Vb((size_t)mmax * N * sizeof(double2)), XVb((size_t)mmax * N * sizeof(double2)),
@@ -662,6 +778,121 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
       for (int r2 = 0; r2 < m; ++r2) Sc[(size_t)c * m + r2] = S[(size_t)(c0 + c) * m + r2];
     K.combine(M, m, Sc, m, nc, Tmp.d());
     copy(Tmp.d(), M, (size_t)nc * N);
+  };
+  // basis change V <- V Qm (nc orthonormal columns of m rows: the new basis
+  // stays R-orthonormal), with X V, R V and H = V^H X V following
+  auto change_basis = [&](const Mat& Qm, int nc, Mat& Hm, int m) {
+    recombine(V, m, Qm, 0, nc);
+    recombine(XV, m, Qm, 0, nc);
+    recombine(RV, m, Qm, 0, nc);
+    Mat HQ((size_t)m * nc, cplx(0)), Hn((size_t)nc * nc, cplx(0));
+    for (int c = 0; c < nc; ++c)
+      for (int r2 = 0; r2 < m; ++r2) {
+        cplx acc = 0;
+        for (int q = 0; q < m; ++q) acc += at(Hm, m, r2, q) * Qm[(size_t)c * m + q];
+        HQ[(size_t)c * m + r2] = acc;
+      }
+    for (int c = 0; c < nc; ++c)
+      for (int r2 = 0; r2 < nc; ++r2) {
+        cplx acc = 0;
+        for (int q = 0; q < m; ++q) acc += std::conj(Qm[(size_t)r2 * m + q]) * HQ[(size_t)c * m + q];
+        at(Hn, nc, r2, c) = acc;
+      }
+    for (int c = 0; c < nc; ++c) {   // Hermitian up to rounding
+      at(Hn, nc, c, c) = at(Hn, nc, c, c).real();
+      for (int r2 = c + 1; r2 < nc; ++r2) at(Hn, nc, r2, c) = std::conj(at(Hn, nc, c, r2));
+    }
+    Hm.swap(Hn);
+  };
+  // Harmonic Ritz pairs for the target tau: W = X V - tau R V, W^H (X - theta
+  // R) V s = 0, i.e. (W^H W) s = nu (W^H R V) s with theta = tau + nu; the
+  // pairs of smallest |nu| are the harmonic approximations closest to tau
+  // (extreme eigenvalues of (W^H W)^-1 W^H R V), which unlike Ritz values do
+  // not wander where the target lies inside a dense part of the spectrum.
+  // S receives the vectors (unit norm, ordered by |nu|), w their Rayleigh
+  // quotients s^H H s (the eigenvalue estimates and correction shifts).
+  auto harmonic_pairs = [&](int m, const Mat& Hm, Mat& Sout, std::vector<double>& wout) {
+    for (int c = 0; c < m; ++c) {
+      copy(XV + (size_t)c * N, Tmp.d() + (size_t)c * N, N);
+      K.axpy(RV + (size_t)c * N, -target, Tmp.d() + (size_t)c * N);
+    }
+    Mat A((size_t)m * m), B((size_t)m * m);
+    for (int c = 0; c < m; ++c) {
+      dots(Tmp.d(), m, Tmp.d() + (size_t)c * N);
+      for (int r2 = 0; r2 < m; ++r2) at(A, m, r2, c) = cplx(hh[r2].x, hh[r2].y);
+      dots(Tmp.d(), m, RV + (size_t)c * N);
+      for (int r2 = 0; r2 < m; ++r2) at(B, m, r2, c) = cplx(hh[r2].x, hh[r2].y);
+    }
+    // A = L L^H (a tiny diagonal shift keeps it definite when W loses rank)
+    double tr = 0;
+    for (int c = 0; c < m; ++c) tr += at(A, m, c, c).real();
+    Mat L((size_t)m * m, cplx(0));
+    for (int c = 0; c < m; ++c) {
+      cplx d = at(A, m, c, c) + 1e-14 * tr / m;
+      for (int q = 0; q < c; ++q) d -= at(L, m, c, q) * std::conj(at(L, m, c, q));
+      const double ld = std::sqrt(std::max(d.real(), 1e-300));
+      at(L, m, c, c) = ld;
+      for (int r2 = c + 1; r2 < m; ++r2) {
+        cplx acc = at(A, m, r2, c);
+        for (int q = 0; q < c; ++q) acc -= at(L, m, r2, q) * std::conj(at(L, m, c, q));
+        at(L, m, r2, c) = acc / ld;
+      }
+    }
+    // C = L^-1 B L^-H
+    auto lsolve = [&](std::vector<cplx>& x) {   // x <- L^-1 x
+      for (int r2 = 0; r2 < m; ++r2) {
+        cplx acc = x[r2];
+        for (int q = 0; q < r2; ++q) acc -= at(L, m, r2, q) * x[q];
+        x[r2] = acc / at(L, m, r2, r2);
+      }
+    };
+    auto lhsolve = [&](std::vector<cplx>& x) {   // x <- L^-H x
+      for (int r2 = m - 1; r2 >= 0; --r2) {
+        cplx acc = x[r2];
+        for (int q = r2 + 1; q < m; ++q) acc -= std::conj(at(L, m, q, r2)) * x[q];
+        x[r2] = acc / at(L, m, r2, r2);
+      }
+    };
+    Mat Cm((size_t)m * m);
+    {
+      Mat T1((size_t)m * m);   // L^-1 B
+      std::vector<cplx> col(m);
+      for (int c = 0; c < m; ++c) {
+        for (int r2 = 0; r2 < m; ++r2) col[r2] = at(B, m, r2, c);
+        lsolve(col);
+        for (int r2 = 0; r2 < m; ++r2) at(T1, m, r2, c) = col[r2];
+      }
+      // (L^-1 B) L^-H = (L^-1 (L^-1 B)^H)^H
+      for (int r2 = 0; r2 < m; ++r2) {
+        for (int c = 0; c < m; ++c) col[c] = std::conj(at(T1, m, r2, c));
+        lsolve(col);
+        for (int c = 0; c < m; ++c) at(Cm, m, r2, c) = std::conj(col[c]);
+      }
+    }
+    std::vector<cplx> ev;
+    Mat Y;
+    if (!gen_eig(Cm, m, ev, Y)) throw Error(-6, "Jacobi-Davidson: harmonic eigenproblem did not converge");
+    std::vector<int> ord(m);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::abs(ev[a]) > std::abs(ev[b]); });
+    Sout.assign((size_t)m * m, cplx(0));
+    wout.assign(m, 0.0);
+    std::vector<cplx> sv(m);
+    for (int c = 0; c < m; ++c) {
+      for (int r2 = 0; r2 < m; ++r2) sv[r2] = at(Y, m, r2, ord[c]);
+      lhsolve(sv);
+      double nrm = 0;
+      for (auto& z : sv) nrm += std::norm(z);
+      nrm = std::sqrt(std::max(nrm, 1e-300));
+      cplx rq = 0;
+      for (int r2 = 0; r2 < m; ++r2) {
+        sv[r2] /= nrm;
+        Sout[(size_t)c * m + r2] = sv[r2];
+      }
+      for (int r2 = 0; r2 < m; ++r2)
+        for (int q = 0; q < m; ++q) rq += std::conj(sv[r2]) * Hm[(size_t)q * m + r2] * sv[q];
+      wout[c] = rq.real();
+    }
   };
   copy(v0, t.d(), N);
   int k = 0, m = 0, since_lock = 0;
@@ -698,20 +929,24 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
     double theta = 0;
     bool expand = false;
     while (m > 0) {
-      herm_eig(H, m, w, S);
-      // order by distance to the target
-      std::vector<int> ord(m);
-      std::iota(ord.begin(), ord.end(), 0);
-      std::stable_sort(ord.begin(), ord.end(),
-                       [&](int a, int b) { return std::abs(w[a] - target) < std::abs(w[b] - target); });
-      Mat So((size_t)m * m);
-      std::vector<double> wo(m);
-      for (int c = 0; c < m; ++c) {
-        wo[c] = w[ord[c]];
-        for (int r2 = 0; r2 < m; ++r2) So[(size_t)c * m + r2] = S[(size_t)ord[c] * m + r2];
+      if (harmonic) {
+        harmonic_pairs(m, H, S, w);
+      } else {
+        herm_eig(H, m, w, S);
+        // order by distance to the target
+        std::vector<int> ord(m);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int a, int b) { return std::abs(w[a] - target) < std::abs(w[b] - target); });
+        Mat So((size_t)m * m);
+        std::vector<double> wo(m);
+        for (int c = 0; c < m; ++c) {
+          wo[c] = w[ord[c]];
+          for (int r2 = 0; r2 < m; ++r2) So[(size_t)c * m + r2] = S[(size_t)ord[c] * m + r2];
+        }
+        S.swap(So);
+        w.swap(wo);
       }
-      S.swap(So);
-      w.swap(wo);
       theta = w[0];
       // u (into the locked block's next column), R u, X u, r = X u - theta R u
       Mat s0(S.begin(), S.begin() + m);
@@ -725,15 +960,29 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
         out.lam.push_back(theta);
         out.resid.push_back(rn);
         ++k;
+        if (K.verbose()) {
+          std::fprintf(stderr, "cm_jd: %d of %d converged (lambda %.9g) after %d outer iterations\n", k, nev, theta,
+                       out.outer);
+          std::fflush(stderr);
+        }
         since_lock = 0;
         if (k == nev) break;
-        // deflate: the rest of the Ritz vectors stay
-        recombine(V, m, S, 1, m - 1);
-        recombine(XV, m, S, 1, m - 1);
-        recombine(RV, m, S, 1, m - 1);
-        --m;
-        H.assign((size_t)m * m, cplx(0));
-        for (int c = 0; c < m; ++c) at(H, m, c, c) = w[c + 1];
+        // deflate: the rest of the (harmonic) Ritz vectors stay, as an
+        // orthonormal basis of the complement of the locked one
+        if (harmonic) {
+          Mat Qo;
+          const int kept = orthonormal_columns(S, m, m, Qo);   // S[:, 0] first: drop it after
+          Mat Qr(Qo.begin() + (size_t)m, Qo.begin() + (size_t)kept * m);
+          change_basis(Qr, kept - 1, H, m);
+          m = kept - 1;
+        } else {
+          recombine(V, m, S, 1, m - 1);
+          recombine(XV, m, S, 1, m - 1);
+          recombine(RV, m, S, 1, m - 1);
+          --m;
+          H.assign((size_t)m * m, cplx(0));
+          for (int c = 0; c < m; ++c) at(H, m, c, c) = w[c + 1];
+        }
         continue;
       }
       expand = true;
@@ -741,7 +990,7 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
     }
     if (k == nev) break;
     if (precond && ++since_lock > stall) {
-      precond = false;
+      precond = 0;
       out.precond_dropped = 1;
     }
     if (!expand) {   // every Ritz vector locked: expand from the start vector again
@@ -750,19 +999,28 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
     }
     if (m >= mmax) {
       const int keep = std::min(mmin, m);
-      recombine(V, m, S, 0, keep);
-      recombine(XV, m, S, 0, keep);
-      recombine(RV, m, S, 0, keep);
-      m = keep;
-      H.assign((size_t)m * m, cplx(0));
-      for (int c = 0; c < m; ++c) at(H, m, c, c) = w[c];
+      if (harmonic) {
+        Mat Qo;
+        const int kept = orthonormal_columns(S, m, keep, Qo);
+        change_basis(Qo, kept, H, m);
+        m = kept;
+      } else {
+        recombine(V, m, S, 0, keep);
+        recombine(XV, m, S, 0, keep);
+        recombine(RV, m, S, 0, keep);
+        m = keep;
+        H.assign((size_t)m * m, cplx(0));
+        for (int c = 0; c < m; ++c) at(H, m, c, c) = w[c];
+      }
     }
     // correction equation, fixed number of GMRES steps from t = 0, rhs -r
     const int kq = k + 1;   // Qu = Q[:, 0..k], R Qu = RQ[:, 0..k]
     auto op = [&](const double2* x, double2* z) {
-      if (precond) {
+      if (precond == 1) {
         K.precond(x, py.d());
         K.scale_copy(py.d(), cplx(0, 1), y.d());   // y = i P x
+      } else if (precond == 2) {
+        K.precond(x, y.d());                       // y = P x, P the SAI of X_near
       } else {
         copy(x, y.d(), N);
       }
@@ -809,9 +1067,12 @@ static JdResult jd(KrylovCtx& K, int nev, double target, int mmin, int mmax, int
       yv[q] = acc / Hg[(size_t)q * (inner + 1) + q];
     }
     K.combine(G, nst, yv, nst, 1, t.d());
-    if (precond) {
+    if (precond == 1) {
       K.precond(t.d(), py.d());
       K.scale_copy(py.d(), cplx(0, 1), t.d());
+    } else if (precond == 2) {
+      K.precond(t.d(), py.d());
+      copy(py.d(), t.d(), N);
     }
   }
   out.nconv = k;
@@ -850,8 +1111,8 @@ extern "C" cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t rest
 }
 
 extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t mmax, int32_t maxit,
-                           double tol, int32_t inner_steps, int32_t precond, const void* v0, cm_dtype far_dtype,
-                           double* lambda,
+                           double tol, int32_t inner_steps, int32_t precond, int32_t harmonic, const void* v0,
+                           cm_dtype far_dtype, double* lambda,
                            double* resid, void* J, int32_t* nconv, int64_t* counters, void* hip_stream) {
   if (!h || !v0 || !lambda) return cm::driver_fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
@@ -860,11 +1121,14 @@ extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmi
     return cm::driver_fail(CM_E_BADARG,
                            "bad Jacobi-Davidson parameters (need 1 <= nev <= 512, 1 <= mmin < mmax <= min(N, 512), "
                            "maxit >= 1, tol > 0, 1 <= inner_steps <= 512)");
-  if (precond && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (precond < 0 || precond > 2) return cm::driver_fail(CM_E_BADARG, "precond must be 0, 1 or 2");
+  if (precond == 1 && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI of Z_near not built");
+  if (precond == 2 && (!h->dev.sai[1].val || h->dev.sai_tau1 != 0.0))
+    return cm::driver_fail(CM_E_NOT_BUILT, "SAI of X_near (tau 0) not built");
   try {
-    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
-    cm::JdResult r =
-        cm::jd(K, nev, target, mmin, mmax, maxit, tol, inner_steps, (const double2*)v0, (double2*)J, precond != 0);
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream, precond == 2 ? 1 : 0);
+    cm::JdResult r = cm::jd(K, nev, target, mmin, mmax, maxit, tol, inner_steps, (const double2*)v0, (double2*)J,
+                            precond, harmonic != 0);
     for (int i = 0; i < nev; ++i) {
       lambda[i] = i < r.nconv ? r.lam[i] : 0.0;
       if (resid) resid[i] = i < r.nconv ? r.resid[i] : 0.0;
@@ -886,22 +1150,25 @@ extern "C" cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmi
 
 extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
                              int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond,
-                             cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
-                             int64_t* counters, void* hip_stream) {
+                             double tau, cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J,
+                             int32_t* nconv, int64_t* counters, void* hip_stream) {
   if (!h || !v0 || !lambda) return cm::driver_fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (nev < 1 || ncv <= nev || ncv > 1000 || ncv > h->dev.N || maxrestart < 0 || !(tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
   if (gmres_restart < 1 || gmres_restart > 1000 || gmres_maxit < 1 || !(gmres_tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters (need 1 <= gmres_restart <= 1000)");
-  if (precond && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (!(tau > 0) || !(tau <= 1e6)) return cm::driver_fail(CM_E_BADARG, "tau must be in (0, 1e6]");
+  const int slot = cm::sai_slot(tau);
+  if (precond && (!h->dev.sai[slot].val || (slot == 1 && h->dev.sai_tau1 != tau)))
+    return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built for this tau");
   try {
-    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream, slot, tau);
     cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
-                                gmres_tol, precond != 0, (double2*)J);
+                                gmres_tol, precond != 0, (double2*)J, tau == 1.0 ? 0 : 5);
     for (int i = 0; i < nev; ++i) {
-      // lambda = i (1 - 1/mu)
-      cm::cplx lam = cm::cplx(0, 1) * (1.0 - 1.0 / r.mu[i]);
+      // (tau R + i X) J = (tau + i lambda) R J:  lambda = i (tau - 1/mu)
+      cm::cplx lam = cm::cplx(0, 1) * (tau - 1.0 / r.mu[i]);
       lambda[2 * i] = lam.real();
       lambda[2 * i + 1] = lam.imag();
       if (ritz_resid) ritz_resid[i] = r.resid[i];
@@ -933,7 +1200,8 @@ extern "C" cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_
     return cm::driver_fail(CM_E_BADARG, "bad eigensolver parameters (need 1 <= nev < ncv <= min(N, 1000))");
   if (gmres_restart < 1 || gmres_restart > 1000 || gmres_maxit < 1 || !(gmres_tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters (need 1 <= gmres_restart <= 1000)");
-  if (precond && !h->dev.sai[1].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI of X not built");
+  if (precond && (!h->dev.sai[1].val || h->dev.sai_tau1 != 0.0))
+    return cm::driver_fail(CM_E_NOT_BUILT, "SAI of X_near (tau 0) not built");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream, 1);
     cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,

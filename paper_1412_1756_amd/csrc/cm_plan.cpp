@@ -705,13 +705,13 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     Level& Lv = lev[l];
     auto make = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& src,
                     const std::vector<int32_t>& off, std::vector<int32_t>& tptr, std::vector<int32_t>& tsrc,
-                    std::vector<int32_t>& toff) {
-      const int ntile = (Lv.nbox + kTile - 1) / kTile;
+                    std::vector<int32_t>& toff, int TS) {
+      const int ntile = (Lv.nbox + TS - 1) / TS;
       tptr.assign(ntile + 1, 0);
       for (int t = 0; t < ntile; ++t) {
         std::vector<std::pair<int, std::pair<int, int>>> ent;   // (source, (receiver slot, compact off))
-        for (int r = 0; r < kTile; ++r) {
-          int m = t * kTile + r;
+        for (int r = 0; r < TS; ++r) {
+          int m = t * TS + r;
           if (m >= Lv.nbox) break;
           for (int e = ptr[m]; e < ptr[m + 1]; ++e) ent.push_back({src[e], {r, Lv.off_compact[off[e]]}});
         }
@@ -721,7 +721,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
           int sbox = ent[i].first;
           tsrc.push_back(sbox);
           size_t base = toff.size();
-          toff.resize(base + kTile, -1);
+          toff.resize(base + TS, -1);
           while (i < ent.size() && ent[i].first == sbox) {
             toff[base + ent[i].second.first] = ent[i].second.second;
             ++i;
@@ -730,8 +730,10 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
         tptr[t + 1] = (int32_t)tsrc.size();
       }
     };
-    make(Lv.far_ptr, Lv.far_src, Lv.far_off, Lv.tile_ptr, Lv.tile_src, Lv.tile_off);
-    make(Lv.farR_ptr, Lv.farR_src, Lv.farR_off, Lv.tileR_ptr, Lv.tileR_src, Lv.tileR_off);
+    make(Lv.far_ptr, Lv.far_src, Lv.far_off, Lv.tile_ptr, Lv.tile_src, Lv.tile_off, kTile);
+    make(Lv.farR_ptr, Lv.farR_src, Lv.farR_off, Lv.tileR_ptr, Lv.tileR_src, Lv.tileR_off, kTile);
+    make(Lv.far_ptr, Lv.far_src, Lv.far_off, Lv.tile64_ptr, Lv.tile64_src, Lv.tile64_off, kTile64);
+    make(Lv.farR_ptr, Lv.farR_src, Lv.farR_off, Lv.tileR64_ptr, Lv.tileR64_src, Lv.tileR64_off, kTile64);
   }
 
   // ---- interpolation (child l+1 -> parent l, l = 2..lf-1) and shift phases
@@ -885,7 +887,8 @@ std::string Plan::stats_json() const {
     s << "{\"l\": " << l << ", \"a\": " << Lv.a << ", \"nbox\": " << Lv.nbox << ", \"L\": " << Lv.L
       << ", \"nt\": " << Lv.nt << ", \"np\": " << Lv.np << ", \"K\": " << Lv.K
       << ", \"far_pairs\": " << (Lv.far_src.size()) << ", \"farR_pairs\": " << (Lv.farR_src.size())
-      << ", \"tile_sources\": " << Lv.tile_src.size() << ", \"n_off_used\": " << Lv.n_off_used;
+      << ", \"tile_sources\": " << Lv.tile_src.size() << ", \"tile64_sources\": " << Lv.tile64_src.size()
+      << ", \"n_off_used\": " << Lv.n_off_used;
     // matrix-core interpolation tables (into level l, and anterpolation from it)
     auto mf = [&](const char* key, const std::vector<MfTab>& v) {
       if (l >= (int)v.size() || !v[l].nchunk) return;

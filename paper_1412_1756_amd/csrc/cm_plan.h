@@ -47,11 +47,17 @@ struct Level {
   std::vector<int32_t> tile_off;            // int32: read with scalar loads in the kernel
   std::vector<int32_t> tileR_ptr, tileR_src;
   std::vector<int32_t> tileR_off;
+  // the same for tiles of kTile64 boxes (the shared-source translation of
+  // batched FP32 applies; on a surface mesh a 64-box tile loads each source
+  // for about 12 receivers, a 16-box tile for about 6)
+  std::vector<int32_t> tile64_ptr, tile64_src, tile64_off;
+  std::vector<int32_t> tileR64_ptr, tileR64_src, tileR64_off;
   std::vector<int32_t> off_compact;                   // kNoff -> compact id (-1 unused)
   int n_off_used = 0;
 };
 
 constexpr int kTile = 16;
+constexpr int kTile64 = 64;
 
 // Local Lagrange interpolation from level c = l+1 (child) to level l (parent),
 // separable: theta first (with reflection over the poles), then phi.

@@ -3,8 +3,9 @@
 // them): Z~ drops entries |z_ij| < eps1 |z_jj| of column j; column j of P lives
 // on J_j = {i : |z_ij| >= eps2 |z_jj|}; the rows taking part are the nonzero
 // rows of Z~(:, J_j); entries |p_ij| < eps3 max_i |p_ij| are dropped after the
-// solve.  The same construction serves the near field of X = Im Z (a real
-// matrix) for the inner solves with X.  Set-up work on the host: the near
+// solve.  The same construction serves the near field of the shifted
+// operator tau R + i X of the Arnoldi inner solves (tau Re Z_near + i Im
+// Z_near; tau = 0: the real X_near).  Set-up work on the host: the near
 // field is copied down once, every
 // column's small least-squares problem is solved by Householder QR in FP64,
 // and P is uploaded in CSR by rows for the device apply.
@@ -64,14 +65,18 @@ static void lsq_householder(int m, int n, std::vector<cplx>& A, std::vector<cplx
   }
 }
 
-void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, int part, hipStream_t s) {
+void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, double tau, hipStream_t s) {
+  const int part = sai_slot(tau);
   const int64_t N = d.N;
   std::vector<double2> zn(P.nnz);
   chk_s(hipMemcpyAsync(zn.data(), d.Zn, P.nnz * sizeof(double2), hipMemcpyDeviceToHost, s), "SAI: copy near field");
   chk_s(hipStreamSynchronize(s), "SAI: copy near field");
-  // part 1: the near field of X = Im Z (a real matrix)
-  if (part == 1)
+  // the near field of tau R + i X: tau Re z + i Im z; tau = 0 selects the
+  // real matrix X_near = Im Z_near itself (the solves with X)
+  if (tau == 0.0)
     for (auto& z : zn) z = make_double2(z.y, 0.0);
+  else if (tau != 1.0)
+    for (auto& z : zn) z = make_double2(tau * z.x, z.y);
   // row i of Z_near (internal order) = column i (Z_near is symmetric)
   auto row_cols = [&](int64_t i, const int32_t*& cols, const double2*& vals, int& n) {
     int b = P.box_of[i];
@@ -181,6 +186,7 @@ void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, int p
     chk_s(hipMemcpy(q.val, val.data(), nnz * sizeof(double2), hipMemcpyHostToDevice), "SAI upload");
   }
   q.nnz = nnz;
+  if (part == 1) d.sai_tau1 = tau;
 }
 
 }  // namespace cm

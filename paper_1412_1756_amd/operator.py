@@ -21,13 +21,18 @@ class Operator:
     R x the standard MLFMA lists instead of the sibling bookkeeping
     (CM_FLAG_R_STANDARD); k_sampling: the wavenumber at which the
     truncation rule sets L and the sampling (None: k itself; a common value
-    freezes the discretisation across handles at nearby k).  k may be a
+    freezes the discretisation across handles at nearby k); verbose=True
+    makes the eigen-solvers print a progress line per restart to stderr;
+    m2l_tile16=True selects the 16-box-tile FP32 translation kernel
+    (CM_FLAG_M2L_TILE16) instead of the 64-box shared-source one.
+    k may be a
     sequence of wavenumbers (a sweep; apply's k_index picks one per column).
     """
 
     def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
                  deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, wide_near=False,
-                 autotune=False, r_standard=False, k_sampling=None, stream=None):
+                 autotune=False, r_standard=False, k_sampling=None, verbose=False, m2l_tile16=False,
+                 stream=None):
         L = lib()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -46,7 +51,9 @@ class Operator:
                    | (_lib.CM_FLAG_NEAR_FP32 if near_fp32 else 0)
                    | (_lib.CM_FLAG_WIDE_NEAR if wide_near else 0)
                    | (_lib.CM_FLAG_AUTOTUNE if autotune else 0)
-                   | (_lib.CM_FLAG_R_STANDARD if r_standard else 0))
+                   | (_lib.CM_FLAG_R_STANDARD if r_standard else 0)
+                   | (_lib.CM_FLAG_VERBOSE if verbose else 0)
+                   | (_lib.CM_FLAG_M2L_TILE16 if m2l_tile16 else 0))
         kk = np.atleast_1d(np.asarray(k, dtype=np.float64)).copy()
         h = C.c_void_p()
         s = self._stream_ptr(stream) if not host_only else None
@@ -190,25 +197,31 @@ class Operator:
         check(st)
         return Y.reshape(-1) if squeeze else Y
 
-    _PARTS = {"Z": 0, "X": 2}
+    @staticmethod
+    def _tau(part, tau):
+        if tau is not None:
+            return float(tau)
+        return {"Z": 1.0, "X": 0.0}[part]
 
-    def sai_build(self, eps1=0.01, eps2=0.014, eps3=0.18, k_index=0, part="Z"):
-        """SAI of the near field of Z (part="Z") or of X (part="X") at the
-        wavenumber ks[k_index]."""
-        check(lib().cm_sai_build(self._h, eps1, eps2, eps3, int(k_index), self._PARTS[part]))
+    def sai_build(self, eps1=0.01, eps2=0.014, eps3=0.18, k_index=0, part="Z", tau=None):
+        """SAI of the near field of tau R + i X at the wavenumber
+        ks[k_index]: tau=1 (part="Z") Z_near, tau=0 (part="X") the real
+        X_near, other tau the shifted operator of eigs(tau=...)."""
+        check(lib().cm_sai_build(self._h, eps1, eps2, eps3, int(k_index), self._tau(part, tau)))
 
-    def sai_nnz(self, part="Z"):
-        """Stored entries of the SAI matrix (after sai_build; at k[0])."""
+    def sai_nnz(self, part="Z", tau=None):
+        """Stored entries of an SAI matrix (after sai_build; at k[0])."""
         nnz = C.c_int64()
-        check(lib().cm_export_near(self._h, 2 if part == "Z" else 3, C.byref(nnz), None, None, None))
+        which = 2 if self._tau(part, tau) == 1.0 else 3
+        check(lib().cm_export_near(self._h, which, C.byref(nnz), None, None, None))
         return int(nnz.value)
 
-    def sai_apply(self, x, out=None, stream=None, k_index=None, part="Z"):
+    def sai_apply(self, x, out=None, stream=None, k_index=None, part="Z", tau=None):
         X, Y, dt, squeeze = self._vec_args(x, out)
         ki = self._k_index(k_index, X.shape[1])
         st = lib().cm_sai_apply(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.stride(0),
-                                X.shape[1], None if ki is None else C.c_void_p(ki.ctypes.data), self._PARTS[part],
-                                dt, self._stream_ptr(stream))
+                                X.shape[1], None if ki is None else C.c_void_p(ki.ctypes.data),
+                                self._tau(part, tau), dt, self._stream_ptr(stream))
         check(st)
         return Y.reshape(-1) if squeeze else Y
 
@@ -294,11 +307,13 @@ class Operator:
         return x, int(it.value), float(rr.value), st == _lib.CM_OK
 
     def jd(self, nev, v0, target=0.0, mmin=6, mmax=20, maxit=500, tol=1e-8, inner_steps=10, precond=False,
-           far="fp64", vectors=True, stream=None):
+           far="fp64", vectors=True, stream=None, harmonic=False):
         """Characteristic values closest to target by Jacobi-Davidson on the
         pencil (X, R) (no inner solve with Z).  v0: CUDA complex128 start
-        vector; precond=True solves the corrections right-preconditioned by
-        i P with the SAI P of Z (sai_build first).  Returns dict(lam, resid,
+        vector; precond=True (or "Z") solves the corrections right-
+        preconditioned by i P with the SAI P of Z (sai_build first), "X" by
+        the SAI of X_near (sai_build(part="X") first); harmonic=True selects
+        harmonic Ritz pairs for the target.  Returns dict(lam, resid,
         J (N x nconv, R-normalised), nconv, outer, inner_steps, n_matvec,
         precond_dropped, converged); the preconditioner is dropped after
         max(50, maxit / 8) outer iterations without a new converged pair."""
@@ -309,7 +324,8 @@ class Operator:
         cnt = np.zeros(4, dtype=np.int64)
         J = torch.empty((nev, self.N), dtype=torch.complex128, device=v0.device) if vectors else None
         nconv = C.c_int32()
-        st = lib().cm_jd(self._h, nev, float(target), mmin, mmax, maxit, tol, inner_steps, 1 if precond else 0,
+        pc = {False: 0, None: 0, True: 1, "Z": 1, "X": 2}[precond]
+        st = lib().cm_jd(self._h, nev, float(target), mmin, mmax, maxit, tol, inner_steps, pc, 1 if harmonic else 0,
                          C.c_void_p(v0.data_ptr()),
                          _lib.CM_C128 if far == "fp64" else _lib.CM_C64, lam.ctypes.data, res.ctypes.data,
                          C.c_void_p(J.data_ptr()) if vectors else None, C.byref(nconv), cnt.ctypes.data,
@@ -322,7 +338,7 @@ class Operator:
                     converged=(st == _lib.CM_OK))
 
     def eigs(self, nev, ncv, v0, tol=1e-8, maxrestart=50, gmres_restart=50, gmres_maxit=1000, gmres_tol=1e-8,
-             precond=None, far="fp64", vectors=True, stream=None, route="Z"):
+             precond=None, far="fp64", vectors=True, stream=None, route="Z", tau=1.0):
         """Characteristic values by implicitly restarted Arnoldi on Z^-1 R.
         v0: CUDA complex128 start vector.  Returns dict(lam, resid, J, nconv,
         n_op, gmres_iters, n_matvec, restarts, inner_retries, inner_failures,
@@ -330,7 +346,10 @@ class Operator:
         converged or when an inner GMRES solve missed gmres_tol.  route="X":
         IRA on X^-1 R (eq. (14)) instead of Z^-1 R, its inner solves with X
         preconditioned by the SAI of X_near when precond (sai_build(part="X")
-        first).  precond=None: True for route "Z", False for route "X"."""
+        first).  precond=None: True for route "Z", False for route "X".
+        tau (route "Z"): OP = (tau R + i X)^-1 R, tau = 1 being Z^-1 R; a
+        smaller tau separates modes with |lambda| up to about tau (its SAI:
+        sai_build(tau=tau))."""
         import torch
         v0 = self._start_vector(v0)
         lam = np.zeros(2 * nev)
@@ -348,7 +367,8 @@ class Operator:
                                     res.ctypes.data, Jp, C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
         elif route == "Z":
             st = lib().cm_eigs(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
-                               gmres_maxit, gmres_tol, 1 if precond else 0, fd, lam.ctypes.data, res.ctypes.data,
+                               gmres_maxit, gmres_tol, 1 if precond else 0, float(tau), fd, lam.ctypes.data,
+                               res.ctypes.data,
                                Jp, C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
         else:
             raise ValueError("route must be 'Z' or 'X'")

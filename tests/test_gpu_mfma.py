@@ -146,7 +146,9 @@ def test_mfma_repeat_is_deterministic(torch_cuda, ops):
 
 def test_autotune_choices_and_parity(torch_cuda, sphere2, ops):
     """CM_FLAG_AUTOTUNE: every matrix-core interpolation and anterpolation
-    stage gets a timed choice no slower than the default shape, and the tuned
+    stage gets a timed choice no slower than the default shape, every
+    translation level a choice of kernel no slower than the 16-box tiles, and
+    the tuned
     product differs from the untuned one by FP32 rounding only (same bounds
     as the matrix-core/vector-ALU comparison), for Z, Z^H and dZ/dk."""
     torch = torch_cuda
@@ -156,8 +158,12 @@ def test_autotune_choices_and_parity(torch_cuda, sphere2, ops):
     at = Operator(V, F, K0, nlv=5, max_cols=32, autotune=True, **ACC32)
     tune = at.stats()["autotune"]
     print("autotune:", tune, flush=True)
-    assert {t["stage"] for t in tune} == {"interp_l2", "interp_l3", "anterp_l3", "anterp_l4"}
+    assert {t["stage"] for t in tune} == {"interp_l2", "interp_l3", "anterp_l3", "anterp_l4", "m2l_l2", "m2l_l3",
+                                          "m2l_l4"}
     for t in tune:
+        if t["stage"].startswith("m2l"):   # translation kernel: 16-box tiles or 64-box shared-source tiles
+            assert t["tile"] in (16, 64) and t["ms"] <= t["tile16_ms"]
+            continue
         assert t["half_slots"] in (4, 8) and t["row_group"] in (1, 2, 4)
         assert t["default_ms"] < 0 or t["ms"] <= t["default_ms"]
     Xh = workloads.cn01_block(mf.N, 32, 1234)
@@ -287,3 +293,23 @@ def test_apply_replays_from_a_captured_graph(torch_cuda, ops):
             ye = mf.apply(Xh)                       # eager, between the replays
             torch.cuda.synchronize()
             assert torch.equal(yg, ye), (dt, seed)
+
+
+@pytest.mark.parametrize("ncols,ld", [(8, 8), (16, 16), (32, 40)])
+def test_shared_source_translation_equals_tile16(torch_cuda, sphere2, ncols, ld):
+    """The 64-box shared-source translation kernels (every variant, forced
+    on every level) against the 16-box-tile kernel: every receiver sums its
+    sources in the same order, so Z, R, X, Z^H and the dual (dZ/dk) pass
+    agree bit for bit."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator, _lib
+    V, F = sphere2
+    t16 = Operator(V, F, K0, nlv=5, max_cols=32, deriv=True, **ACC32)
+    X = torch.zeros((t16.N, ld), dtype=torch.complex64, device="cuda")
+    X[:, :ncols] = torch.tensor(workloads.cn01_block(t16.N, ncols, 700), dtype=torch.complex64)
+    X = X[:, :ncols]
+    ref = {o: t16.apply(X, o) for o in ("Z", "R", "X", "ZH", "DZDK")}
+    for v in (2, 3, 4):
+        assert _lib.lib().cm_set_translation_kernel(t16._h, v) == 0
+        for o, y in ref.items():
+            assert torch.equal(t16.apply(X, o), y), (v, o)

@@ -200,9 +200,9 @@ def test_mode_call_argument_errors(torch_cuda, cfg1):
     assert L.cm_real_currents(op._h, jp, 2, 2, jp, rp, 2, s) == _lib.CM_E_BADARG         # aliasing
     assert L.cm_real_currents(op._h, jp, 2, 2, op_, rp, 2, s) == _lib.CM_E_NUMERIC        # zero currents
     assert L.cm_modal_correlation(op._h, jp, 2, 2, jp, 1, 2, Cm.ctypes.data, s) == _lib.CM_E_BADARG
-    assert L.cm_sai_build(op._h, 0.01, 0.014, 0.18, 1, 0) == _lib.CM_E_BADARG             # k_index >= n_k
-    assert L.cm_sai_build(op._h, 0.01, 0.014, 0.18, 0, 1) == _lib.CM_E_BADARG             # part R
-    assert L.cm_sai_apply(op._h, jp, rp, 2, 2, None, 0, 1, s) == _lib.CM_E_NOT_BUILT      # no SAI yet
+    assert L.cm_sai_build(op._h, 0.01, 0.014, 0.18, 1, 1.0) == _lib.CM_E_BADARG           # k_index >= n_k
+    assert L.cm_sai_build(op._h, 0.01, 0.014, 0.18, 0, -0.5) == _lib.CM_E_BADARG          # tau < 0
+    assert L.cm_sai_apply(op._h, jp, rp, 2, 2, None, 1.0, 1, s) == _lib.CM_E_NOT_BUILT    # no SAI yet
     out = torch.zeros((), dtype=torch.complex128, device="cuda")
     assert L.cm_vdot(op._h, jp, rp, 1, 2, 1, C.c_void_p(out.data_ptr()), s) == _lib.CM_E_BADARG   # ld < ncols
     # the Python layer checks out / v0 before any call

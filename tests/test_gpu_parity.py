@@ -208,7 +208,7 @@ def test_sphere_r1_sampled_rows(torch_cuda, wide):
             yo = op.apply(torch.tensor(x, dtype=dt, device="cuda"), op=opname).cpu().numpy()
             eo = relerr(yo[rows], part @ x)
             print(f"  op {opname}: {eo:.3e}", flush=True)
-            assert eo < (2 * tol if opname == "X" else tol)
+            assert eo < tol
 
 
 def _golden(name):
@@ -286,29 +286,28 @@ def test_config2_R_sibling_and_standard_lists(torch_cuda):
 def test_config5_sampled_rows(torch_cuda):
     """N = 1,966,080 (radius 12 wavelengths, 8 levels, 0.1875-wavelength
     leaves, 790M near-field entries): the 32-column FP32 batch (d0 4.5, p 10,
-    autotuned) on four columns and the FP64 vector (d0 4, p 8, two-box
-    buffer, 2.2G near-field entries) on column 0, at four oracle rows written
-    by tests/golden/make_oracle_rows.py; Z x, and R x (sibling translation
-    lists, own leaf box as near field) and X x on the same handles."""
-    import json
-    import os
+    autotuned) on the first eight columns and the FP64 vector (d0 4, p 8,
+    two-box buffer, 2.2G near-field entries) on column 0, at 256 oracle rows
+    (seed 2) written by tests/golden/make_oracle_rows.py; Z x, and R x
+    (sibling translation lists, own leaf box as near field) and X x on the
+    same handles; the largest element error (over the rms of the reference)
+    is reported beside the bounded 2-norm error."""
     torch = torch_cuda
-    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_rows_sphere_r12_n1966080.json")))
-    rows = np.array(g["rows"])
-    ref = {o: np.array(g[o + "x_re"]) + 1j * np.array(g[o + "x_im"]) for o in ("Z", "R", "X")}
+    rows, ref, Xg = _golden("sphere_r12_n1966080")
     nc = ref["Z"].shape[1]
     V, F, spec = workloads.workload("sphere_r12_n1966080")
-    N = g["N"]
-    Xh = workloads.cn01_block(N, 32, 100)
-    Xh[:, 0] = workloads.cn01(N, 0)
-    tol = {"Z": 1.0, "R": 1.0, "X": 2.0}          # X: the larger cos-kernel error, as at 7,680 unknowns
+    N = Xg.shape[0]
+    Xh = np.zeros((N, 32), dtype=np.complex128)
+    Xh[:, :nc] = Xg
+    Xh[:, nc:] = workloads.cn01_block(N, 32, 100)[:, nc:]
+    del Xg
     print("building the FP32 handle (N = 1,966,080)", flush=True)
     op = _op(V, F, 8, dict(d0=4.5, interp_p=10), max_cols=32, autotune=True)
     X32 = torch.tensor(Xh, dtype=torch.complex64, device="cuda")
     e32 = {}
     for o in ("Z", "R", "X"):
         Y = op.apply(X32, op=o)[:, :nc].cpu().numpy()
-        e32[o] = float(np.linalg.norm(Y[rows] - ref[o]) / np.linalg.norm(ref[o]))
+        e32[o] = _errs(Y[rows], ref[o])
     del op, X32
     print("building the FP64 handle", flush=True)
     op = _op(V, F, 8, dict(d0=4.0, interp_p=8), max_cols=1, wide_near=True)
@@ -316,12 +315,14 @@ def test_config5_sampled_rows(torch_cuda):
     e64 = {}
     for o in ("Z", "R", "X"):
         y = op.apply(x64, op=o).cpu().numpy()
-        e64[o] = float(np.linalg.norm(y[rows] - ref[o][:, 0]) / np.linalg.norm(ref[o][:, 0]))
+        e64[o] = _errs(y[rows], ref[o][:, 0])
     del op
-    print("cfg5 fp32-batched", e32, "fp64", e64, flush=True)
     for o in ("Z", "R", "X"):
-        assert e32[o] < tol[o] * TOL32
-        assert e64[o] < tol[o] * TOL64
+        print(f"cfg5 {o}: fp32-batched 2-norm {e32[o][0]:.3e} (max element {e32[o][1]:.3e}), "
+              f"fp64 2-norm {e64[o][0]:.3e} (max element {e64[o][1]:.3e}), {rows.size} rows", flush=True)
+    for o in ("Z", "R", "X"):
+        assert e32[o][0] < TOL32
+        assert e64[o][0] < TOL64
 
 
 def test_sai_matches_oracle(torch_cuda, cfg1):
@@ -438,12 +439,15 @@ def test_dzdk_apply_matches_oracle(torch_cuda, cfg1_deriv):
 
 
 def test_dzdk_with_interpolation_sampled_rows(torch_cuda):
-    """The dual pass through interpolation/anterpolation (4 levels), plate in
-    the octree mid-plane, 30 oracle rows of dZ/dk.  Without interpolation
-    levels (3 levels) the pass matches to 5e-8; through interpolation the
-    k-derivative of the interpolated patterns (weighted by khat.(r - c)) is
-    approximated about 10x less accurately than the patterns themselves
-    (measured 3.8e-4 here against 2.7e-5 for Z), so the bound is 1e-3."""
+    """The dual pass through interpolation/anterpolation (4 levels, 0.625
+    wavelength leaves), plate in the octree mid-plane, 30 oracle rows of
+    dZ/dk, with the two-box buffer at the two finest levels: the
+    acceptance bound of the FP64 product, 1e-4.  Without interpolation levels
+    (3 levels) the pass matches to 1e-6.  With the paper's one-box buffer
+    the derivative of the expansion error of the distance-2 leaf pairs (whose
+    RWG supports overhang their boxes) is about 10x the error of Z itself
+    (3.8e-4 against 2.7e-5 measured), so that setting is reported, not
+    bounded at 1e-4."""
     torch = torch_cuda
     from oracle import efie
     V, F = workloads.plate(50, 50, 0.1)
@@ -451,14 +455,18 @@ def test_dzdk_with_interpolation_sampled_rows(torch_cuda):
     rows = np.sort(np.random.default_rng(2).choice(N, 30, replace=False))
     _, dZr = efie.rows_Z(V, F, K0, rows, deriv=True)
     x = workloads.cn01(N, 0)
-    op = _op(V, F, 4, ACC64, max_cols=1, deriv=True)
+    ref = dZr @ x
+    op = _op(V, F, 4, ACC64, max_cols=1, deriv=True, wide_near=True)
     y = op.apply(torch.tensor(x, dtype=torch.complex128, device="cuda"), "DZDK").cpu().numpy()
-    e = relerr(y[rows], dZr @ x)
-    print(f"plate dZ/dk x fp64: {e:.3e}", flush=True)
-    assert e < 1e-3
+    e = relerr(y[rows], ref)
+    op1 = _op(V, F, 4, ACC64, max_cols=1, deriv=True)
+    y1 = op1.apply(torch.tensor(x, dtype=torch.complex128, device="cuda"), "DZDK").cpu().numpy()
+    e1 = relerr(y1[rows], ref)
+    print(f"plate dZ/dk x fp64: two-box buffer {e:.3e}, one-box buffer {e1:.3e}", flush=True)
+    assert e < TOL64
     op3 = _op(V, F, 3, ACC64, max_cols=1, deriv=True)
     y3 = op3.apply(torch.tensor(x, dtype=torch.complex128, device="cuda"), "DZDK").cpu().numpy()
-    assert relerr(y3[rows], dZr @ x) < 1e-6
+    assert relerr(y3[rows], ref) < 1e-6
 
 
 def test_autograd_backward_matches_dense_gradient(torch_cuda, cfg1_deriv):
@@ -485,7 +493,7 @@ def test_autograd_backward_matches_dense_gradient(torch_cuda, cfg1_deriv):
     ek = abs(k.grad.item() - gk_ref) / abs(gk_ref)
     print(f"autograd: x.grad {ex:.2e}, k.grad {ek:.2e}", flush=True)
     assert ex < TOL64
-    assert ek < 10 * TOL64
+    assert ek < TOL64
 
 
 def test_config3_autograd_sampled_rows(torch_cuda):
@@ -495,7 +503,7 @@ def test_config3_autograd_sampled_rows(torch_cuda):
     gradients follow from the oracle's rows S of Z and dZ/dk: x.grad =
     Z[S, :]^H c_S (every entry, through the adjoint pass) and k.grad =
     Re c_S^H dZ[S, :] x (through the dual pass).  Bounds: 1e-4 for the
-    product and its adjoint, 1e-3 for dZ/dk through interpolation."""
+    product, its adjoint and the k-gradient."""
     torch = torch_cuda
     from oracle import efie
     from paper_1412_1756_amd.autograd import z_apply
@@ -521,7 +529,7 @@ def test_config3_autograd_sampled_rows(torch_cuda):
     ek = abs(k.grad.item() - gk_ref) / abs(gk_ref)
     print(f"plate autograd: y {ey:.2e}, x.grad {ex:.2e}, k.grad {ek:.2e}", flush=True)
     assert ey < TOL64 and ex < TOL64
-    assert ek < 1e-3
+    assert ek < TOL64
 
 
 def test_dlambda_dk_matches_oracle(torch_cuda, cfg1_deriv):
@@ -661,6 +669,28 @@ def test_jacobi_davidson_matches_qz(torch_cuda, cfg1):
     assert np.abs(G - np.eye(8)).max() < 1e-6
 
 
+def test_jacobi_davidson_harmonic_matches_qz(torch_cuda, cfg1):
+    """Jacobi-Davidson with harmonic Ritz extraction for the target 0 (and
+    with the SAI of X_near as the correction preconditioner): the eight
+    characteristic values nearest 0 of the 1,920-unknown sphere against dense
+    QZ, R-orthonormal vectors."""
+    torch = torch_cuda
+    from oracle import modes
+    V, F, Z = cfg1
+    N = Z.shape[0]
+    op = _op(V, F, 3, ACC64, max_cols=1)
+    op.sai_build(part="X")
+    v0 = torch.tensor(workloads.cn01(N, 3), dtype=torch.complex128, device="cuda")
+    lo = np.sort(modes.qz_modes(Z.imag, Z.real, nev=8).real)
+    for pc in (False, "X"):
+        r = op.jd(8, v0, target=0.0, mmin=6, mmax=20, maxit=400, tol=1e-8, inner_steps=20, harmonic=True, precond=pc)
+        print("harmonic JD precond", pc, np.sort(r["lam"]), "outer", r["outer"], "applies", r["n_matvec"], flush=True)
+        assert r["converged"] and r["nconv"] == 8
+        assert np.abs(np.sort(r["lam"]) - lo).max() < 1e-3
+        J = r["J"].cpu().numpy()
+        assert np.abs(J.conj().T @ Z.real @ J - np.eye(8)).max() < 1e-6
+
+
 def test_jacobi_davidson_plate_matches_qz(torch_cuda):
     """The 1.0 m x 0.6 m plate at 300 MHz (1,085 unknowns): the four
     characteristic values nearest 0 by Jacobi-Davidson against dense QZ."""
@@ -732,13 +762,15 @@ def test_argument_errors_return_status_before_any_launch(torch_cuda, cfg1):
     lam = np.zeros(8)
     nconv = C.c_int32()
     v0 = C.c_void_p(X.data_ptr())
-    assert L.cm_eigs(op._h, 4, 4, 10, 1e-8, v0, 20, 100, 1e-8, 0, 1, lam.ctypes.data, None, None,
+    assert L.cm_eigs(op._h, 4, 4, 10, 1e-8, v0, 20, 100, 1e-8, 0, 1.0, 1, lam.ctypes.data, None, None,
                      C.byref(nconv), None, s) == -1                      # ncv <= nev
-    assert L.cm_eigs(op._h, 2, 8, 10, 1e-8, v0, 20, 100, 1e-8, 1, 1, lam.ctypes.data, None, None,
+    assert L.cm_eigs(op._h, 2, 8, 10, 1e-8, v0, 20, 100, 1e-8, 1, 1.0, 1, lam.ctypes.data, None, None,
                      C.byref(nconv), None, s) == -5                      # SAI not built
-    assert L.cm_jd(op._h, 2, 0.0, 6, 5, 10, 1e-8, 10, 0, v0, 1, lam.ctypes.data, None, None,
+    assert L.cm_eigs(op._h, 2, 8, 10, 1e-8, v0, 20, 100, 1e-8, 0, 0.0, 1, lam.ctypes.data, None, None,
+                     C.byref(nconv), None, s) == -1                      # tau = 0
+    assert L.cm_jd(op._h, 2, 0.0, 6, 5, 10, 1e-8, 10, 0, 0, v0, 1, lam.ctypes.data, None, None,
                    C.byref(nconv), None, s) == -1                        # mmax <= mmin
-    assert L.cm_jd(op._h, 2, 0.0, 6, 20, 10, 1e-8, 10, 1, v0, 1, lam.ctypes.data, None, None,
+    assert L.cm_jd(op._h, 2, 0.0, 6, 20, 10, 1e-8, 10, 1, 0, v0, 1, lam.ctypes.data, None, None,
                    C.byref(nconv), None, s) == -5                        # i P without the SAI
     x = workloads.cn01(N, 0)
     y = op.apply(torch.tensor(x, dtype=torch.complex128, device="cuda")).cpu().numpy()
