@@ -22,6 +22,9 @@ What it computes, each by its plain definition:
 * ``translators``  the truncated translator series of eqs. (10), (16), (20)
                    with the truncation rule of eq. (30), and the point test of
                    the numerical-results section.
+* ``cmp``          the Calderon multiplicative preconditioner of eqs.
+                   (25)-(27): barycentric refinement, Buffa-Christiansen
+                   functions, the mixed Gram matrix, Z~ and Z~ G^-1 Z (dense).
 * ``sai``          the sparse approximate inverse of the near-field matrix
                    (section IV), column by column by least squares.
                    Parity unpinned: the paper does not define its thresholds.

@@ -147,10 +147,9 @@ def _incidence(rwg, nT):
     return sp.csr_matrix((vals, (rows, cols)), shape=(rwg["N"], 3 * nT))
 
 
-def dense_Z(V, F, k, eta=ETA0, deriv=False, chunk=48):
-    """Dense Z (N x N complex128); with deriv=True returns (Z, dZ/dk)."""
+def _dense_half(V, F, k, eta, deriv, chunk):
+    """Symmetrised half-function matrices (3 nT x 3 nT), row/column 3 T + a."""
     geo = Geometry(V, F)
-    rwg = build_rwg(V, F)
     nT = geo.tv.shape[0]
     H = np.zeros((nT, 3, nT, 3), dtype=np.complex128)
     dH = np.zeros_like(H) if deriv else None
@@ -165,17 +164,28 @@ def dense_Z(V, F, k, eta=ETA0, deriv=False, chunk=48):
         if deriv:
             dblk = _hf_dblock(k, eta, geo, To, Ts, out[0], out[1], out[2], out[3])
             dH[obs] = dblk.reshape(obs.size, nT, 3, 3).transpose(0, 2, 1, 3)
-    P = _incidence(rwg, nT)
 
-    def assemble(Hm):
+    def sym(Hm):
         Hm = Hm.reshape(3 * nT, 3 * nT)
-        Hm = 0.5 * (Hm + Hm.T)                # symmetrise (only near-singular blocks change)
-        return np.asarray((P @ (P @ Hm.T).T))
+        return 0.5 * (Hm + Hm.T)              # only near-singular blocks change
+    return (sym(H), sym(dH)) if deriv else (sym(H),)
 
-    Z = assemble(H)
-    if deriv:
-        return Z, assemble(dH)
-    return Z
+
+def dense_H(V, F, k, eta=ETA0, chunk=48):
+    """EFIE matrix between the half functions h_{T,a}(r) = (r - v_a)/(2 A_T)
+    of every triangle (unit flux out of T through the edge opposite v_a),
+    row/column 3 T + a: Z = P H P^T with P the incidence of RWGs on half
+    functions (sign times edge length)."""
+    return _dense_half(V, F, k, eta, False, chunk)[0]
+
+
+def dense_Z(V, F, k, eta=ETA0, deriv=False, chunk=48):
+    """Dense Z (N x N complex128); with deriv=True returns (Z, dZ/dk)."""
+    rwg = build_rwg(V, F)
+    Hs = _dense_half(V, F, k, eta, deriv, chunk)
+    P = _incidence(rwg, np.asarray(F).shape[0])
+    Zs = [np.asarray(P @ (P @ Hm.T).T) for Hm in Hs]
+    return (Zs[0], Zs[1]) if deriv else Zs[0]
 
 
 def rows_Z(V, F, k, rows, eta=ETA0, deriv=False, geo=None, rwg=None):
