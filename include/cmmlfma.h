@@ -288,9 +288,11 @@ cm_status cm_modal_correlation(cm_handle* h, const void* Ja, int64_t lda, int32_
 cm_status cm_dlambda_dk(cm_handle* h, double lambda, const void* J, int64_t ldj, int32_t m, double* dldk,
                         void* hip_stream);
 
-/* Right-preconditioned GMRES(restart) for Z x = b (the inner solves
-   Z^-1 u of section IV), x = P u with the SAI P when precond != 0 (needs
-   cm_sai_build).  b, x: device, N complex128 (FP64 Krylov vectors and
+/* GMRES(restart) for Z x = b (the inner solves Z^-1 u of section IV).
+   precond: 0 none; 1 right-preconditioned by the SAI P, x = P u (needs
+   cm_sai_build); 2 the Calderon preconditioner of eq. (25), GMRES on
+   Z~ G^-1 Z x = Z~ G^-1 b (needs cm_cmp_build; tol and *relres then refer
+   to that system).  b, x: device, N complex128 (FP64 Krylov vectors and
    Gram-Schmidt); far_dtype selects the far field of the Z products (CM_C128
    FP64, CM_C64 FP32).  x0 = 0; stops when ||b - Z x|| <= tol ||b|| or after
    maxit iterations (CM_E_NOT_CONVERGED).  *iters and *relres (may be NULL)
@@ -310,7 +312,8 @@ cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t restart, int32_
    ncv-vector factorisation with exact-shift restarts (nev < ncv <= N), each
    OP product one R apply and one GMRES solve with tau R + i X
    (gmres_restart, gmres_maxit, gmres_tol), right-preconditioned when
-   precond != 0 by the SAI built with the same tau (cm_sai_build).  v0:
+   precond = 1 by the SAI built with the same tau (cm_sai_build), or, with
+   precond = 2 and tau = 1, by the Calderon preconditioner (cm_cmp_build).  v0:
    device start vector (N complex128, nonzero; the caller draws it).
    Outputs (host): lambda[2*nev] interleaved complex characteristic values
    lambda = i (tau - 1/mu), smallest |tau + i lambda| first; ritz_resid[nev]
@@ -328,6 +331,46 @@ cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, do
                   int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond, double tau,
                   cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
                   int64_t* counters, void* hip_stream);
+
+/* Calderon multiplicative preconditioner (section IV, eqs. (25)-(27)) of a
+   handle on a closed surface (CM_E_MESH otherwise): builds the barycentric
+   refinement of the mesh (each triangle split into six at its edge midpoints
+   and centroid), an MLFMA handle on it with nlv_refined levels (0: one more
+   than the handle's) and the handle's other options (one column), the
+   Buffa-Christiansen function of every RWG as a combination of the refined
+   mesh's RWG functions (the paper names these functions without defining
+   them: each carries the RWG's flux l_e from the dual cell of one endpoint
+   of the edge to that of the other, with equal charge on every small
+   triangle of a cell, half of the flux through each half of the dual edge
+   and none through the refined edges along the primal edge), and the mixed
+   Gram matrix G_ij = <n x f_i, f~_j> (eq. (27)).  Z~ (eq. (26)) is then
+   applied as B Z_ref B^T and G^-1 by GMRES on G.  info (host, may be NULL)
+   receives 5 values: refined unknowns, entries of B, entries of G, near-field
+   entries of the refined handle, its levels.  A second call rebuilds.  On a
+   host-only handle (CM_FLAG_HOST_ONLY) only the host tables are built
+   (cm_cmp_export).  Synchronises. */
+cm_status cm_cmp_build(cm_handle* h, int32_t nlv_refined, int64_t* info, void* hip_stream);
+
+/* Host copy of a Calderon table in CSR by rows (public indices): which = 0
+   B (N x N_refined: row i holds the coefficients of the i-th BC function on
+   the refined mesh's RWG functions, in that handle's public order, i.e.
+   interior refined edges in increasing (smaller, larger) vertex order, the
+   refined vertices being the mesh's vertices, then one midpoint per RWG in
+   RWG order, then one centroid per triangle; refined triangle 6t + 2a is
+   (v_a, m(a, a+1), c_t) and 6t + 2a + 1 is (v_a, c_t, m(a-1, a)) for corner a
+   of triangle t), 1 G (N x N).  *rows and *nnz always; ptr (rows + 1), col
+   and val (nnz) are filled when all three are non-NULL (caller-allocated).
+   Needs cm_cmp_build. */
+cm_status cm_cmp_export(const cm_handle* h, int32_t which, int64_t* rows, int64_t* nnz, int64_t* ptr, int32_t* col,
+                        double* val);
+
+/* One product with the Calderon preconditioner's matrices on a single
+   column (x, y: device, N complex128, must not alias): which = 0 y = Z~ x,
+   1 y = G x, 2 y = Z~ G^-1 Z x (the matrix of eq. (25); the Gram solve to a
+   relative residual of 1e-12, CM_E_NOT_CONVERGED if it misses).  far_dtype
+   selects the far field of the MLFMA products.  Needs cm_cmp_build.
+   Synchronises with hip_stream. */
+cm_status cm_cmp_apply(cm_handle* h, int32_t which, const void* x, void* y, cm_dtype far_dtype, void* hip_stream);
 
 /* Characteristic modes by the implicitly restarted Arnoldi method on
    OP = X^-1 R (the standard eigenvalue problem of eq. (14)): mu = 1/lambda,

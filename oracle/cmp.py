@@ -45,7 +45,7 @@ EFIE matrix between half functions of the refined mesh (``efie.dense_H``).
 import numpy as np
 import scipy.sparse as sp
 
-from .efie import ETA0, dense_H, dense_Z
+from .efie import ETA0, Geometry, _hf_block, dense_H, dense_Z, pair_blocks
 from .quadrature import BARY, WEIGHTS
 from .rwg import MeshError, build_rwg
 
@@ -250,3 +250,35 @@ def cmp_matrices(V, F, k, eta=ETA0):
 def cmp_operator(Z, Zt, G):
     """The preconditioned matrix Z~ G^-1 Z of eq. (25)."""
     return Zt @ np.linalg.solve(G, Z)
+
+
+def ztilde_rows(V, F, k, rows, X, eta=ETA0, B=None, Vr=None, Fr=None):
+    """Rows `rows` of Z~ X (X: (N, ncol)) without the dense Z~: row i is
+    B[i] H (B^T X) with the rows of the symmetrised half-function matrix
+    0.5 (H + H^T) of the small triangles in the support of BC function i
+    (the definition of ``dense_Ztilde`` restricted to those rows)."""
+    if B is None:
+        B, Vr, Fr = bc_table(V, F)
+    X = np.asarray(X).reshape(B.shape[0], -1)
+    geo = Geometry(Vr, Fr)
+    ntr = Fr.shape[0]
+    Y = np.asarray(B.T @ X).reshape(ntr, 3, -1)              # half-function coefficients
+    Bc = B.tocsr()
+    allT = np.arange(ntr)
+    out = np.zeros((len(rows), X.shape[1]), dtype=np.complex128)
+    for r, i in enumerate(rows):
+        row = Bc.getrow(int(i))
+        for t in np.unique(row.indices // 3):
+            To = np.full(ntr, t)
+            s1 = pair_blocks(k, geo, To, allT)
+            h1 = _hf_block(k, eta, geo, To, allT, s1[0], s1[1])       # H[(t,a),(s,b)] as (s, a, b)
+            s2 = pair_blocks(k, geo, allT, To)
+            h2 = _hf_block(k, eta, geo, allT, To, s2[0], s2[1])       # H[(s,b),(t,a)] as (s, b, a)
+            Hr = 0.5 * (h1 + h2.transpose(0, 2, 1))                    # (s, a, b)
+            HY = np.einsum("sab,sbc->ac", Hr, Y)                       # (3a, ncol)
+            for a in range(3):
+                c = 3 * t + a
+                w = row[0, c]
+                if w != 0:
+                    out[r] += w * HY[a]
+    return out

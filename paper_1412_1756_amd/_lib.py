@@ -16,7 +16,7 @@ CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD, CM_FLAG_VERBOSE, CM_FLA
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
            "cm_apply_noalloc",
            "cm_sai_build", "cm_sai_apply", "cm_vdot", "cm_real_currents", "cm_modal_correlation", "cm_dlambda_dk",
-           "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_jd", "cm_export_near", "cm_stats", "cm_set_translation_kernel",
+           "cm_gmres", "cm_eigs", "cm_eigs_xinv", "cm_cmp_build", "cm_cmp_apply", "cm_cmp_export", "cm_jd", "cm_export_near", "cm_stats", "cm_set_translation_kernel",
            "cm_stage_timing",
            "cm_stage_times", "cm_last_error"]
 
@@ -86,6 +86,12 @@ def lib():
     L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, i32, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp,
                         vp]
     L.cm_jd.restype = C.c_int
+    L.cm_cmp_build.argtypes = [vp, i32, vp, vp]
+    L.cm_cmp_build.restype = C.c_int
+    L.cm_cmp_apply.argtypes = [vp, i32, vp, vp, C.c_int, vp]
+    L.cm_cmp_apply.restype = C.c_int
+    L.cm_cmp_export.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64), vp, vp, vp]
+    L.cm_cmp_export.restype = C.c_int
     L.cm_set_translation_kernel.argtypes = [vp, i32]
     L.cm_set_translation_kernel.restype = C.c_int
     L.cm_stage_timing.argtypes = [vp, i32]

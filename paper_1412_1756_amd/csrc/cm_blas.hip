@@ -526,4 +526,25 @@ void blas_to_c128(const float2* x, double2* y, int64_t N, hipStream_t s) {
   hipLaunchKernelGGL(k_to_c128, g1(N), dim3(256), 0, s, x, y, N);
 }
 
+// y = M x, M real CSR, x and y complex double; one row per thread (the
+// Calderon matrices hold a few tens of entries per row)
+__global__ void __launch_bounds__(256) k_csr_real(int64_t rows, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                  const double2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  double ax = 0.0, ay = 0.0;
+  for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+    const double v = val[p];
+    const double2 xv = x[col[p]];
+    ax = fma(v, xv.x, ax);
+    ay = fma(v, xv.y, ay);
+  }
+  y[i] = make_double2(ax, ay);
+}
+
+void blas_csr_real(const CsrD& M, const double2* x, double2* y, hipStream_t s) {
+  if (M.rows > 0) hipLaunchKernelGGL(k_csr_real, g1(M.rows), dim3(256), 0, s, M.rows, M.ptr, M.col, M.val, x, y);
+}
+
 }  // namespace cm

@@ -390,8 +390,28 @@ void cm_default_opts(cm_opts* o) {
   o->k_sampling = 0;
 }
 
+static void free_csr(cm::CsrD& m) {
+  if (m.ptr) (void)hipFree(m.ptr);
+  if (m.col) (void)hipFree(m.col);
+  if (m.val) (void)hipFree(m.val);
+  m = cm::CsrD();
+}
+
+static void destroy_handle(cm_handle* h);
+
+static void free_cmp(cm::CmpD* c) {
+  if (!c) return;
+  destroy_handle(c->ref);
+  free_csr(c->B);
+  free_csr(c->Bt);
+  free_csr(c->G);
+  delete c;
+}
+
 static void destroy_handle(cm_handle* h) {
   if (!h) return;
+  free_cmp(h->cmp);
+  h->cmp = nullptr;
   for (cm_handle* t : h->sub) destroy_handle(t);
   h->sub.clear();
   if (h->xs) (void)hipFree(h->xs);
@@ -462,6 +482,77 @@ cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64
 }
 
 void cm_destroy(cm_handle* h) { destroy_handle(h); }
+
+static void upload_csr(const cm::CsrHost& m, cm::CsrD& d) {
+  d.rows = m.rows;
+  d.nnz = (int64_t)m.col.size();
+  auto chk = [](hipError_t e) {
+    if (e != hipSuccess) throw cm::Error(e == hipErrorOutOfMemory ? CM_E_OOM : CM_E_HIP, "Calderon tables upload");
+  };
+  chk(hipMalloc(&d.ptr, (m.rows + 1) * sizeof(int64_t)));
+  chk(hipMalloc(&d.col, std::max<int64_t>(1, d.nnz) * sizeof(int32_t)));
+  chk(hipMalloc(&d.val, std::max<int64_t>(1, d.nnz) * sizeof(double)));
+  chk(hipMemcpy(d.ptr, m.ptr.data(), (m.rows + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  if (d.nnz) {
+    chk(hipMemcpy(d.col, m.col.data(), d.nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+    chk(hipMemcpy(d.val, m.val.data(), d.nnz * sizeof(double), hipMemcpyHostToDevice));
+  }
+}
+
+cm_status cm_cmp_build(cm_handle* h, int32_t nlv_refined, int64_t* info, void* hip_stream) {
+  g_err.clear();
+  if (!h) return fail(CM_E_BADARG, "null argument");
+  if (nlv_refined != 0 && (nlv_refined < 3 || nlv_refined > 20))
+    return fail(CM_E_BADARG, "nlv_refined must be 0 or in [3, 20]");
+  CM_TRY({
+    std::vector<double> Vr;
+    std::vector<int32_t> Fr;
+    cm::cmp_refine(h->plan, Vr, Fr);
+    cm::Opts op = h->plan.opt;
+    op.nlv = nlv_refined > 0 ? nlv_refined : h->plan.nlv + 1;
+    op.max_cols = 1;
+    op.flags &= ~(uint32_t)(CM_FLAG_DERIV | CM_FLAG_AUTOTUNE | CM_FLAG_VERBOSE | CM_FLAG_HOST_ONLY);
+    if (!h->has_dev) op.flags |= CM_FLAG_HOST_ONLY;
+    std::unique_ptr<cm::CmpD, void (*)(cm::CmpD*)> c(new cm::CmpD(), free_cmp);
+    c->ref = build_handle(Vr.data(), (int64_t)Vr.size() / 3, Fr.data(), (int64_t)Fr.size() / 3, h->plan.k, op,
+                          op.flags, (hipStream_t)hip_stream);
+    c->Nr = c->ref->plan.rwg.N;
+    cm::CsrHost Bt;
+    cm::cmp_tables(h->plan, c->ref->plan, Vr, Fr, c->hB, Bt, c->hG);
+    if (h->has_dev) {
+      upload_csr(c->hB, c->B);
+      upload_csr(Bt, c->Bt);
+      upload_csr(c->hG, c->G);
+    }
+    if (info) {
+      info[0] = c->Nr;
+      info[1] = (int64_t)c->hB.col.size();
+      info[2] = (int64_t)c->hG.col.size();
+      info[3] = c->ref->plan.nnz;
+      info[4] = c->ref->plan.nlv;
+    }
+    free_cmp(h->cmp);
+    h->cmp = c.release();
+    return CM_OK;
+  })
+}
+
+cm_status cm_cmp_export(const cm_handle* h, int32_t which, int64_t* rows, int64_t* nnz, int64_t* ptr, int32_t* col,
+                        double* val) {
+  g_err.clear();
+  if (!h || !rows || !nnz) return fail(CM_E_BADARG, "null argument");
+  if (!h->cmp) return fail(CM_E_NOT_BUILT, "Calderon preconditioner not built");
+  if (which != 0 && which != 1) return fail(CM_E_BADARG, "which must be 0 (B) or 1 (G)");
+  const cm::CsrHost& m = which == 0 ? h->cmp->hB : h->cmp->hG;
+  *rows = m.rows;
+  *nnz = (int64_t)m.col.size();
+  if (ptr && col && val) {
+    std::memcpy(ptr, m.ptr.data(), (m.rows + 1) * sizeof(int64_t));
+    std::memcpy(col, m.col.data(), m.col.size() * sizeof(int32_t));
+    std::memcpy(val, m.val.data(), m.val.size() * sizeof(double));
+  }
+  return CM_OK;
+}
 
 cm_status cm_num_unknowns(const cm_handle* h, int64_t* n) {
   if (!h || !n) return fail(CM_E_BADARG, "null argument");

@@ -220,6 +220,40 @@ struct GmState {
 
 // gather / scatter of up to 64 columns (by index) of an N x ld complex array
 namespace cm {
+// Real sparse matrices of the Calderon preconditioner, CSR by rows (public
+// unknown indices): on the host while built, on the device for the products.
+struct CsrHost {
+  int64_t rows = 0;
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+struct CsrD {
+  int64_t rows = 0, nnz = 0;
+  int64_t* ptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+};
+// y = M x for complex double x, y (one column)
+void blas_csr_real(const CsrD& M, const double2* x, double2* y, hipStream_t s);
+
+// Calderon multiplicative preconditioner of a handle (eqs. (25)-(27)): the
+// MLFMA handle of the barycentric refinement, the BC functions' coefficients
+// B (N x Nr) on its RWG functions and their transpose, and the mixed Gram
+// matrix G (N x N).
+struct CmpD {
+  cm_handle* ref = nullptr;
+  int64_t Nr = 0;
+  CsrD B, Bt, G;          // device copies (empty on a host-only handle)
+  CsrHost hB, hG;         // host copies (cm_cmp_export)
+};
+// the barycentric refinement of a closed mesh (vertices 3 x (nv + N + nt),
+// triangles 3 x 6 nt); CM_E_MESH for an open surface
+void cmp_refine(const Plan& P, std::vector<double>& Vr, std::vector<int32_t>& Fr);
+// B, B^T and G from the primal plan and the refined mesh's plan
+void cmp_tables(const Plan& P, const Plan& Pr, const std::vector<double>& Vr, const std::vector<int32_t>& Fr,
+                CsrHost& B, CsrHost& Bt, CsrHost& G);
+
 struct ColList {
   int n;
   int c[64];
@@ -246,4 +280,5 @@ struct cm_handle {
   void *xs = nullptr, *ys = nullptr;
   hipStream_t ks = nullptr;
   hipEvent_t ks_in = nullptr, ks_out = nullptr;
+  cm::CmpD* cmp = nullptr;   // Calderon preconditioner (cm_cmp_build), null when not built
 };

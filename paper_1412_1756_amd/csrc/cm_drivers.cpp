@@ -11,6 +11,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <memory>
 #include <numeric>
 #include <vector>
 
@@ -93,9 +94,23 @@ class KrylovCtx {
   hipStream_t stream() const { return s_; }
   bool verbose() const { return (P_.opt.flags & CM_FLAG_VERBOSE) != 0; }
 
+  // the Calderon preconditioner that ops 6 and 7 use (cm_cmp_build)
+  void set_cmp(const CmpD* c) { cmp_ = c; }
+
   // y = op(x), op 0 = Z, 1 = R, 2 = X, 5 = tau R + i X (an R and an X
-  // apply); far field in FP64 or FP32
+  // apply), 6 = Z~ G^-1 Z (the Calderon-preconditioned operator of eq. (25)),
+  // 7 = G (the mixed Gram matrix); far field in FP64 or FP32
   void apply(int op, const double2* x, double2* y) {
+    if (op == 6) {
+      if (!c6_.p) c6_.alloc((size_t)N_ * sizeof(double2));
+      apply(0, x, c6_.d());
+      cmp_left(c6_.d(), y);
+      return;
+    }
+    if (op == 7) {
+      blas_csr_real(cmp_->G, x, y, s_);
+      return;
+    }
     if (op == 5) {
       if (!tsh_.p) tsh_.alloc((size_t)N_ * sizeof(double2));
       apply(1, x, tsh_.d());
@@ -114,6 +129,13 @@ class KrylovCtx {
     }
   }
   void precond(const double2* x, double2* y) { dev_sai_apply(d_, P_, x, y, 1, 1, true, sai_part_, s_); }
+
+  // y = Z~ G^-1 u: the Gram solve by GMRES on G to a relative residual of
+  // 1e-12 (a context of its own), then B Z_ref B^T on the refined mesh
+  void cmp_left(const double2* u, double2* y);
+  // y = Z~ x (B Z_ref B^T x)
+  void cmp_ztilde(const double2* x, double2* y);
+  int64_t n_ref_apply = 0, n_gram_iters = 0, n_gram_fail = 0;
 
   // h[k] = V[k]^H w, k < nk <= 1025 (device output), over all CUs
   void multidot(const double2* V, int nk, const double2* w, double2* h) {
@@ -200,6 +222,9 @@ class KrylovCtx {
   int sai_part_;
   double tau_;
   DevBuf t32a_, t32b_, hdev_, part_, tsh_{0};
+  const CmpD* cmp_ = nullptr;
+  std::unique_ptr<KrylovCtx> gk_;            // the Gram solves' context
+  DevBuf c6_{0}, cg_{0}, r1_{0}, r2_{0}, r32a_{0}, r32b_{0};
   static constexpr int kRing = 8;
   double* pin_ = nullptr;
   hipEvent_t ev_[kRing] = {};
@@ -535,6 +560,58 @@ static int orthonormal_columns(const Mat& S, int m, int nc, Mat& Qo) {
   return kept;
 }
 
+void KrylovCtx::cmp_ztilde(const double2* x, double2* y) {
+  if (!cmp_) throw Error(CM_E_NOT_BUILT, "Calderon preconditioner not built");
+  const int64_t Nr = cmp_->Nr;
+  if (!r1_.p) {
+    r1_.alloc((size_t)Nr * sizeof(double2));
+    r2_.alloc((size_t)Nr * sizeof(double2));
+  }
+  blas_csr_real(cmp_->Bt, x, r1_.d(), s_);
+  cm_handle* rh = cmp_->ref;
+  if (far64_) {
+    dev_apply(rh->dev, rh->plan, 0, r1_.p, r2_.p, 1, 1, true, s_);
+  } else {
+    if (!r32a_.p) {
+      r32a_.alloc((size_t)Nr * sizeof(float2));
+      r32b_.alloc((size_t)Nr * sizeof(float2));
+    }
+    blas_to_c64(r1_.d(), (float2*)r32a_.p, Nr, s_);
+    dev_apply(rh->dev, rh->plan, 0, r32a_.p, r32b_.p, 1, 1, false, s_);
+    blas_to_c128((const float2*)r32b_.p, r2_.d(), Nr, s_);
+  }
+  ++n_ref_apply;
+  blas_csr_real(cmp_->B, r2_.d(), y, s_);
+}
+
+void KrylovCtx::cmp_left(const double2* u, double2* y) {
+  if (!cmp_) throw Error(CM_E_NOT_BUILT, "Calderon preconditioner not built");
+  if (!gk_) {
+    gk_.reset(new KrylovCtx(d_, P_, true, s_));
+    gk_->set_cmp(cmp_);
+  }
+  if (!cg_.p) cg_.alloc((size_t)N_ * sizeof(double2));
+  GmresResult g = gmres(*gk_, u, cg_.d(), 60, 600, 1e-12, false, 7);
+  n_gram_iters += g.iters;
+  if (!g.converged) ++n_gram_fail;
+  cmp_ztilde(cg_.d(), y);
+}
+
+// Solve Z x = b (aop 0) or A x = b for the other operators of gmres():
+// precond 0 none, 1 the SAI (right), 2 the Calderon preconditioner (left:
+// Z~ G^-1 Z x = Z~ G^-1 b, eq. (25), aop 0 only; the residual is that of
+// the preconditioned system)
+static GmresResult solve(KrylovCtx& K, const double2* b, double2* x, int m, int maxit, double tol, int precond,
+                         int aop, DevBuf& tmp) {
+  if (precond == 2) {
+    if (aop != 0) throw Error(CM_E_BADARG, "the Calderon preconditioner applies to Z only");
+    if (!tmp.p) tmp.alloc((size_t)K.N() * sizeof(double2));
+    K.cmp_left(b, tmp.d());
+    return gmres(K, tmp.d(), x, m, maxit, tol, false, 6);
+  }
+  return gmres(K, b, x, m, maxit, tol, precond != 0, aop);
+}
+
 // ---------------------------------------------------------------- implicitly restarted Arnoldi
 struct EigsResult {
   int nconv = 0, restarts = 0;
@@ -550,10 +627,10 @@ struct EigsResult {
 // whose eigenvalues mu = 1/(tau + i lambda) spread the modes with |lambda|
 // near or below tau around a circle of diameter 1/tau)
 static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double tol, const double2* v0, int gm_m,
-                       int gm_maxit, double gm_tol, bool precond, double2* Xout, int aop = 0) {
+                       int gm_maxit, double gm_tol, int precond, double2* Xout, int aop = 0) {
   const int64_t N = K.N();
   DevBuf Vb((size_t)ncv * N * sizeof(double2)), Vt((size_t)ncv * N * sizeof(double2)), f(N * sizeof(double2)),
-      ru(N * sizeof(double2));
+      ru(N * sizeof(double2)), pre(0);
   double2* V = Vb.d();
   double2* Vw = Vt.d();
   EigsResult out;
@@ -571,9 +648,9 @@ static EigsResult eigs(KrylovCtx& K, int nev, int ncv, int maxrestart, double to
     for (int j = j0; j < ncv; ++j) {
       // w = Z^-1 R v_j
       K.apply(1, V + (size_t)j * N, ru.d());
-      GmresResult g = gmres(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, precond, aop);
+      GmresResult g = solve(K, ru.d(), f.d(), gm_m, gm_maxit, gm_tol, precond, aop, pre);
       out.gmres_iters += g.iters;
-      if (!g.converged && precond) {
+      if (!g.converged && precond == 1) {
         // the SAI can be nearly singular (e.g. the plate at low frequency,
         // where the column-wise least squares leave Z P with condition
         // number ~1e5): solve this product again without it
@@ -1095,11 +1172,15 @@ extern "C" cm_status cm_gmres(cm_handle* h, const void* b, void* x, int32_t rest
   if (!h || !b || !x) return cm::driver_fail(CM_E_BADARG, "null argument");
   if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
   if (restart < 1 || restart > 1000 || maxit < 1 || !(tol > 0)) return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters");
-  if (precond && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (precond < 0 || precond > 2) return cm::driver_fail(CM_E_BADARG, "precond must be 0, 1 or 2");
+  if (precond == 1 && !h->dev.sai[0].val) return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built");
+  if (precond == 2 && !h->cmp) return cm::driver_fail(CM_E_NOT_BUILT, "Calderon preconditioner not built");
   if (b == x) return cm::driver_fail(CM_E_BADARG, "b and x must not alias");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
-    cm::GmresResult r = cm::gmres(K, (const double2*)b, (double2*)x, restart, maxit, tol, precond != 0);
+    K.set_cmp(h->cmp);
+    cm::DevBuf tmp(0);
+    cm::GmresResult r = cm::solve(K, (const double2*)b, (double2*)x, restart, maxit, tol, precond, 0, tmp);
     if (iters) *iters = r.iters;
     if (relres) *relres = r.relres;
     return r.converged ? CM_OK : CM_E_NOT_CONVERGED;
@@ -1159,13 +1240,18 @@ extern "C" cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t max
   if (gmres_restart < 1 || gmres_restart > 1000 || gmres_maxit < 1 || !(gmres_tol > 0))
     return cm::driver_fail(CM_E_BADARG, "bad GMRES parameters (need 1 <= gmres_restart <= 1000)");
   if (!(tau > 0) || !(tau <= 1e6)) return cm::driver_fail(CM_E_BADARG, "tau must be in (0, 1e6]");
+  if (precond < 0 || precond > 2) return cm::driver_fail(CM_E_BADARG, "precond must be 0, 1 or 2");
   const int slot = cm::sai_slot(tau);
-  if (precond && (!h->dev.sai[slot].val || (slot == 1 && h->dev.sai_tau1 != tau)))
+  if (precond == 1 && (!h->dev.sai[slot].val || (slot == 1 && h->dev.sai_tau1 != tau)))
     return cm::driver_fail(CM_E_NOT_BUILT, "SAI preconditioner not built for this tau");
+  if (precond == 2 && (!h->cmp || tau != 1.0))
+    return cm::driver_fail(h->cmp ? CM_E_BADARG : CM_E_NOT_BUILT,
+                           "the Calderon preconditioner needs cm_cmp_build and tau = 1");
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream, slot, tau);
+    K.set_cmp(h->cmp);
     cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
-                                gmres_tol, precond != 0, (double2*)J, tau == 1.0 ? 0 : 5);
+                                gmres_tol, precond, (double2*)J, tau == 1.0 ? 0 : 5);
     for (int i = 0; i < nev; ++i) {
       // (tau R + i X) J = (tau + i lambda) R J:  lambda = i (tau - 1/mu)
       cm::cplx lam = cm::cplx(0, 1) * (tau - 1.0 / r.mu[i]);
@@ -1205,7 +1291,7 @@ extern "C" cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_
   try {
     cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream, 1);
     cm::EigsResult r = cm::eigs(K, nev, ncv, maxrestart, tol, (const double2*)v0, gmres_restart, gmres_maxit,
-                                gmres_tol, precond != 0, (double2*)J, 2);
+                                gmres_tol, precond != 0 ? 1 : 0, (double2*)J, 2);
     for (int i = 0; i < nev; ++i) {
       // X^-1 R J = mu J  <=>  X J = (1 / mu) R J
       cm::cplx lam = 1.0 / r.mu[i];
@@ -1223,6 +1309,31 @@ extern "C" cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_
       counters[5] = r.inner_failures;
     }
     return (r.nconv >= nev && r.inner_failures == 0) ? CM_OK : CM_E_NOT_CONVERGED;
+  } catch (const cm::Error& e) {
+    return cm::driver_fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return cm::driver_fail(CM_E_OOM, e.what());
+  }
+}
+
+extern "C" cm_status cm_cmp_apply(cm_handle* h, int32_t which, const void* x, void* y, cm_dtype far_dtype,
+                                  void* hip_stream) {
+  if (!h || !x || !y) return cm::driver_fail(CM_E_BADARG, "null argument");
+  if (!h->has_dev) return cm::driver_fail(CM_E_NOT_BUILT, "handle was built host-only");
+  if (!h->cmp) return cm::driver_fail(CM_E_NOT_BUILT, "Calderon preconditioner not built");
+  if (which < 0 || which > 2) return cm::driver_fail(CM_E_BADARG, "which must be 0 (Z~), 1 (G) or 2 (Z~ G^-1 Z)");
+  if (far_dtype != CM_C128 && far_dtype != CM_C64) return cm::driver_fail(CM_E_BADARG, "bad far-field dtype");
+  if (x == y) return cm::driver_fail(CM_E_BADARG, "x and y must not alias");
+  try {
+    cm::KrylovCtx K(h->dev, h->plan, far_dtype == CM_C128, (hipStream_t)hip_stream);
+    K.set_cmp(h->cmp);
+    if (which == 0) K.cmp_ztilde((const double2*)x, (double2*)y);
+    if (which == 1) K.apply(7, (const double2*)x, (double2*)y);
+    if (which == 2) K.apply(6, (const double2*)x, (double2*)y);
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess)
+      return cm::driver_fail(CM_E_HIP, "cm_cmp_apply: stream synchronisation");
+    if (K.n_gram_fail) return cm::driver_fail(CM_E_NOT_CONVERGED, "the Gram solve missed its tolerance");
+    return CM_OK;
   } catch (const cm::Error& e) {
     return cm::driver_fail(e.code, e.what());
   } catch (const std::exception& e) {

@@ -8,6 +8,15 @@ from . import _lib
 from ._lib import CmError, check, lib
 
 
+def _precond_code(precond):
+    """False/None -> 0, True/"sai" -> 1 (the SAI), "cmp" -> 2 (Calderon)."""
+    if isinstance(precond, str):
+        if precond not in ("sai", "cmp"):
+            raise ValueError("precond must be a bool, 'sai' or 'cmp'")
+        return 1 if precond == "sai" else 2
+    return 1 if precond else 0
+
+
 class Operator:
     """MLFMA operator of one mesh at one wavenumber.
 
@@ -287,11 +296,58 @@ class Operator:
                                   self._stream_ptr(stream)))
         return d
 
+    # ------------------------------------------------------------ Calderon preconditioner
+    def cmp_build(self, nlv=0, stream=None):
+        """Build the Calderon preconditioner of eqs. (25)-(27) (closed
+        surfaces): the barycentric refinement, its MLFMA handle (nlv levels,
+        0: one more than this handle's), the Buffa-Christiansen functions and
+        the mixed Gram matrix (cm_cmp_build).  Returns dict(N_refined, B_nnz,
+        G_nnz, near_nnz_refined, nlv_refined)."""
+        info = np.zeros(5, dtype=np.int64)
+        s = None if self.host_only else self._stream_ptr(stream)
+        check(lib().cm_cmp_build(self._h, int(nlv), info.ctypes.data, s))
+        return dict(N_refined=int(info[0]), B_nnz=int(info[1]), G_nnz=int(info[2]), near_nnz_refined=int(info[3]),
+                    nlv_refined=int(info[4]))
+
+    def cmp_export(self, which="G"):
+        """Host copy of a Calderon table as (ptr, col, val) CSR arrays:
+        which="B" (N x N_refined BC coefficients) or "G" (cm_cmp_export)."""
+        if which not in ("B", "G"):
+            raise ValueError("which must be 'B' or 'G'")
+        w = 0 if which == "B" else 1
+        rows, nnz = C.c_int64(), C.c_int64()
+        check(lib().cm_cmp_export(self._h, w, C.byref(rows), C.byref(nnz), None, None, None))
+        ptr = np.zeros(rows.value + 1, dtype=np.int64)
+        col = np.zeros(max(1, nnz.value), dtype=np.int32)
+        val = np.zeros(max(1, nnz.value))
+        check(lib().cm_cmp_export(self._h, w, C.byref(rows), C.byref(nnz), ptr.ctypes.data, col.ctypes.data,
+                                  val.ctypes.data))
+        return ptr, col[:nnz.value], val[:nnz.value]
+
+    def cmp_apply(self, x, which="M", far="fp64", stream=None):
+        """One column through the Calderon preconditioner's matrices:
+        which="Zt" Z~ x, "G" G x, "M" Z~ G^-1 Z x (cm_cmp_apply).  x: CUDA
+        complex128 tensor of N."""
+        import torch
+        codes = {"Zt": 0, "G": 1, "M": 2}
+        if which not in codes:
+            raise ValueError("which must be 'Zt', 'G' or 'M'")
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.complex128 or x.numel() != self.N:
+            raise TypeError("x must be a complex128 CUDA tensor of N entries")
+        x = x.reshape(-1).contiguous()
+        y = torch.empty_like(x)
+        check(lib().cm_cmp_apply(self._h, codes[which], C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                 _lib.CM_C128 if far == "fp64" else _lib.CM_C64, self._stream_ptr(stream)))
+        return y
+
     # ------------------------------------------------------------ Krylov drivers
     def gmres(self, b, restart=50, maxit=500, tol=1e-6, precond=True, far="fp64", stream=None,
               raise_on_fail=False):
-        """Solve Z x = b (b: CUDA complex128 tensor of N).  Returns
-        (x, iterations, final relative residual, converged)."""
+        """Solve Z x = b (b: CUDA complex128 tensor of N).  precond: False,
+        True (the SAI, sai_build first) or "cmp" (the Calderon preconditioner
+        of eq. (25), cmp_build first; the residual is then that of
+        Z~ G^-1 Z x = Z~ G^-1 b).  Returns (x, iterations, final relative
+        residual, converged)."""
         import torch
         if not isinstance(b, torch.Tensor) or not b.is_cuda or b.dtype != torch.complex128 or b.numel() != self.N:
             raise TypeError("b must be a complex128 CUDA tensor of N entries")
@@ -300,7 +356,7 @@ class Operator:
         it = C.c_int32()
         rr = C.c_double()
         st = lib().cm_gmres(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), restart, maxit, tol,
-                            1 if precond else 0, _lib.CM_C128 if far == "fp64" else _lib.CM_C64, C.byref(it),
+                            _precond_code(precond), _lib.CM_C128 if far == "fp64" else _lib.CM_C64, C.byref(it),
                             C.byref(rr), self._stream_ptr(stream))
         if st not in (_lib.CM_OK, _lib.CM_E_NOT_CONVERGED) or (raise_on_fail and st != _lib.CM_OK):
             check(st)
@@ -349,7 +405,8 @@ class Operator:
         first).  precond=None: True for route "Z", False for route "X".
         tau (route "Z"): OP = (tau R + i X)^-1 R, tau = 1 being Z^-1 R; a
         smaller tau separates modes with |lambda| up to about tau (its SAI:
-        sai_build(tau=tau))."""
+        sai_build(tau=tau)).  precond="cmp" (route "Z", tau 1): the inner
+        solves take the Calderon preconditioner (cmp_build first)."""
         import torch
         v0 = self._start_vector(v0)
         lam = np.zeros(2 * nev)
@@ -367,7 +424,7 @@ class Operator:
                                     res.ctypes.data, Jp, C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
         elif route == "Z":
             st = lib().cm_eigs(self._h, nev, ncv, maxrestart, tol, C.c_void_p(v0.data_ptr()), gmres_restart,
-                               gmres_maxit, gmres_tol, 1 if precond else 0, float(tau), fd, lam.ctypes.data,
+                               gmres_maxit, gmres_tol, _precond_code(precond), float(tau), fd, lam.ctypes.data,
                                res.ctypes.data,
                                Jp, C.byref(nconv), cnt.ctypes.data, self._stream_ptr(stream))
         else:

@@ -167,3 +167,15 @@ def test_open_surface_has_no_bc_functions():
     V, F = workloads.plate(4, 4, 0.1)
     with pytest.raises(MeshError):
         cmp.bc_table(V, F)
+
+
+def test_ztilde_rows_equal_dense_rows(ico1):
+    """The row-wise product (used for large meshes) is the dense definition."""
+    V, F, B, Vr, Fr = ico1
+    k = 0.5
+    Zt = cmp.dense_Ztilde(V, F, k, B=B, Vr=Vr, Fr=Fr)
+    X = workloads.cn01_block(B.shape[0], 2, 3)
+    rows = [0, 5, 77, 119]
+    zr = cmp.ztilde_rows(V, F, k, rows, X, B=B, Vr=Vr, Fr=Fr)
+    ref = (Zt @ X)[rows]
+    assert np.abs(zr - ref).max() < 1e-13 * np.abs(ref).max()
