@@ -336,7 +336,9 @@ cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, do
    handle on a closed surface (CM_E_MESH otherwise): builds the barycentric
    refinement of the mesh (each triangle split into six at its edge midpoints
    and centroid), an MLFMA handle on it with nlv_refined levels (0: one more
-   than the handle's) and the handle's other options (one column), the
+   than the handle's), interpolation order interp_p_refined and truncation
+   parameter d0_refined (0: the handle's) and its other options (one column;
+   FP32 products take the near field in FP32, CM_FLAG_NEAR_FP32), the
    Buffa-Christiansen function of every RWG as a combination of the refined
    mesh's RWG functions (the paper names these functions without defining
    them: each carries the RWG's flux l_e from the dual cell of one endpoint
@@ -344,12 +346,16 @@ cm_status cm_eigs(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, do
    triangle of a cell, half of the flux through each half of the dual edge
    and none through the refined edges along the primal edge), and the mixed
    Gram matrix G_ij = <n x f_i, f~_j> (eq. (27)).  Z~ (eq. (26)) is then
-   applied as B Z_ref B^T and G^-1 by GMRES on G.  info (host, may be NULL)
+   applied as B Z_ref B^T and G^-1 by GMRES on G.  Z~ only preconditions
+   (any fixed Z~ leaves the solution of eq. (25) that of Z x = u), so the
+   refined handle may be built coarser and cheaper than the handle itself.
+   info (host, may be NULL)
    receives 5 values: refined unknowns, entries of B, entries of G, near-field
    entries of the refined handle, its levels.  A second call rebuilds.  On a
    host-only handle (CM_FLAG_HOST_ONLY) only the host tables are built
    (cm_cmp_export).  Synchronises. */
-cm_status cm_cmp_build(cm_handle* h, int32_t nlv_refined, int64_t* info, void* hip_stream);
+cm_status cm_cmp_build(cm_handle* h, int32_t nlv_refined, int32_t interp_p_refined, double d0_refined,
+                       int64_t* info, void* hip_stream);
 
 /* Host copy of a Calderon table in CSR by rows (public indices): which = 0
    B (N x N_refined: row i holds the coefficients of the i-th BC function on
@@ -367,7 +373,9 @@ cm_status cm_cmp_export(const cm_handle* h, int32_t which, int64_t* rows, int64_
 /* One product with the Calderon preconditioner's matrices on a single
    column (x, y: device, N complex128, must not alias): which = 0 y = Z~ x,
    1 y = G x, 2 y = Z~ G^-1 Z x (the matrix of eq. (25); the Gram solve to a
-   relative residual of 1e-12, CM_E_NOT_CONVERGED if it misses).  far_dtype
+   relative residual of 1e-12, CM_E_NOT_CONVERGED if it misses; inside
+   cm_gmres and cm_eigs the Gram solves go to 1e-2 of the outer tolerance,
+   within [1e-13, 1e-6]).  far_dtype
    selects the far field of the MLFMA products.  Needs cm_cmp_build.
    Synchronises with hip_stream. */
 cm_status cm_cmp_apply(cm_handle* h, int32_t which, const void* x, void* y, cm_dtype far_dtype, void* hip_stream);

@@ -86,7 +86,7 @@ def lib():
     L.cm_jd.argtypes = [vp, i32, dbl, i32, i32, i32, dbl, i32, i32, i32, vp, C.c_int, vp, vp, vp, C.POINTER(i32), vp,
                         vp]
     L.cm_jd.restype = C.c_int
-    L.cm_cmp_build.argtypes = [vp, i32, vp, vp]
+    L.cm_cmp_build.argtypes = [vp, i32, i32, dbl, vp, vp]
     L.cm_cmp_build.restype = C.c_int
     L.cm_cmp_apply.argtypes = [vp, i32, vp, vp, C.c_int, vp]
     L.cm_cmp_apply.restype = C.c_int

@@ -499,19 +499,25 @@ static void upload_csr(const cm::CsrHost& m, cm::CsrD& d) {
   }
 }
 
-cm_status cm_cmp_build(cm_handle* h, int32_t nlv_refined, int64_t* info, void* hip_stream) {
+cm_status cm_cmp_build(cm_handle* h, int32_t nlv_refined, int32_t interp_p_refined, double d0_refined,
+                       int64_t* info, void* hip_stream) {
   g_err.clear();
   if (!h) return fail(CM_E_BADARG, "null argument");
   if (nlv_refined != 0 && (nlv_refined < 3 || nlv_refined > 20))
     return fail(CM_E_BADARG, "nlv_refined must be 0 or in [3, 20]");
+  if (interp_p_refined < 0 || interp_p_refined > 32 || !(d0_refined >= 0) || d0_refined > 20)
+    return fail(CM_E_BADARG, "interp_p_refined must be in [0, 32] and d0_refined in [0, 20]");
   CM_TRY({
     std::vector<double> Vr;
     std::vector<int32_t> Fr;
     cm::cmp_refine(h->plan, Vr, Fr);
     cm::Opts op = h->plan.opt;
     op.nlv = nlv_refined > 0 ? nlv_refined : h->plan.nlv + 1;
+    if (interp_p_refined > 0) op.p = interp_p_refined;
+    if (d0_refined > 0) op.d0 = d0_refined;
     op.max_cols = 1;
     op.flags &= ~(uint32_t)(CM_FLAG_DERIV | CM_FLAG_AUTOTUNE | CM_FLAG_VERBOSE | CM_FLAG_HOST_ONLY);
+    op.flags |= CM_FLAG_NEAR_FP32;   // FP32 products of Z~ read FP32 near-field values
     if (!h->has_dev) op.flags |= CM_FLAG_HOST_ONLY;
     std::unique_ptr<cm::CmpD, void (*)(cm::CmpD*)> c(new cm::CmpD(), free_cmp);
     c->ref = build_handle(Vr.data(), (int64_t)Vr.size() / 3, Fr.data(), (int64_t)Fr.size() / 3, h->plan.k, op,

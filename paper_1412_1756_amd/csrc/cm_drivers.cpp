@@ -136,6 +136,7 @@ class KrylovCtx {
   // y = Z~ x (B Z_ref B^T x)
   void cmp_ztilde(const double2* x, double2* y);
   int64_t n_ref_apply = 0, n_gram_iters = 0, n_gram_fail = 0;
+  double gram_tol = 1e-12;   // relative residual of the Gram solves
 
   // h[k] = V[k]^H w, k < nk <= 1025 (device output), over all CUs
   void multidot(const double2* V, int nk, const double2* w, double2* h) {
@@ -591,7 +592,7 @@ void KrylovCtx::cmp_left(const double2* u, double2* y) {
     gk_->set_cmp(cmp_);
   }
   if (!cg_.p) cg_.alloc((size_t)N_ * sizeof(double2));
-  GmresResult g = gmres(*gk_, u, cg_.d(), 60, 600, 1e-12, false, 7);
+  GmresResult g = gmres(*gk_, u, cg_.d(), 60, 600, gram_tol, false, 7);
   n_gram_iters += g.iters;
   if (!g.converged) ++n_gram_fail;
   cmp_ztilde(cg_.d(), y);
@@ -606,6 +607,9 @@ static GmresResult solve(KrylovCtx& K, const double2* b, double2* x, int m, int 
   if (precond == 2) {
     if (aop != 0) throw Error(CM_E_BADARG, "the Calderon preconditioner applies to Z only");
     if (!tmp.p) tmp.alloc((size_t)K.N() * sizeof(double2));
+    // Gram solves well below the outer tolerance keep the operator fixed to
+    // within 1e-2 of what GMRES resolves
+    K.gram_tol = std::min(1e-6, std::max(1e-13, 1e-2 * tol));
     K.cmp_left(b, tmp.d());
     return gmres(K, tmp.d(), x, m, maxit, tol, false, 6);
   }

@@ -297,15 +297,16 @@ class Operator:
         return d
 
     # ------------------------------------------------------------ Calderon preconditioner
-    def cmp_build(self, nlv=0, stream=None):
+    def cmp_build(self, nlv=0, interp_p=0, d0=0.0, stream=None):
         """Build the Calderon preconditioner of eqs. (25)-(27) (closed
         surfaces): the barycentric refinement, its MLFMA handle (nlv levels,
-        0: one more than this handle's), the Buffa-Christiansen functions and
-        the mixed Gram matrix (cm_cmp_build).  Returns dict(N_refined, B_nnz,
-        G_nnz, near_nnz_refined, nlv_refined)."""
+        0: one more than this handle's; interp_p and d0, 0: this handle's),
+        the Buffa-Christiansen functions and the mixed Gram matrix
+        (cm_cmp_build).  Returns dict(N_refined, B_nnz, G_nnz,
+        near_nnz_refined, nlv_refined)."""
         info = np.zeros(5, dtype=np.int64)
         s = None if self.host_only else self._stream_ptr(stream)
-        check(lib().cm_cmp_build(self._h, int(nlv), info.ctypes.data, s))
+        check(lib().cm_cmp_build(self._h, int(nlv), int(interp_p), float(d0), info.ctypes.data, s))
         return dict(N_refined=int(info[0]), B_nnz=int(info[1]), G_nnz=int(info[2]), near_nnz_refined=int(info[3]),
                     nlv_refined=int(info[4]))
 
