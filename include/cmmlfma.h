@@ -141,6 +141,11 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
                                   use receiver tiles of 16 boxes (the
                                   default without the autotuner; the kernels
                                   give the same bits)                        */
+#define CM_FLAG_M2L_SINGLE_TILES 1024u /* single-column translations use the
+                                  receiver tiles of 16 boxes instead of the
+                                  receiver-major kernel (one wave per
+                                  receiver and 64 directions); the two give
+                                  the same bits                              */
 #define CM_FLAG_VERBOSE   256u /* the eigen-solvers print one progress line to
                                   stderr per Arnoldi restart (cm_eigs,
                                   cm_eigs_xinv) or converged pair (cm_jd) */

@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(256) k_interp_up_direct(const C2<R>* __restric
 // receivers' lists; each source pattern element is loaded once and applied to
 // every receiver of the tile that lists it (register accumulators).  With
 // STAGE the block's translator rows are staged in LDS first.
-template <typename R, bool STAGE, int QPT, int RT>
+template <typename R, bool STAGE, int QPT, int RT, int PD>
 __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tsrc,
                                              const int32_t* __restrict__ toff, const C2<R>* __restrict__ T,
                                              int n_off, const C2<R>* __restrict__ S, C2<R>* __restrict__ G,
@@ -372,21 +372,31 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
     for (int u = 0; u < QPT; ++u)
 #pragma unroll
       for (int r = 0; r < RT; ++r) a0[u][r] = a1[u][r] = mk<R>(0, 0);
-    // software pipelining: the next source's pattern loads are in flight while
-    // the current one is applied to the tile's receivers
-    // source patterns: a uniform per-box base plus a loop-invariant lane
-    // offset (inactive lanes read direction 0, which is always in range)
+    // software pipelining: the loads of the next PD - 1 sources are in flight
+    // while the current one is applied to the tile's receivers (a ring of PD
+    // register sets, rotated by unrolling, so no copies and no wait on loads
+    // issued in the same step).  Source patterns: a uniform per-box base plus a
+    // loop-invariant 32-bit lane offset in bytes (inactive lanes read
+    // direction 0, which is always in range).
     const int64_t bstride = (int64_t)2 * K * ldp, cstride = (int64_t)K * ldp;
+    const uint32_t cbytes = (uint32_t)K * (uint32_t)ldp * (uint32_t)sizeof(C2<R>);
     int lo[QPT];
+    uint32_t lob[QPT];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) lo[u] = (act[u] ? q[u] * ldp : 0) + (c < nc ? c : 0);
+    for (int u = 0; u < QPT; ++u) {
+      lo[u] = (act[u] ? q[u] * ldp : 0) + (c < nc ? c : 0);
+      lob[u] = (uint32_t)lo[u] * (uint32_t)sizeof(C2<R>);
+    }
     auto load_src = [&](int e, C2<R>(&n0)[QPT], C2<R>(&n1)[QPT]) {
-      const C2<R>* sp = S + tsrc[e] * bstride;
+      const char* sp = reinterpret_cast<const char*>(S + tsrc[e] * bstride);
 #pragma unroll
       for (int u = 0; u < QPT; ++u) {
-        n0[u] = sp[lo[u]];
-        n1[u] = sp[cstride + lo[u]];
+        n0[u] = *reinterpret_cast<const C2<R>*>(sp + lob[u]);
+        n1[u] = *reinterpret_cast<const C2<R>*>(sp + (lob[u] + cbytes));
       }
+      // keep the slots' loads in issue order (the waits for a slot then leave
+      // the younger slots in flight)
+      __builtin_amdgcn_sched_barrier(0);
     };
     auto apply_src = [&](int e, const C2<R>(&s0)[QPT], const C2<R>(&s1)[QPT]) {
       // the translator ids of this pass's receivers for this source: uniform,
@@ -420,17 +430,23 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
         }
       }
     };
-    C2<R> n0[QPT], n1[QPT];
-    if (e0 < e1) load_src(e0, n0, n1);
-    for (int e = e0; e < e1; ++e) {
-      C2<R> s0[QPT], s1[QPT];
+    if (e0 < e1) {
+      C2<R> b0[PD][QPT], b1[PD][QPT];
 #pragma unroll
-      for (int u = 0; u < QPT; ++u) {
-        s0[u] = n0[u];
-        s1[u] = n1[u];
+      for (int d = 0; d < PD; ++d) load_src(min(e0 + d, e1 - 1), b0[d], b1[d]);
+      int e = e0;
+      for (; e + PD <= e1; e += PD) {
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+          apply_src(e + d, b0[d], b1[d]);
+          // refill the slot with the source PD ahead (past the end: the last
+          // source again, never applied)
+          load_src(min(e + d + PD, e1 - 1), b0[d], b1[d]);
+        }
       }
-      if (e + 1 < e1) load_src(e + 1, n0, n1);
-      apply_src(e, s0, s1);
+#pragma unroll
+      for (int d = 0; d < PD; ++d)
+        if (e + d < e1) apply_src(e + d, b0[d], b1[d]);
     }
 #pragma unroll
     for (int u = 0; u < QPT; ++u) {
@@ -454,6 +470,73 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
         }
       }
     }
+  }
+}
+
+// Translation of a single column, receiver-major: one wave per (receiver
+// box, 64 directions), walking the receiver's far list (sorted by source, so
+// each receiver sums its sources in the order of the tile kernel and gives
+// the same bits) in groups of kGP entries whose source-pattern and translator
+// loads are all issued before the group is applied.  Without the tile's
+// register reuse each pair reads its source rows again, but a single
+// column's patterns of a level (tens of MB) stay in L2 and the MALL, and
+// every wave has independent work: the tile kernel has few blocks per level
+// for one column and loads each source of a tile once per block of its
+// receiver split.  Block = 4 waves; consecutive receivers go to the same XCD.
+template <typename R>
+__global__ void __launch_bounds__(256) k_m2l_pairs(const int32_t* __restrict__ fptr,
+                                                   const int32_t* __restrict__ fsrc,
+                                                   const int32_t* __restrict__ foff, const C2<R>* __restrict__ T,
+                                                   const C2<R>* __restrict__ S, C2<R>* __restrict__ G, int nbox,
+                                                   int K, int nqc, int ldp, int accum) {
+  constexpr int kGP = 4;
+  const int per_xcd = gridDim.x / 8;
+  const int lb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int wid = lb * 4 + (int)(threadIdx.x >> 6);
+  const int m = wid / nqc, qc = wid - m * nqc;
+  if (m >= nbox) return;
+  const int q = qc * 64 + (int)(threadIdx.x & 63);
+  const bool act = q < K;
+  const int qq = act ? q : 0;
+  const int64_t bstride = (int64_t)2 * K * ldp;
+  const uint32_t lob = (uint32_t)qq * (uint32_t)ldp * (uint32_t)sizeof(C2<R>);
+  const uint32_t cbytes = (uint32_t)K * (uint32_t)ldp * (uint32_t)sizeof(C2<R>);
+  const uint32_t tob = (uint32_t)qq * (uint32_t)sizeof(C2<R>);
+  C2<R> a0 = mk<R>(0, 0), a1 = mk<R>(0, 0);
+  const int e0 = fptr[m], e1 = fptr[m + 1];
+  auto group = [&](int e, int n) {
+    C2<R> s0[kGP], s1[kGP], t[kGP];
+#pragma unroll
+    for (int i = 0; i < kGP; ++i)
+      if (i < n) {
+        const char* sp = reinterpret_cast<const char*>(S + fsrc[e + i] * bstride);
+        const char* tp = reinterpret_cast<const char*>(T + (int64_t)foff[e + i] * K);
+        s0[i] = *reinterpret_cast<const C2<R>*>(sp + lob);
+        s1[i] = *reinterpret_cast<const C2<R>*>(sp + (lob + cbytes));
+        t[i] = *reinterpret_cast<const C2<R>*>(tp + tob);
+      }
+#pragma unroll
+    for (int i = 0; i < kGP; ++i)
+      if (i < n) {
+        a0 = cfma(a0, t[i], s0[i]);
+        a1 = cfma(a1, t[i], s1[i]);
+      }
+  };
+  int e = e0;
+  for (; e + kGP <= e1; e += kGP) group(e, kGP);
+  if (e < e1) group(e, e1 - e);
+  if (!act) return;
+  C2<R>* gp = G + m * bstride + (int64_t)qq * ldp;
+  C2<R>& g0 = gp[0];
+  C2<R>& g1 = gp[(int64_t)K * ldp];
+  if (accum) {
+    g0.x += a0.x;
+    g0.y += a0.y;
+    g1.x += a1.x;
+    g1.y += a1.y;
+  } else {
+    g0 = a0;
+    g1 = a1;
   }
 }
 
@@ -1264,13 +1347,24 @@ struct Stages {
       if (cw >= 8 && sh2 <= 64 * 1024) {
         // FP32 batched: two directions per thread share the translator ids
         dim3 grid(gx, (Lv.K + 2 * qb - 1) / (2 * qb), (nc + cw - 1) / cw);
-        hipLaunchKernelGGL((k_m2l<R, true, 2, kTile>), grid, dim3(threads), sh2, s, tptr, tsrc, toff, (const CR*)T,
+        hipLaunchKernelGGL((k_m2l<R, true, 2, kTile, 3>), grid, dim3(threads), sh2, s, tptr, tsrc, toff, (const CR*)T,
                            Lv.n_off, S, G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
         return;
       }
     const size_t sh = (size_t)Lv.n_off * qb * sizeof(CR);
     const bool stage = (cw >= 8) && sh <= 64 * 1024;
     dim3 grid(gx, (Lv.K + qb - 1) / qb, (nc + cw - 1) / cw);
+    if (nc == 1 && !(P.opt.flags & CM_FLAG_M2L_SINGLE_TILES)) {
+      const int32_t* fptr = (kind == 1) ? Lv.farR_ptr : Lv.far_ptr;
+      const int32_t* fsrc = (kind == 1) ? Lv.farR_src : Lv.far_src;
+      const int32_t* foff = (kind == 1) ? Lv.farR_off : Lv.far_off;
+      const int nqc = (Lv.K + 63) / 64;
+      const int64_t nw = (int64_t)Lv.nbox * nqc;
+      const unsigned gb = (unsigned)((nw + 31) / 32 * 8);   // 4 waves per block, a multiple of 8 blocks
+      hipLaunchKernelGGL(k_m2l_pairs<R>, dim3(gb), dim3(256), 0, s, fptr, fsrc, foff, (const CR*)T, S, G, Lv.nbox,
+                         Lv.K, nqc, ldp, accum);
+      return;
+    }
     if (nc == 1) {
       // single vector: one wave per block and few blocks per level, so the
       // tile's 16 receivers go to 4 blocks of grid z (8 where the level has
@@ -1278,20 +1372,20 @@ struct Stages {
       // N = 122,880 (same sums in the same order)
       if (Lv.ntile < 32) {
         grid.z *= kTile / 2;
-        hipLaunchKernelGGL((k_m2l<R, false, 1, 2>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T,
+        hipLaunchKernelGGL((k_m2l<R, false, 1, 2, 4>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T,
                            Lv.n_off, S, G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
       } else {
         grid.z *= kTile / 4;
-        hipLaunchKernelGGL((k_m2l<R, false, 1, 4>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T,
+        hipLaunchKernelGGL((k_m2l<R, false, 1, 4, 4>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T,
                            Lv.n_off, S, G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
       }
       return;
     }
     if (stage)
-      hipLaunchKernelGGL((k_m2l<R, true, 1, kTile>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
+      hipLaunchKernelGGL((k_m2l<R, true, 1, kTile, 2>), grid, dim3(threads), sh, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
                          G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
     else
-      hipLaunchKernelGGL((k_m2l<R, false, 1, kTile>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
+      hipLaunchKernelGGL((k_m2l<R, false, 1, kTile, 2>), grid, dim3(threads), 0, s, tptr, tsrc, toff, (const CR*)T, Lv.n_off, S,
                          G, Lv.nbox, Lv.ntile, Lv.K, nc, cw, ldp, accum);
   }
 

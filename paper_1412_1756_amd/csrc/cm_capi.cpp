@@ -252,12 +252,28 @@ void dev_build(Dev& d, const Plan& P, hipStream_t s) {
   std::vector<int32_t*> lists(8 * (lf + 1) + (lf + 1) + 6 * (lf + 1), nullptr);
   for (int l = 2; l <= lf; ++l) {
     const Level& Lv = P.lev[l];
-    lists[8 * l + 0] = upload(d, Lv.far_ptr, s);
-    lists[8 * l + 1] = upload(d, Lv.far_src, s);
-    lists[8 * l + 2] = upload(d, Lv.far_off, s);
-    lists[8 * l + 3] = upload(d, Lv.farR_ptr, s);
-    lists[8 * l + 4] = upload(d, Lv.farR_src, s);
-    lists[8 * l + 5] = upload(d, Lv.farR_off, s);
+    // receiver-major lists for the single-column translation: each
+    // receiver's sources in increasing order with compact translator ids
+    auto sorted_lists = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& src,
+                            const std::vector<int32_t>& off, int slot) {
+      std::vector<int32_t> ss(src.size()), so(off.size());
+      std::vector<std::pair<int32_t, int32_t>> ent;
+      for (int m = 0; m < Lv.nbox; ++m) {
+        ent.clear();
+        for (int e = ptr[m]; e < ptr[m + 1]; ++e) ent.push_back({src[e], Lv.off_compact[off[e]]});
+        std::sort(ent.begin(), ent.end());
+        for (size_t i = 0; i < ent.size(); ++i) {
+          ss[ptr[m] + i] = ent[i].first;
+          so[ptr[m] + i] = ent[i].second;
+        }
+      }
+      lists[8 * l + slot] = upload(d, ptr, s);
+      lists[8 * l + slot + 1] = upload(d, ss, s);
+      lists[8 * l + slot + 2] = upload(d, so, s);
+      chk(hipStreamSynchronize(s), "hipStreamSynchronize");   // ss, so are about to go
+    };
+    sorted_lists(Lv.far_ptr, Lv.far_src, Lv.far_off, 0);
+    sorted_lists(Lv.farR_ptr, Lv.farR_src, Lv.farR_off, 3);
     lists[8 * l + 6] = upload(d, Lv.child_ptr, s);
     lists[8 * l + 7] = upload(d, Lv.parent, s);
     std::vector<int8_t> oc(Lv.nbox);

@@ -33,15 +33,17 @@ class Operator:
     freezes the discretisation across handles at nearby k); verbose=True
     makes the eigen-solvers print a progress line per restart to stderr;
     m2l_tile16=True selects the 16-box-tile FP32 translation kernel
-    (CM_FLAG_M2L_TILE16) instead of the 64-box shared-source one.
-    k may be a
+    (CM_FLAG_M2L_TILE16) instead of the 64-box shared-source one;
+    m2l_single_tiles=True makes single-column translations use the 16-box
+    receiver tiles instead of the receiver-major kernel
+    (CM_FLAG_M2L_SINGLE_TILES; same bits).  k may be a
     sequence of wavenumbers (a sweep; apply's k_index picks one per column).
     """
 
     def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
                  deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, wide_near=False,
                  autotune=False, r_standard=False, k_sampling=None, verbose=False, m2l_tile16=False,
-                 stream=None):
+                 m2l_single_tiles=False, stream=None):
         L = lib()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -62,7 +64,8 @@ class Operator:
                    | (_lib.CM_FLAG_AUTOTUNE if autotune else 0)
                    | (_lib.CM_FLAG_R_STANDARD if r_standard else 0)
                    | (_lib.CM_FLAG_VERBOSE if verbose else 0)
-                   | (_lib.CM_FLAG_M2L_TILE16 if m2l_tile16 else 0))
+                   | (_lib.CM_FLAG_M2L_TILE16 if m2l_tile16 else 0)
+                   | (_lib.CM_FLAG_M2L_SINGLE_TILES if m2l_single_tiles else 0))
         kk = np.atleast_1d(np.asarray(k, dtype=np.float64)).copy()
         h = C.c_void_p()
         s = self._stream_ptr(stream) if not host_only else None

@@ -313,3 +313,25 @@ def test_shared_source_translation_equals_tile16(torch_cuda, sphere2, ncols, ld)
         assert _lib.lib().cm_set_translation_kernel(t16._h, v) == 0
         for o, y in ref.items():
             assert torch.equal(t16.apply(X, o), y), (v, o)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_single_column_translation_equals_tiles(torch_cuda, sphere2, prec):
+    """Single-column translations: the receiver-major kernel (default) and
+    the 16-box receiver tiles (CM_FLAG_M2L_SINGLE_TILES) sum every
+    receiver's sources in increasing source order, so Z, R, X, Z^H and the
+    dual (dZ/dk) pass agree bit for bit, also with the two-box buffer, whose
+    leaf lists start at distance 3."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = sphere2
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    for wide in (False, True):
+        kw = dict(nlv=5, max_cols=4, deriv=True, wide_near=wide, **ACC32)
+        a = Operator(V, F, K0, **kw)
+        b = Operator(V, F, K0, m2l_single_tiles=True, **kw)
+        x = torch.tensor(workloads.cn01(a.N, 0), dtype=dt, device="cuda")
+        for o in ("Z", "R", "X", "ZH", "DZDK"):
+            ya, yb = a.apply(x, o), b.apply(x, o)
+            assert torch.equal(ya, yb), (prec, wide, o, float((ya - yb).abs().max()))
+        del a, b
