@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcmmlfma.so")
-SOURCES = ["cm_plan.cpp", "cm_capi.cpp", "cm_sai.cpp", "cm_drivers.cpp", "cm_cmp.cpp", "cm_fill.hip", "cm_apply.hip", "cm_mfma.hip", "cm_blas.hip", "cm_noalloc.hip",
+SOURCES = ["cm_plan.cpp", "cm_capi.cpp", "cm_drivers.cpp", "cm_cmp.cpp", "cm_fill.hip", "cm_apply.hip", "cm_mfma.hip", "cm_blas.hip", "cm_noalloc.hip", "cm_sai.hip",
            "cm_modes.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

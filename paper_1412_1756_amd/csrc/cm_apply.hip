@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
   extern __shared__ unsigned char smem_raw[];
   const int qb = blockDim.x / cw;                     // direction rows per block pass
   const int qspan = qb * QPT;                         // directions per block
-  C2<R>* Ts = reinterpret_cast<C2<R>*>(smem_raw);    // [n_off][qspan]
+  C2<R>* Ts = reinterpret_cast<C2<R>*>(smem_raw);    // [n_off][qb][QPT]: a thread's QPT translators adjacent
   // XCD-aware order: consecutive tiles (which share most sources) go to the
   // same XCD, i.e. the same L2
   const int per_xcd = gridDim.x / 8;
@@ -358,7 +358,8 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
   }
   if (STAGE) {
     for (int e = threadIdx.x; e < n_off * qspan; e += blockDim.x) {
-      const int f = e / qspan, qq = blockIdx.y * qspan + e % qspan;
+      const int f = e / qspan, r = e % qspan;
+      const int qq = blockIdx.y * qspan + (r % QPT) * qb + r / QPT;
       Ts[e] = (qq < K) ? T[(int64_t)f * K + qq] : mk<R>(0, 0);
     }
     __syncthreads();
@@ -387,8 +388,8 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
       lo[u] = (act[u] ? q[u] * ldp : 0) + (c < nc ? c : 0);
       lob[u] = (uint32_t)lo[u] * (uint32_t)sizeof(C2<R>);
     }
-    auto load_src = [&](int e, C2<R>(&n0)[QPT], C2<R>(&n1)[QPT]) {
-      const char* sp = reinterpret_cast<const char*>(S + tsrc[e] * bstride);
+    auto load_src = [&](int sb, C2<R>(&n0)[QPT], C2<R>(&n1)[QPT]) {
+      const char* sp = reinterpret_cast<const char*>(S + sb * bstride);
 #pragma unroll
       for (int u = 0; u < QPT; ++u) {
         n0[u] = *reinterpret_cast<const C2<R>*>(sp + lob[u]);
@@ -398,10 +399,10 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
       // the younger slots in flight)
       __builtin_amdgcn_sched_barrier(0);
     };
-    auto apply_src = [&](int e, const C2<R>(&s0)[QPT], const C2<R>(&s1)[QPT]) {
-      // the translator ids of this pass's receivers for this source: uniform,
-      // one batch of scalar loads
-      int f[RT];
+    // the translator ids of this pass's receivers for source e: uniform, one
+    // batch of scalar loads (issued for a whole ring step at once, so that
+    // the step waits on the scalar cache once)
+    auto load_ids = [&](int e, int(&f)[RT]) {
       if constexpr (RT % 4 == 0) {
         const int4* of4 = reinterpret_cast<const int4*>(toff + (int64_t)e * kTile + h);
 #pragma unroll
@@ -416,16 +417,31 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
 #pragma unroll
         for (int r = 0; r < RT; ++r) f[r] = toff[(int64_t)e * kTile + h + r];
       }
+    };
+    auto apply_src = [&](const int(&f)[RT], const C2<R>(&s0)[QPT], const C2<R>(&s1)[QPT]) {
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
         if (f[r] >= 0) {
+          C2<R> t[QPT];
+          if constexpr (STAGE) {
+            // staged rows: in range for every thread (ql clamped), zero beyond K
+            const C2<R>* tp = Ts + f[r] * qspan + qlr * QPT;
+            if constexpr (QPT == 2 && sizeof(R) == 4) {
+              const float4 t4 = *reinterpret_cast<const float4*>(tp);
+              t[0] = mk<R>(t4.x, t4.y);
+              t[1] = mk<R>(t4.z, t4.w);
+            } else {
+#pragma unroll
+              for (int u = 0; u < QPT; ++u) t[u] = tp[u];
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < QPT; ++u) t[u] = act[u] ? T[(int64_t)f[r] * K + q[u]] : mk<R>(0, 0);
+          }
 #pragma unroll
           for (int u = 0; u < QPT; ++u) {
-            // staged rows: in range for every thread (ql clamped), zero beyond K
-            const C2<R> t = STAGE ? Ts[f[r] * qspan + u * qb + qlr]
-                                  : (act[u] ? T[(int64_t)f[r] * K + q[u]] : mk<R>(0, 0));
-            a0[u][r] = cfma(a0[u][r], t, s0[u]);
-            a1[u][r] = cfma(a1[u][r], t, s1[u]);
+            a0[u][r] = cfma(a0[u][r], t[u], s0[u]);
+            a1[u][r] = cfma(a1[u][r], t[u], s1[u]);
           }
         }
       }
@@ -433,20 +449,32 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
     if (e0 < e1) {
       C2<R> b0[PD][QPT], b1[PD][QPT];
 #pragma unroll
-      for (int d = 0; d < PD; ++d) load_src(min(e0 + d, e1 - 1), b0[d], b1[d]);
+      for (int d = 0; d < PD; ++d) load_src(tsrc[min(e0 + d, e1 - 1)], b0[d], b1[d]);
       int e = e0;
       for (; e + PD <= e1; e += PD) {
+        // the step's scalar loads together: translator ids of its sources and
+        // the box indices of the sources PD ahead (past the end: the last
+        // source again, loaded but never applied)
+        int f[PD][RT], sb[PD];
 #pragma unroll
         for (int d = 0; d < PD; ++d) {
-          apply_src(e + d, b0[d], b1[d]);
-          // refill the slot with the source PD ahead (past the end: the last
-          // source again, never applied)
-          load_src(min(e + d + PD, e1 - 1), b0[d], b1[d]);
+          load_ids(e + d, f[d]);
+          sb[d] = tsrc[min(e + d + PD, e1 - 1)];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+          apply_src(f[d], b0[d], b1[d]);
+          load_src(sb[d], b0[d], b1[d]);   // refill the slot
         }
       }
 #pragma unroll
       for (int d = 0; d < PD; ++d)
-        if (e + d < e1) apply_src(e + d, b0[d], b1[d]);
+        if (e + d < e1) {
+          int f[RT];
+          load_ids(e + d, f);
+          apply_src(f, b0[d], b1[d]);
+        }
     }
 #pragma unroll
     for (int u = 0; u < QPT; ++u) {
@@ -1121,20 +1149,22 @@ __global__ void __launch_bounds__(256) k_disagg_box(const C2<R>* __restrict__ V,
 }
 
 // ---------------------------------------------------------------- SAI apply
-// y_pub[perm[i]] = sum_t P[i, t] x_int[col[t]]  (FP64 products), one wavefront per row
+// y_pub[perm[i]] = sum_t P[i, t] x_int[col[t]]  (FP64 products)
 template <typename R>
 __global__ void __launch_bounds__(256) k_sai_apply(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const double2* __restrict__ val, const C2<R>* __restrict__ xi,
                                                    const int32_t* __restrict__ perm, C2<R>* __restrict__ y, int64_t ld,
                                                    int64_t N, int nc) {
+  // a group of G = max(8, NC) lanes per row: NC column lanes times G / NC
+  // entry strides (P has about ten entries per row), 64 / G rows per wave
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= N) return;
   const int NC = pow2ceil(nc);
-  const int S = 64 / NC;
-  const int c = lane % NC, s = lane / NC;
+  const int G = NC < 8 ? 8 : NC;
+  const int l = lane % G;
+  const int c = l % NC, s = l / NC, S = G / NC;
+  const int64_t i = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / G) + lane / G;
   double ax = 0.0, ay = 0.0;
-  if (c < nc) {
+  if (i < N && c < nc) {
 #pragma unroll 4
     for (int64_t t = ptr[i] + s; t < ptr[i + 1]; t += S) {
       double2 v = val[t];
@@ -1146,11 +1176,11 @@ __global__ void __launch_bounds__(256) k_sai_apply(const int64_t* __restrict__ p
       ay = fma(v.y, xr, ay);
     }
   }
-  for (int o = NC; o < 64; o <<= 1) {
+  for (int o = NC; o < G; o <<= 1) {
     ax += __shfl_xor(ax, o, 64);
     ay += __shfl_xor(ay, o, 64);
   }
-  if (s == 0 && c < nc) y[(int64_t)perm[i] * ld + c] = mk<R>((R)ax, (R)ay);
+  if (i < N && s == 0 && c < nc) y[(int64_t)perm[i] * ld + c] = mk<R>((R)ax, (R)ay);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1701,7 +1731,9 @@ static void sai_apply_impl(Dev& d, const SaiD& q, const void* x, void* y, int64_
   hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
                      d.perm, (CR*)d.xi, N, 0);
   stage_begin(d, s, 7);
-  hipLaunchKernelGGL(k_sai_apply<R>, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, q.ptr, q.col,
+  const int NC = nc <= 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)(nc - 1)));
+  const int64_t waves = (N + 64 / std::max(8, NC) - 1) / (64 / std::max(8, NC));
+  hipLaunchKernelGGL(k_sai_apply<R>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, q.ptr, q.col,
                      (const double2*)q.val, (const CR*)d.xi, d.perm, (CR*)y, ld, N, nc);
   stage_end(d, s);
   chk(hipGetLastError(), "sai apply launch");
