@@ -77,8 +77,8 @@ __device__ __forceinline__ void stage_theta_tables(const MfD& T, int t0, int NT,
 // blocks, each redoing the phi step).  The phi-step loads of a child are
 // double-buffered in groups of kRG rows and the first group of the next
 // child is loaded during the theta step, which touches only LDS.
-template <int NT, int S2, int kMK, int kRG>
-__global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc, float* __restrict__ Sp,
+template <int NT, int S2, int kMK, int kRG, int kW>
+__global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__ Sc, float* __restrict__ Sp,
                                                    const int32_t* __restrict__ child_ptr,
                                                    const int8_t* __restrict__ octant, MfD T,
                                                    const float2* __restrict__ shiftT, int ntc, int npc, int ntp,
@@ -249,8 +249,8 @@ __global__ void __launch_bounds__(256) k_interp_mf(const float* __restrict__ Sc,
 // values for the child's octant (zg: [chunk][octant][parent theta row][4
 // kmax], in K-step key order) and the theta tables in LDS; the parent-row
 // loads are double-buffered in groups of kRG rows.
-template <int NT, int S2, int kMK, int kRG>
-__global__ void __launch_bounds__(256) k_anterp_mf(const float* __restrict__ Gp, float* __restrict__ Gc,
+template <int NT, int S2, int kMK, int kRG, int kW>
+__global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__ Gp, float* __restrict__ Gc,
                                                    const int32_t* __restrict__ parent,
                                                    const int8_t* __restrict__ octant, MfD T,
                                                    const float2* __restrict__ zg, int ntc, int npc, int ntp,
@@ -862,11 +862,18 @@ static int anterp_wpb(const MfD& T, int ntp) {
 
 // Rows per double-buffered load group: by default from the K-step register
 // budget (two rows up to 8 K steps, one row at 16), or the autotuner's choice
-// for the level (LevelD::rg_ip / rg_at; 4 rows only up to 8 K steps).
+// for the level (LevelD::rg_ip / rg_at; 4 rows only up to 8 K steps).  The
+// code's bit 8 selects the variant compiled for at least three waves per
+// SIMD (register file capped at 168 per lane; 1 or 2 rows only).
+constexpr int kRgW3 = 8;
 static int rg_default(int mk) { return mk <= 8 ? 2 : 1; }
-static bool rg_valid(int mk, int rg) { return rg == 1 || rg == 2 || (rg == 4 && mk <= 8); }
+static bool rg_valid(int mk, int rg) {
+  const int r = rg & ~kRgW3;
+  if (rg & kRgW3) return r == 1 || r == 2;
+  return r == 1 || r == 2 || (r == 4 && mk <= 8);
+}
 
-template <int NT, int S2, int MK, int RG>
+template <int NT, int S2, int MK, int RG, int W>
 static void launch_interp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
                              int ldp, int accum, const void* shiftT, hipStream_t s) {
   const MfD& T = Lp.mip;
@@ -874,8 +881,8 @@ static void launch_interp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, c
   const int ntiles = nc / 4;   // 2 components x nc/8
   const int wpb = interp_wpb(T, Lc.nt);
   const size_t sh = interp_lds(T, Lc.nt, wpb);
-  lds_limit((const void*)k_interp_mf<NT, S2, MK, RG>, sh);
-  hipLaunchKernelGGL((k_interp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
+  lds_limit((const void*)k_interp_mf<NT, S2, MK, RG, W>, sh);
+  hipLaunchKernelGGL((k_interp_mf<NT, S2, MK, RG, W>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
                      sh, s,
                      (const float*)Sc,
                      (float*)Sp, Lp.child_ptr, Lc.octant, T, (const float2*)shiftT, Lc.nt, Lc.np, Lp.nt, Lp.np,
@@ -886,12 +893,14 @@ template <int NT, int S2, int MK>
 static void launch_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
                           int ldp, int accum, const void* shiftT, int rg, hipStream_t s) {
   if constexpr (MK <= 8)
-    if (rg == 4) return launch_interp_rg<NT, S2, MK, 4>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
-  if (rg == 1) return launch_interp_rg<NT, S2, MK, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
-  launch_interp_rg<NT, S2, MK, 2>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+    if (rg == 4) return launch_interp_rg<NT, S2, MK, 4, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+  if (rg == (1 | kRgW3)) return launch_interp_rg<NT, S2, MK, 1, 3>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+  if (rg == (2 | kRgW3)) return launch_interp_rg<NT, S2, MK, 2, 3>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+  if (rg == 1) return launch_interp_rg<NT, S2, MK, 1, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+  launch_interp_rg<NT, S2, MK, 2, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
 }
 
-template <int NT, int S2, int MK, int RG>
+template <int NT, int S2, int MK, int RG, int W>
 static void launch_anterp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
                              int ldp, int add, const void* zg, hipStream_t s) {
   const MfD& T = Lp.mat;
@@ -899,8 +908,8 @@ static void launch_anterp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, c
   const int ntiles = nc / 4;
   const int wpb = anterp_wpb(T, Lp.nt);
   const size_t sh = anterp_lds(T, Lp.nt, wpb);
-  lds_limit((const void*)k_anterp_mf<NT, S2, MK, RG>, sh);
-  hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
+  lds_limit((const void*)k_anterp_mf<NT, S2, MK, RG, W>, sh);
+  hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG, W>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
                      sh, s,
                      (const float*)Gp,
                      (float*)Gc, Lc.parent, Lc.octant, T, (const float2*)zg, Lc.nt, Lc.np, Lp.nt, Lp.np, Lc.nbox, nc,
@@ -911,9 +920,11 @@ template <int NT, int S2, int MK>
 static void launch_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
                           int ldp, int add, const void* zg, int rg, hipStream_t s) {
   if constexpr (MK <= 8)
-    if (rg == 4) return launch_anterp_rg<NT, S2, MK, 4>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
-  if (rg == 1) return launch_anterp_rg<NT, S2, MK, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
-  launch_anterp_rg<NT, S2, MK, 2>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+    if (rg == 4) return launch_anterp_rg<NT, S2, MK, 4, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+  if (rg == (1 | kRgW3)) return launch_anterp_rg<NT, S2, MK, 1, 3>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+  if (rg == (2 | kRgW3)) return launch_anterp_rg<NT, S2, MK, 2, 3>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+  if (rg == 1) return launch_anterp_rg<NT, S2, MK, 1, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+  launch_anterp_rg<NT, S2, MK, 2, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
 }
 
 #define CM_MF_CASES(X)                                                    \
@@ -1024,7 +1035,7 @@ std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, c
         }
         if (cur.ok) {
           const int mk = mk_of(cur);
-          for (int rg : {1, 2, 4}) {
+          for (int rg : {1, 2, 4, 1 | kRgW3, 2 | kRgW3}) {
             if (!rg_valid(mk, rg)) continue;
             rgsel = rg;
             const float ms = kind ? time_it([&] {
@@ -1065,7 +1076,8 @@ std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, c
       }
       rgsel = best_rg;
       js << (first ? "" : ", ") << "{\"stage\": \"" << (kind ? "anterp_l" : "interp_l") << (kind ? l + 1 : l)
-         << "\", \"half_slots\": " << best_s2 << ", \"row_group\": " << best_rg << ", \"ms\": " << best
+         << "\", \"half_slots\": " << best_s2 << ", \"row_group\": " << (best_rg & ~kRgW3)
+         << ", \"min_waves\": " << ((best_rg & kRgW3) ? 3 : 1) << ", \"ms\": " << best
          << ", \"default_ms\": " << base << "}";
       first = false;
     }
