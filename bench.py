@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the 8-wavenumber sweep measurement")
     ap.add_argument("--no-d0-3", action="store_true", help="skip the 3-digit truncation measurement")
     ap.add_argument("--no-sai", action="store_true", help="skip the SAI build and apply measurement")
+    ap.add_argument("--no-cmp", action="store_true",
+                    help="skip the Calderon-against-SAI inner iteration count (needs the SAI leg)")
     ap.add_argument("--no-track", action="store_true",
                     help="skip the plate frequency sweep with mode tracking")
     ap.add_argument("--no-r", action="store_true",
@@ -124,6 +126,35 @@ def measured_traffic(stage, path_tag, cfg):
     if h.hexdigest() != rec["source_sha256"]:
         return None
     return rec["read_bytes"] + rec["write_bytes"]
+
+
+def inner_solves(op):
+    """GMRES iterations per Arnoldi step (nii) of the characteristic-mode
+    solve on this handle: IRA on Z^-1 R (eq. (24)) for 10 modes, 30 Arnoldi
+    steps, inner GMRES(200) to 1e-3 (the paper's tolerance), FP64 far field,
+    with no preconditioner, with the SAI (built by the caller) and with the
+    Calderon preconditioner of eqs. (25)-(27) (refined handle one level
+    deeper, p 6, d0 3: it only preconditions)."""
+    import torch
+    import workloads
+    v0 = torch.tensor(workloads.cn01(op.N, 3), dtype=torch.complex128, device="cuda")
+    res = {"nev": 10, "arnoldi_steps": 30, "gmres_tol": 1e-3, "far": "fp64"}
+    t0 = time.perf_counter()
+    info = op.cmp_build(nlv=op.stats()["nlv"] + 1, interp_p=6, d0=3.0)
+    torch.cuda.synchronize()
+    res["cmp_build_s"] = time.perf_counter() - t0
+    res["cmp_refined_unknowns"] = info["N_refined"]
+    for name, pc in (("none", False), ("sai", True), ("cmp", "cmp")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.eigs(10, 30, v0, tol=1e-6, maxrestart=0, gmres_restart=200, gmres_maxit=2000, gmres_tol=1e-3,
+                    far="fp64", precond=pc, vectors=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"gmres_per_arnoldi_step": r["gmres_iters"] / max(1, r["n_op"]), "seconds": dt,
+                     "ms_per_gmres_iteration": dt * 1e3 / max(1, r["gmres_iters"]),
+                     "inner_failures": r["inner_failures"]}
+    return res
 
 
 def _oracle_rows_times_x(args):
@@ -518,6 +549,8 @@ def main():
         out["sai_apply"] = {"nnz": nnz_p, "ms": ms_sai, "alg_bytes": sai_bytes,
                             "GBps": sai_bytes / (ms_sai * 1e-3) / 1e9, "frac_of_hbm_peak": sai_bytes / (ms_sai * 1e-3) / HBM_PEAK,
                             "build_s": t_sai, "thresholds": [0.01, 0.014, 0.18]}
+        if not a.no_cmp:
+            out["inner_solves_sai_vs_cmp"] = inner_solves(op64)
     if not a.no_d0_3:
         # the workload's named truncation (3 digits, eq. (30)) on the same batch: faster, and
         # past the FP32 error bound on this tree (stated, not the headline)

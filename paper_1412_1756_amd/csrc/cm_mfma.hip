@@ -442,16 +442,18 @@ __global__ void __launch_bounds__(256) k_aggregate_mf(const float2* __restrict__
 // far-field part of every unknown of a box), optionally conjugated, written
 // at perm[i] (internal position i without perm).  One block per leaf box: its
 // four waves split the 2K rows, each accumulating all the box's unknowns (MTU
-// tiles of 16) times NTL column tiles on the matrix cores; the partial sums
-// meet in LDS.
+// tiles of 16) times NTL column tiles on the matrix cores in one pass over
+// the box's leaf patterns; the partial sums meet in LDS, two column tiles at
+// a time (so the reduction buffer stays at 4 waves x MTU x 2 x 4 floats per
+// lane).
 template <int MTU, int NTL>
 __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V, const float* __restrict__ G, int ldp,
                                                    const float* __restrict__ qwc, const float* __restrict__ yi,
                                                    const int32_t* __restrict__ box_start,
                                                    const int32_t* __restrict__ perm, int K, int nc,
                                                    float* __restrict__ y, int64_t ld, int conj_out) {
-  constexpr int NV = MTU * NTL * 4;   // accumulator floats per lane
-  extern __shared__ float red[];      // [4 waves][NV][64]
+  constexpr int NR = MTU * 2 * 4;     // floats per lane of one reduction round (two column tiles)
+  extern __shared__ float red[];      // [4 waves][NR][64]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
   const int box = blockIdx.x;
@@ -493,24 +495,29 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
         }
       }
     }
-    __syncthreads();   // the previous column group's reads of red are done
 #pragma unroll
-    for (int mt = 0; mt < MTU; ++mt)
+    for (int np = 0; np < NTL; np += 2) {
+      __syncthreads();   // the previous round's reads of red are done
 #pragma unroll
-      for (int nt = 0; nt < NTL; ++nt)
+      for (int mt = 0; mt < MTU; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) red[(w * NV + (mt * NTL + nt) * 4 + j) * 64 + lane] = acc[mt][nt][j];
-    __syncthreads();
-    for (int e = threadIdx.x; e < NV * 64; e += 256) {
-      const int v = e >> 6, l = e & 63;
-      const int j = v & 3, nt = (v >> 2) % NTL, mt = (v >> 2) / NTL;
-      const int i = i0 + 16 * mt + 4 * (l >> 4) + j;
-      const int colf = 16 * (nt0 + nt) + (l & 15);
-      if (i >= i1 || nt0 + nt >= ntiles) continue;
-      float sum = red[e] + red[NV * 64 + e] + red[2 * NV * 64 + e] + red[3 * NV * 64 + e];
-      sum += yi[(int64_t)i * 2 * nc + colf];
-      if (conj_out && (colf & 1)) sum = -sum;
-      y[(int64_t)(perm ? perm[i] : i) * 2 * ld + colf] = sum;
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            red[(w * NR + (mt * 2 + h) * 4 + j) * 64 + lane] = (np + h < NTL) ? acc[mt][np + h][j] : 0.f;
+      __syncthreads();
+      for (int e = threadIdx.x; e < NR * 64; e += 256) {
+        const int v = e >> 6, l = e & 63;
+        const int j = v & 3, h = (v >> 2) & 1, mt = (v >> 2) >> 1;
+        const int nt = np + h;
+        const int i = i0 + 16 * mt + 4 * (l >> 4) + j;
+        const int colf = 16 * (nt0 + nt) + (l & 15);
+        if (i >= i1 || nt >= NTL || nt0 + nt >= ntiles) continue;
+        float sum = red[e] + red[NR * 64 + e] + red[2 * NR * 64 + e] + red[3 * NR * 64 + e];
+        sum += yi[(int64_t)i * 2 * nc + colf];
+        if (conj_out && (colf & 1)) sum = -sum;
+        y[(int64_t)(perm ? perm[i] : i) * 2 * ld + colf] = sum;
+      }
     }
   }
 }
@@ -531,11 +538,12 @@ bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const 
                int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
                hipStream_t s) {
   if (nc % 8 != 0 || max_box > 64) return false;
-  // two column tiles per pass: the LDS reduction buffer (4 waves x MTU x
-  // NTL x 4 floats per lane) then leaves room for four blocks per CU
-  constexpr int NTL = 2;
+  // four column tiles per pass over the leaf patterns (each read once for
+  // 32 columns), reduced two tiles at a time: the LDS buffer (4 waves x MTU
+  // x 2 x 4 floats per lane) leaves room for four blocks per CU
+  constexpr int NTL = 4;
 #define CM_DIS(MTU)                                                                                            \
-  hipLaunchKernelGGL((k_disagg_mf<MTU, NTL>), dim3(nbox), dim3(256), (size_t)4 * MTU * NTL * 4 * 64 * 4, s,   \
+  hipLaunchKernelGGL((k_disagg_mf<MTU, NTL>), dim3(nbox), dim3(256), (size_t)4 * MTU * 2 * 4 * 64 * 4, s,     \
                      (const float2*)V, (const float*)G, ldp, qwc, (const float*)yi, box_start, perm, K, nc,   \
                      (float*)y, ld, conj)
   if (max_box <= 16)
