@@ -73,6 +73,10 @@ class Operator:
                          C.byref(h))
         check(st)
         self._h = h
+        self._dev_index = None
+        if not host_only:
+            import torch
+            self._dev_index = torch.cuda.current_device()   # the device the handle's tables live on
         self.ks = [float(v) for v in kk]   # the sweep's wavenumbers (k_index selects one per column)
         self.k = self.ks[0]
         self.host_only = host_only
@@ -143,6 +147,10 @@ class Operator:
         import torch
         return torch.device("cuda", torch.cuda.current_device())
 
+    def _check_device(self, t):
+        if self._dev_index is not None and t.device.index != self._dev_index:
+            raise ValueError(f"tensor on {t.device}, operator built on cuda:{self._dev_index}")
+
     def _vec_args(self, x, out):
         """x as a row-major (N, ncols) view with unit column stride, and an
         output of the same dtype, shape, device and row stride."""
@@ -157,6 +165,7 @@ class Operator:
             raise ValueError("x must have shape (N,) or (N, ncols)")
         if X.shape[0] != self.N:
             raise ValueError(f"x has {X.shape[0]} rows, operator has N={self.N}")
+        self._check_device(X)
         if X.stride(1) != 1 or X.stride(0) < X.shape[1]:
             X = X.contiguous()
         if out is None:
@@ -187,6 +196,7 @@ class Operator:
             raise TypeError("v0 must be complex128")
         if v0.numel() != self.N:
             raise ValueError(f"v0 has {v0.numel()} entries, operator has N={self.N}")
+        self._check_device(v0)
         return v0.reshape(-1).contiguous()
 
     @staticmethod
