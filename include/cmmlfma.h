@@ -393,9 +393,9 @@ cm_status cm_cmp_apply(cm_handle* h, int32_t which, const void* x, void* y, cm_d
    GMRES solves with X, right-preconditioned when precond != 0 by the SAI of
    X_near (cm_sai_build with tau = 0; the paper notes that no efficient
    preconditioner for X is documented: this one is the library's own).  The
-   cos-kernel expansion of X degrades on boxes small against the wavelength,
-   so this route suits trees whose leaves are not far below 0.25 wavelength.
-   Synchronises. */
+   far field of X uses the imaginary part of Z's translator, so X x is as
+   accurate as Z x on the same tree (the two-box buffer, CM_FLAG_WIDE_NEAR,
+   where leaf boxes are small against the wavelength).  Synchronises. */
 cm_status cm_eigs_xinv(cm_handle* h, int32_t nev, int32_t ncv, int32_t maxrestart, double tol, const void* v0,
                        int32_t gmres_restart, int32_t gmres_maxit, double gmres_tol, int32_t precond,
                        cm_dtype far_dtype, double* lambda, double* ritz_resid, void* J, int32_t* nconv,
