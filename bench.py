@@ -192,17 +192,20 @@ def hbm_copy_rate(dev):
     return {"GBps": gbs, "frac_of_peak": gbs * 1e9 / HBM_PEAK, "kernel": "device copy 2 GiB (torch copy_)"}
 
 
-def sweep_rate(V, F, k0, ncols, steps, d0, p):
+def sweep_rate(V, F, k0, ncols, steps, d0, p, shared=True):
     """The wavenumber-sweep workload: one handle at 8 wavenumbers 0.9 k0 ..
     1.1 k0 (a plan, tables and near field per wavenumber), a block of ncols
     columns with column j at wavenumber j mod 8, FP32 far field, autotuned;
-    column-matvecs/s over `steps` applies between HIP events."""
+    column-matvecs/s over `steps` applies between HIP events.  shared: the
+    one-pass route (CM_FLAG_SWEEP_SHARED: sampling at 1.1 k0, slots of four
+    columns per wavenumber, one tree pass), else one batched apply per
+    wavenumber on its own stream."""
     import torch
     import workloads
     from paper_1412_1756_amd import Operator
     ks = list(np.linspace(0.9, 1.1, 8) * k0)
     t0 = time.perf_counter()
-    sw = Operator(V, F, ks, nlv=6, d0=d0, interp_p=p, max_cols=ncols, autotune=True)
+    sw = Operator(V, F, ks, nlv=6, d0=d0, interp_p=p, max_cols=ncols, autotune=True, sweep_shared=shared)
     t_build = time.perf_counter() - t0
     X = torch.tensor(workloads.cn01_block(sw.N, ncols, 100), dtype=torch.complex64, device="cuda")
     Y = torch.empty_like(X)
@@ -217,11 +220,23 @@ def sweep_rate(V, F, k0, ncols, steps, d0, p):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    out = {"workload": "sphere_r4_n122880, 8 wavenumbers 0.9-1.1 k0, column j at j mod 8", "ncols": ncols,
+           "route": "one pass" if shared else "per wavenumber", "ms_per_apply": ms,
+           "column_matvecs_per_s": ncols * 1000.0 / ms, "setup_s": t_build, "d0": d0, "interp_p": p}
+    if shared:
+        st = sw.stats()
+        out["one_pass_applies"] = st["sweep_one_pass_calls"]
+        out["L_per_level"] = {lv["l"]: lv["L"] for lv in st["levels"] if lv["l"] >= 2}
+        # one stage-timed pass (kernels one at a time), ms per apply per stage
+        sw.stage_timing(True)
+        for _ in range(3):
+            sw.apply(X, out=Y, k_index=kidx)
+        torch.cuda.synchronize()
+        out["stage_ms"] = {k_: v["ms"] / 3 for k_, v in sw.stage_times().items()}
+        sw.stage_timing(False)
     del sw
     torch.cuda.empty_cache()
-    return {"workload": "sphere_r4_n122880, 8 wavenumbers 0.9-1.1 k0, column j at j mod 8", "ncols": ncols,
-            "ms_per_apply": ms, "column_matvecs_per_s": ncols * 1000.0 / ms, "setup_s": t_build,
-            "d0": d0, "interp_p": p}
+    return out
 
 
 def eigs_small(no_cpu):
@@ -571,6 +586,7 @@ def main():
         del op64
         torch.cuda.empty_cache()
         out["sweep_8k"] = sweep_rate(V, F, k, a.ncols, max(3, a.steps // 2), a.d0, a.p)
+        out["sweep_8k_per_wavenumber"] = sweep_rate(V, F, k, a.ncols, max(3, a.steps // 2), a.d0, a.p, shared=False)
     if not a.no_eigs:
         out["eigenmodes"] = eigs_small(a.no_cpu)
     if not a.no_track:

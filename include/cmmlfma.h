@@ -146,6 +146,20 @@ typedef enum { CM_C64 = 0, CM_C128 = 1 } cm_dtype;
                                   receiver-major kernel (one wave per
                                   receiver and 64 directions); the two give
                                   the same bits                              */
+#define CM_FLAG_SWEEP_SHARED 2048u /* wavenumber sweeps (n_k > 1): every
+                                  wavenumber's plan takes its truncation and
+                                  angular sampling at the largest wavenumber
+                                  (or k_sampling when set), and FP32 applies
+                                  of Z and Z^H whose columns span several
+                                  wavenumbers run as one pass: the columns
+                                  in slots of four per wavenumber, the near
+                                  field, aggregation and disaggregation per
+                                  slot with that wavenumber's tables, and the
+                                  interpolation, translations and
+                                  anterpolation once over all columns with
+                                  per-slot translators and shift phases (at
+                                  most 16 slots; other ops, FP64 or wider
+                                  batches take the per-wavenumber route) */
 #define CM_FLAG_VERBOSE   256u /* the eigen-solvers print one progress line to
                                   stderr per Arnoldi restart (cm_eigs,
                                   cm_eigs_xinv) or converged pair (cm_jd) */
@@ -202,7 +216,10 @@ cm_status cm_rwg_table(const cm_handle* h, int32_t* edge_v, int32_t* tri_pm);
    array, column j being applied at k[k_index[j]] (columns sharing a
    wavenumber are gathered into one batched apply, padded with zero columns
    to a multiple of 8 where max_cols allows, so that it takes the
-   matrix-core kernels; a batch at a single wavenumber runs in place).
+   matrix-core kernels; a batch at a single wavenumber runs in place; with
+   CM_FLAG_SWEEP_SHARED an FP32 Z or Z^H batch at several wavenumbers runs as
+   one pass over slots of four columns per wavenumber, padded with zero
+   columns, when 4 x slots <= max_cols and slots <= 16).
    Asynchronous on hip_stream; CM_E_BADARG for an index outside [0, n_k). */
 cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, int32_t ncols,
                    const int32_t* k_index, cm_dtype dt, void* hip_stream);

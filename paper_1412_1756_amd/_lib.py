@@ -12,7 +12,7 @@ OPS = {"Z": 0, "R": 1, "X": 2, "ZH": 3, "DZDK": 4}
 CM_C64, CM_C128 = 0, 1
 CM_FLAG_HOST_ONLY, CM_FLAG_DERIV, CM_FLAG_CHECK, CM_FLAG_NO_MATRIX_CORES, CM_FLAG_NEAR_FP32 = 1, 2, 4, 8, 16
 CM_FLAG_WIDE_NEAR, CM_FLAG_AUTOTUNE, CM_FLAG_R_STANDARD, CM_FLAG_VERBOSE, CM_FLAG_M2L_TILE16 = 32, 64, 128, 256, 512
-CM_FLAG_M2L_SINGLE_TILES = 1024
+CM_FLAG_M2L_SINGLE_TILES, CM_FLAG_SWEEP_SHARED = 1024, 2048
 
 EXPORTS = ["cm_default_opts", "cm_create", "cm_destroy", "cm_num_unknowns", "cm_rwg_table", "cm_apply",
            "cm_apply_noalloc",

@@ -59,17 +59,21 @@ __device__ __forceinline__ int pow2ceil(int n) {
 }
 
 // ---------------------------------------------------------------- permutation
-// x (public order, row stride ld) -> xi (internal order, nc contiguous)
+// x (public order, row stride ld) -> xi (internal order, row stride ldo >=
+// nc; columns nc .. ldo-1 are set to zero)
 template <typename R>
 __global__ void __launch_bounds__(256) k_permute_in(const C2<R>* __restrict__ x, int64_t ld, int nc,
                                                     const int32_t* __restrict__ perm, C2<R>* __restrict__ xi,
-                                                    int64_t N, int conj_in) {
+                                                    int64_t N, int conj_in, int ldo) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= N * nc) return;
-  int64_t i = g / nc;
-  int c = (int)(g % nc);
-  C2<R> v = x[(int64_t)perm[i] * ld + c];
-  if (conj_in) v.y = -v.y;
+  if (g >= N * ldo) return;
+  int64_t i = g / ldo;
+  int c = (int)(g % ldo);
+  C2<R> v = mk<R>(0, 0);
+  if (c < nc) {
+    v = x[(int64_t)perm[i] * ld + c];
+    if (conj_in) v.y = -v.y;
+  }
   xi[g] = v;
 }
 
@@ -565,6 +569,146 @@ __global__ void __launch_bounds__(256) k_m2l_pairs(const int32_t* __restrict__ f
   } else {
     g0 = a0;
     g1 = a1;
+  }
+}
+
+// Translation of a wavenumber-sweep batch (FP32): the columns come in slots
+// of four, slot j at wavenumber sw.k[j], and the translators of all nk
+// wavenumbers are interleaved, T[(f K + q) nk + k].  Thread = (direction,
+// slot): the slot's four columns of both components in registers, so one
+// translator load (L1/L2) serves eight complex products.  Block = (tile of
+// kTile receivers, chunk of 256 / sw.n directions, group of RT of the tile's
+// receivers).  The tile's source list is walked as in k_m2l: source loads in
+// a ring of PD register sets, translator ids by scalar loads, and the
+// translators of a ring step's listed pairs issued together before the step
+// is applied; each receiver sums its sources in increasing source order.
+__device__ __forceinline__ float4 cfma2(float4 a, float2 t, float4 v) {
+  a.x = fmaf(t.x, v.x, a.x);
+  a.x = fmaf(-t.y, v.y, a.x);
+  a.y = fmaf(t.x, v.y, a.y);
+  a.y = fmaf(t.y, v.x, a.y);
+  a.z = fmaf(t.x, v.z, a.z);
+  a.z = fmaf(-t.y, v.w, a.z);
+  a.w = fmaf(t.x, v.w, a.w);
+  a.w = fmaf(t.y, v.z, a.w);
+  return a;
+}
+
+template <int RT, int PD>
+__global__ void __launch_bounds__(256) k_m2l_slots(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tsrc,
+                                                   const int32_t* __restrict__ toff, const float2* __restrict__ T,
+                                                   int nk, SweepSlots sw, const float2* __restrict__ S,
+                                                   float2* __restrict__ G, int nbox, int ntile, int K, int ldp,
+                                                   int accum) {
+  const int per_xcd = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (tile >= ntile) return;
+  const int ns = sw.n;
+  const int qb = (int)blockDim.x / ns;
+  const int slot = (int)threadIdx.x % ns, ql = (int)threadIdx.x / ns;
+  const int q = (int)blockIdx.y * qb + ql;
+  const bool act = ql < qb && q < K;
+  const int qq = act ? q : 0;   // inactive lanes read direction 0 (always in range)
+  const int h = (int)blockIdx.z * RT;
+  const float2* Tq = T + (int64_t)qq * nk + sw.k[slot];
+  const int64_t fstride = (int64_t)K * nk;
+  const int64_t bstride = (int64_t)2 * K * ldp;
+  const uint32_t lob = ((uint32_t)qq * (uint32_t)ldp + 4u * (uint32_t)slot) * 8u;   // bytes into a box
+  const uint32_t cbytes = (uint32_t)K * (uint32_t)ldp * 8u;                          // component plane
+  float4 acc[RT][2][2];   // [receiver][component][column pair]
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[r][c][0] = acc[r][c][1] = float4{0.f, 0.f, 0.f, 0.f};
+  auto load_src = [&](int sb, float4(&v)[2][2]) {
+    const char* sp = reinterpret_cast<const char*>(S + sb * bstride);
+    v[0][0] = *reinterpret_cast<const float4*>(sp + lob);
+    v[0][1] = *reinterpret_cast<const float4*>(sp + (lob + 16u));
+    v[1][0] = *reinterpret_cast<const float4*>(sp + (lob + cbytes));
+    v[1][1] = *reinterpret_cast<const float4*>(sp + (lob + cbytes + 16u));
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto load_ids = [&](int e, int(&f)[RT]) {
+    const int4* of4 = reinterpret_cast<const int4*>(toff + (int64_t)e * kTile + h);
+#pragma unroll
+    for (int r4 = 0; r4 < RT / 4; ++r4) {
+      const int4 v = of4[r4];
+      f[4 * r4 + 0] = v.x;
+      f[4 * r4 + 1] = v.y;
+      f[4 * r4 + 2] = v.z;
+      f[4 * r4 + 3] = v.w;
+    }
+  };
+  auto apply_src = [&](const int(&f)[RT], const float2(&t)[RT], const float4(&v)[2][2]) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (f[r] >= 0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          acc[r][c][0] = cfma2(acc[r][c][0], t[r], v[c][0]);
+          acc[r][c][1] = cfma2(acc[r][c][1], t[r], v[c][1]);
+        }
+      }
+  };
+  auto load_t = [&](const int(&f)[RT], float2(&t)[RT]) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (f[r] >= 0) t[r] = Tq[(int64_t)f[r] * fstride];
+  };
+  const int e0 = tptr[tile], e1 = tptr[tile + 1];
+  if (e0 < e1) {
+    float4 b[PD][2][2];
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_src(tsrc[min(e0 + d, e1 - 1)], b[d]);
+    int e = e0;
+    for (; e + PD <= e1; e += PD) {
+      int f[PD][RT], sb[PD];
+#pragma unroll
+      for (int d = 0; d < PD; ++d) {
+        load_ids(e + d, f[d]);
+        sb[d] = tsrc[min(e + d + PD, e1 - 1)];
+      }
+      float2 t[PD][RT];
+#pragma unroll
+      for (int d = 0; d < PD; ++d) load_t(f[d], t[d]);
+#pragma unroll
+      for (int d = 0; d < PD; ++d) {
+        apply_src(f[d], t[d], b[d]);
+        load_src(sb[d], b[d]);   // refill the slot
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+      if (e + d < e1) {
+        int f[RT];
+        float2 t[RT];
+        load_ids(e + d, f);
+        load_t(f, t);
+        apply_src(f, t, b[d]);
+      }
+  }
+  if (!act) return;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int m = tile * kTile + h + r;
+    if (m >= nbox) continue;
+    char* gp = reinterpret_cast<char*>(G + m * bstride);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int p2 = 0; p2 < 2; ++p2) {
+        float4* o = reinterpret_cast<float4*>(gp + (lob + (c ? cbytes : 0u) + 16u * p2));
+        if (accum) {
+          float4 v = *o;
+          v.x += acc[r][c][p2].x;
+          v.y += acc[r][c][p2].y;
+          v.z += acc[r][c][p2].z;
+          v.w += acc[r][c][p2].w;
+          *o = v;
+        } else {
+          *o = acc[r][c][p2];
+        }
+      }
   }
 }
 
@@ -1498,6 +1642,29 @@ struct Stages {
   }
 };
 
+// yi = Z_near xi (kind 0; 1 Re Z of the own box, 2 Im Z; dual: dZ_near/dk),
+// internal order, nc contiguous columns
+template <typename R>
+static void near_product(Dev& d, const Plan& P, const C2<R>* xi, C2<R>* yi, int nc, int kind, bool dual,
+                         hipStream_t s) {
+  bool done = false;
+  if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES)) {
+    if (sizeof(R) == 4 && (P.opt.flags & CM_FLAG_NEAR_FP32))
+      done = mf_near32(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off, dual ? d.dZn32 : d.Zn32,
+                       (const float2*)xi, (float2*)yi, d.nleaf, d.max_near_cols, nc, kind, s);
+    else
+      done = mf_near<R>(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off, (const double2*)(dual ? d.dZn : d.Zn),
+                        xi, yi, d.nleaf, d.max_box, d.max_near_cols, nc, kind, s);
+  }
+  if (done) return;
+  if (nc % 4 == 0 && nc <= 64)
+    hipLaunchKernelGGL(k_near_box<R>, dim3(d.nleaf), dim3(256), 0, s, d.row_ptr, d.box_start, d.bcol_ptr, d.bcol,
+                       d.self_off, (const double2*)(dual ? d.dZn : d.Zn), xi, yi, nc, kind);
+  else
+    hipLaunchKernelGGL(k_near<R>, dim3((unsigned)((d.N + 3) / 4)), dim3(256), 0, s, d.row_ptr, d.box_of, d.bcol_ptr,
+                       d.bcol, d.self_off, d.box_start, (const double2*)(dual ? d.dZn : d.Zn), xi, yi, d.N, nc, kind);
+}
+
 template <typename R>
 static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* x, void* y, int64_t ld, int nc,
                        const Work& w, hipStream_t s) {
@@ -1529,29 +1696,12 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
     int64_t tot = N * nc;
     stage_begin(d, s, 0);
     hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
-                       d.perm, xi, N, conj);
+                       d.perm, xi, N, conj, nc);
     stage_end(d, s);
   }
   fork_to(s, sA, 0);
-  const dim3 rows_grid((unsigned)((N + 3) / 4));
   stage_begin(d, sA, 1);
-  bool near_done = false;
-  if (!(P.opt.flags & CM_FLAG_NO_MATRIX_CORES)) {
-    if (sizeof(R) == 4 && (P.opt.flags & CM_FLAG_NEAR_FP32))
-      near_done = mf_near32(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off, dual ? d.dZn32 : d.Zn32,
-                            (const float2*)xi, (float2*)yi, d.nleaf, d.max_near_cols, nc, kind, sA);
-    else
-      near_done = mf_near<R>(d.row_ptr, d.box_start, d.bcol_ptr, d.bcol, d.self_off,
-                             (const double2*)(dual ? d.dZn : d.Zn), xi, yi, d.nleaf, d.max_box, d.max_near_cols, nc,
-                             kind, sA);
-  }
-  if (near_done) {
-  } else if (nc % 4 == 0 && nc <= 64)
-    hipLaunchKernelGGL(k_near_box<R>, dim3(d.nleaf), dim3(256), 0, sA, d.row_ptr, d.box_start, d.bcol_ptr, d.bcol,
-                       d.self_off, (const double2*)(dual ? d.dZn : d.Zn), (const CR*)xi, yi, nc, kind);
-  else
-    hipLaunchKernelGGL(k_near<R>, rows_grid, dim3(256), 0, sA, d.row_ptr, d.box_of, d.bcol_ptr, d.bcol, d.self_off,
-                       d.box_start, (const double2*)(dual ? d.dZn : d.Zn), (const CR*)xi, yi, N, nc, kind);
+  near_product<R>(d, P, xi, yi, nc, kind, dual, sA);
   stage_end(d, sA);
   if (fork) chk(hipEventRecord(d.fork_ev[1], sA), "hipEventRecord");   // near field done
   // translations and downward pass: the translations of a level are stored,
@@ -1618,6 +1768,118 @@ static void apply_impl(Dev& d, const Plan& P, PrecD<R>& pd, int op, const void* 
   }
   stage_end(d, s);
   chk(hipGetLastError(), "apply launch");
+}
+
+// One pass over a wavenumber-sweep batch (FP32 far field and vectors, op Z
+// or Z^H).  x (public order, row stride ld) holds 4 sw.n columns, slot j being
+// columns 4j .. 4j+3 at the wavenumber with index sw.k[j], whose device data
+// and plan are dk[sw.k[j]], Pk[sw.k[j]].  Per slot, with its wavenumber's
+// tables: the permutation into the slot's block of the permuted input (slot
+// blocks N x 8, one after another: the four columns and four zero columns,
+// one column tile of the matrix-core kernels), the near field on that block
+// (on aux[0] when the handle has its auxiliary streams), the aggregation of
+// the slot's four columns into the leaf patterns, and at the end the
+// disaggregation.  The interpolation, the translations (levels lf .. 3 on
+// aux[1]) and the anterpolation run once over all columns with d0's sweep
+// tables: all the wavenumbers share tree, lists and angular sampling.
+void dev_apply_sweep(Dev& d0, const Plan& P0, Dev* const* dk, const Plan* const* Pk, const SweepSlots& sw, int op,
+                     const void* x, void* y, int64_t ld, hipStream_t s) {
+  using CR = C2<float>;
+  const int lf = d0.lf;
+  const int64_t N = d0.N;
+  const int nc = 4 * sw.n;
+  const int conj = (op == 3);
+  if (!sw.on || sw.n < 1 || !sweep_covers(d0, P0, nc))
+    throw Error(-7, "sweep batch not covered by the handle's sweep tables and matrix-core kernels");
+  CR* xi = (CR*)d0.xi;
+  CR* yi = (CR*)d0.yi;
+  const bool fork = !d0.timing && d0.aux[0] && d0.aux[1] && d0.fork_ev.size() >= (size_t)(4 + lf);
+  hipStream_t sA = fork ? d0.aux[0] : s, sB = fork ? d0.aux[1] : s;
+  auto fork_to = [&](hipStream_t from, hipStream_t to, int e) {
+    if (!fork) return;
+    chk(hipEventRecord(d0.fork_ev[e], from), "hipEventRecord");
+    chk(hipStreamWaitEvent(to, d0.fork_ev[e], 0), "hipStreamWaitEvent");
+  };
+  constexpr int kSB = 8;   // columns of a slot block (4 of the slot, 4 zero)
+  auto xs = [&](int j) { return xi + (int64_t)j * N * kSB; };
+  auto ys = [&](int j) { return yi + (int64_t)j * N * kSB; };
+  stage_begin(d0, s, 0);
+  for (int j = 0; j < sw.n; ++j)
+    hipLaunchKernelGGL(k_permute_in<float>, dim3((unsigned)((N * kSB + 255) / 256)), dim3(256), 0, s,
+                       (const CR*)x + 4 * j, ld, 4, d0.perm, xs(j), N, conj, kSB);
+  stage_end(d0, s);
+  fork_to(s, sA, 0);
+  stage_begin(d0, sA, 1);
+  for (int j = 0; j < sw.n; ++j) near_product<float>(*dk[sw.k[j]], *Pk[sw.k[j]], xs(j), ys(j), kSB, 0, false, sA);
+  stage_end(d0, sA);
+  if (fork) chk(hipEventRecord(d0.fork_ev[1], sA), "hipEventRecord");
+  auto m2l = [&](hipStream_t ss, int l) {
+    LevelD<float>& Lv = d0.f32.lev[l];
+    constexpr int RT = 8, PD = 2;
+    const int qb = 256 / sw.n;
+    const dim3 grid((Lv.ntile + 7) / 8 * 8, (Lv.K + qb - 1) / qb, kTile / RT);
+    stage_begin(d0, ss, 4 + 10 * l);
+    hipLaunchKernelGGL((k_m2l_slots<RT, PD>), grid, dim3(256), 0, ss, Lv.tile_ptr, Lv.tile_src, Lv.tile_off,
+                       (const float2*)Lv.sw_T, d0.sw_nk, sw, (const float2*)d0.S[l], (float2*)d0.G[l], Lv.nbox,
+                       Lv.ntile, Lv.K, nc, 0);
+    stage_end(d0, ss);
+  };
+  stage_begin(d0, s, 2);
+  for (int j = 0; j < sw.n; ++j) {
+    Dev& dj = *dk[sw.k[j]];
+    mf_aggregate(dj.f32.V, (const float2*)xs(j), kSB, (float2*)d0.S[lf] + 4 * j, nc, dj.box_start, dj.nleaf,
+                 P0.lev[lf].K, kSB, s, 4);
+  }
+  stage_end(d0, s);
+  fork_to(s, sB, 2);
+  m2l(sB, lf);
+  for (int l = lf - 1; l >= 2; --l) {
+    SweepSlots si = sw;
+    si.stride = d0.f32.lev[l].sw_shift_stride;
+    stage_begin(d0, s, 3 + 10 * l);
+    if (!mf_interp(d0.f32.lev[l], d0.f32.lev[l + 1], (const float2*)d0.S[l + 1], (float2*)d0.S[l], nc, nc, 0,
+                   d0.f32.lev[l].sw_shiftT, s, &si))
+      throw Error(-7, "sweep batch: matrix-core interpolation does not cover this level");
+    stage_end(d0, s);
+    if (l >= 3) {
+      fork_to(s, sB, 3 + l);
+      m2l(sB, l);
+    } else {
+      m2l(s, l);
+    }
+  }
+  fork_to(sB, s, 3);
+  for (int l = 2; l < lf; ++l) {
+    SweepSlots sz = sw;
+    sz.stride = d0.f32.lev[l].sw_zg_stride;
+    stage_begin(d0, s, 5 + 10 * (l + 1));
+    if (!mf_anterp(d0.f32.lev[l], d0.f32.lev[l + 1], (const float2*)d0.G[l], (float2*)d0.G[l + 1], nc, nc, 1,
+                   d0.f32.lev[l].sw_zg, s, &sz))
+      throw Error(-7, "sweep batch: matrix-core anterpolation does not cover this level");
+    stage_end(d0, s);
+  }
+  if (fork) chk(hipStreamWaitEvent(s, d0.fork_ev[1], 0), "hipStreamWaitEvent");
+  stage_begin(d0, s, 6);
+  for (int j = 0; j < sw.n; ++j) {
+    Dev& dj = *dk[sw.k[j]];
+    if (!mf_disagg(dj.f32.V, (const float2*)d0.G[lf] + 4 * j, nc, (const float*)dj.f32.qwc,
+                           (const float2*)ys(j), dj.box_start, dj.nleaf, dj.max_box, d0.perm, P0.lev[lf].K, kSB,
+                           (float2*)y + 4 * j, ld, conj, s, 4, kSB))
+      throw Error(-7, "sweep batch: leaf boxes too large for the matrix-core disaggregation");
+  }
+  stage_end(d0, s);
+  chk(hipGetLastError(), "sweep apply launch");
+  ++d0.sw_calls;
+}
+
+bool sweep_covers(const Dev& d0, const Plan& P0, int nc) {
+  if (d0.sw_nk <= 0 || nc % 4 != 0 || nc / 4 > kMaxSlots || nc > d0.max_cols) return false;
+  if ((P0.opt.flags & CM_FLAG_NO_MATRIX_CORES) || d0.max_box > 64) return false;
+  for (int l = 2; l < d0.lf; ++l)
+    if (!mf_interp_covers(d0.f32.lev[l], d0.f32.lev[l + 1], nc, true) || !mf_covers(d0.f32.lev[l], nc, true) ||
+        !d0.f32.lev[l].sw_shiftT || !d0.f32.lev[l].sw_zg)
+      return false;
+  return true;
 }
 
 // Autotuning of the FP32 batched translation at nc columns: for every level
@@ -1729,7 +1991,7 @@ static void sai_apply_impl(Dev& d, const SaiD& q, const void* x, void* y, int64_
   const int64_t N = d.N;
   int64_t tot = N * nc;
   hipLaunchKernelGGL(k_permute_in<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const CR*)x, ld, nc,
-                     d.perm, (CR*)d.xi, N, 0);
+                     d.perm, (CR*)d.xi, N, 0, nc);
   stage_begin(d, s, 7);
   const int NC = nc <= 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)(nc - 1)));
   const int64_t waves = (N + 64 / std::max(8, NC) - 1) / (64 / std::max(8, NC));

@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_gather_cols(const C* __restrict__ x, in
   C v;
   v.x = 0;
   v.y = 0;
-  xs[e] = (j < cols.n) ? x[i * ld + cols.c[j]] : v;   // columns past the list: zero padding
+  xs[e] = (j < cols.n && cols.c[j] >= 0) ? x[i * ld + cols.c[j]] : v;   // past the list or -1: zero padding
 }
 template <typename C>
 __global__ void __launch_bounds__(256) k_scatter_cols(const C* __restrict__ ys, int ws, ColList cols,
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_scatter_cols(const C* __restrict__ ys, 
   if (e >= N * cols.n) return;
   const int64_t i = e / cols.n;
   const int j = (int)(e - i * cols.n);
-  y[i * ld + cols.c[j]] = ys[i * ws + j];
+  if (cols.c[j] >= 0) y[i * ld + cols.c[j]] = ys[i * ws + j];   // -1: a padding column
 }
 
 // ---------------------------------------------------------------- small dense projections

@@ -78,17 +78,20 @@ static MfD upload_mf(Dev& d, const MfTab& T, hipStream_t s) {
 }
 
 // phase table [8][K] (q = t*np + u) re-laid as [8][np][16 NT] with theta fastest
-static void* upload_shiftT(Dev& d, const std::vector<cplx>& sh, int nt, int np, int NT, hipStream_t s) {
+static std::vector<cplx> shiftT_table(const std::vector<cplx>& sh, int nt, int np, int NT) {
   const int tp = 16 * NT;
   std::vector<cplx> v((size_t)8 * np * tp, cplx(0, 0));
   for (int oc = 0; oc < 8; ++oc)
     for (int t = 0; t < nt; ++t)
       for (int u = 0; u < np; ++u) v[((size_t)oc * np + u) * tp + t] = sh[(size_t)oc * nt * np + (size_t)t * np + u];
-  return upload_complex<float>(d, v, s);
+  return v;
+}
+static void* upload_shiftT(Dev& d, const std::vector<cplx>& sh, int nt, int np, int NT, hipStream_t s) {
+  return upload_complex<float>(d, shiftT_table(sh, nt, np, NT), s);
 }
 
 // phase values of the anterpolation K steps: [chunk][octant][t][4 kmax]
-static void* upload_zg(Dev& d, const std::vector<cplx>& sh, const MfTab& T, int nt, int np, hipStream_t s) {
+static std::vector<cplx> zg_table(const std::vector<cplx>& sh, const MfTab& T, int nt, int np) {
   const int kz = 4 * T.kmax;
   std::vector<cplx> v((size_t)T.nchunk * 8 * nt * kz, cplx(0, 0));
   for (int c = 0; c < T.nchunk; ++c)
@@ -97,7 +100,68 @@ static void* upload_zg(Dev& d, const std::vector<cplx>& sh, const MfTab& T, int 
         for (int k = 0; k < 4 * T.nk[c]; ++k)
           v[(((size_t)c * 8 + oc) * nt + t) * kz + k] =
               sh[(size_t)oc * nt * np + (size_t)t * np + T.kidx[((size_t)c * T.kmax) * 4 + k]];
-  return upload_complex<float>(d, v, s);
+  return v;
+}
+static void* upload_zg(Dev& d, const std::vector<cplx>& sh, const MfTab& T, int nt, int np, hipStream_t s) {
+  return upload_complex<float>(d, zg_table(sh, T, nt, np), s);
+}
+
+// The one-pass sweep tables of d (the first wavenumber's device data): per
+// level Z's FP32 translators of all wavenumbers interleaved [n_off][K][n_k],
+// and the interpolation / anterpolation phase tables of every wavenumber one
+// after another, laid out for the matrix-core tables d uses (after its
+// autotuning).  Every plan must have the same tree, lists and sampling.
+void build_sweep_tables(Dev& d, const Plan& P, const std::vector<const Plan*>& Pk, hipStream_t s) {
+  const int nk = (int)Pk.size();
+  for (const Plan* q : Pk) {
+    if (q->lf != P.lf || q->rwg.N != P.rwg.N) throw Error(CM_E_UNSUPPORTED, "sweep plans differ in their tree");
+    for (int l = 2; l <= P.lf; ++l)
+      if (q->lev[l].K != P.lev[l].K || q->lev[l].nt != P.lev[l].nt || q->lev[l].np != P.lev[l].np ||
+          q->lev[l].n_off_used != P.lev[l].n_off_used || q->lev[l].nbox != P.lev[l].nbox)
+        throw Error(CM_E_UNSUPPORTED, "sweep plans differ in their sampling or lists");
+  }
+  for (int l = 2; l <= P.lf; ++l) {
+    const Level& Lv = P.lev[l];
+    LevelD<float>& D = d.f32.lev[l];
+    const size_t nT = (size_t)Lv.n_off_used * Lv.K;
+    std::vector<float> T(2 * nT * nk);
+    for (int kk = 0; kk < nk; ++kk)
+      for (size_t e = 0; e < nT; ++e) {
+        T[2 * (e * nk + kk)] = (float)Pk[kk]->TZ[l][e].real();
+        T[2 * (e * nk + kk) + 1] = (float)Pk[kk]->TZ[l][e].imag();
+      }
+    D.sw_T = upload(d, T, s);
+    if (l == P.lf) continue;
+    if (D.mip.ok) {
+      std::vector<cplx> all;
+      for (int kk = 0; kk < nk; ++kk) {
+        const std::vector<cplx> v = shiftT_table(Pk[kk]->shift[l], Lv.nt, Lv.np, D.mip.NT);
+        D.sw_shift_stride = (int64_t)v.size();
+        all.insert(all.end(), v.begin(), v.end());
+      }
+      D.sw_shiftT = upload_complex<float>(d, all, s);
+    }
+    if (D.mat.ok) {
+      // the anterpolation table in use: the plan's, or the other width the autotuner swapped in
+      // (the other width exists only on an autotuned handle)
+      const MfTab* A = nullptr;
+      for (const std::vector<MfTab>* v : {&P.mf_at, &P.mf_at_alt})
+        if (l < (int)v->size()) {
+          const MfTab& c = (*v)[l];
+          if (c.ok && c.S2 == D.mat.S2 && c.nchunk == D.mat.nchunk && c.kmax == D.mat.kmax) A = &c;
+        }
+      if (!A) throw Error(CM_E_UNSUPPORTED, "sweep tables: anterpolation table not found");
+      std::vector<cplx> all;
+      for (int kk = 0; kk < nk; ++kk) {
+        const std::vector<cplx> v = zg_table(Pk[kk]->shift[l], *A, Lv.nt, Lv.np);
+        D.sw_zg_stride = (int64_t)v.size();
+        all.insert(all.end(), v.begin(), v.end());
+      }
+      D.sw_zg = upload_complex<float>(d, all, s);
+    }
+  }
+  chk(hipStreamSynchronize(s), "sweep tables");
+  d.sw_nk = nk;
 }
 
 template <typename R>
@@ -472,10 +536,20 @@ cm_status cm_create(const double* xyz, int64_t n_vert, const int32_t* tri, int64
     op.flags = o->flags;
     op.max_cols = o->max_cols;
     op.k_sampling = o->k_sampling;
+    const bool shared = n_k > 1 && (o->flags & CM_FLAG_SWEEP_SHARED);
+    if (shared && !(o->k_sampling > 0)) {
+      op.k_sampling = k[0];
+      for (int i = 1; i < n_k; ++i) op.k_sampling = std::max(op.k_sampling, k[i]);
+    }
     cm_handle* h = build_handle(xyz, n_vert, tri, n_tri, k[0], op, o->flags, (hipStream_t)hip_stream);
     try {
       for (int i = 1; i < n_k; ++i)
         h->sub.push_back(build_handle(xyz, n_vert, tri, n_tri, k[i], op, o->flags, (hipStream_t)hip_stream));
+      if (shared && h->has_dev) {
+        std::vector<const cm::Plan*> pk{&h->plan};
+        for (cm_handle* t : h->sub) pk.push_back(&t->plan);
+        cm::build_sweep_tables(h->dev, h->plan, pk, (hipStream_t)hip_stream);
+      }
       if (n_k > 1 && h->has_dev) {
         const size_t b = (size_t)h->dev.N * h->dev.max_cols * 16;
         for (int i = 0; i < n_k; ++i) {
@@ -644,6 +718,63 @@ static void by_wavenumber(cm_handle* h, const void* x, void* y, int64_t ld, int3
   if (hipGetLastError() != hipSuccess) throw cm::Error(CM_E_HIP, "sweep gather/scatter launch");
 }
 
+// The one-pass route of a wavenumber sweep (CM_FLAG_SWEEP_SHARED, FP32, op Z
+// or Z^H, columns at more than one wavenumber): the columns of each
+// wavenumber in slots of four (the last one padded with zero columns).  When
+// slot j is exactly columns 4j .. 4j+3 of x the pass reads x and writes y in
+// place, otherwise it gathers the slots into the staging block and scatters
+// the result back.  False (nothing launched) when the batch does not fit:
+// more than 16 slots, more than max_cols slot columns, or a level the
+// matrix-core kernels do not cover.
+static bool sweep_one_pass(cm_handle* h, int op, const void* x, void* y, int64_t ld, int ncols,
+                           const int32_t* k_index, hipStream_t s) {
+  if (h->dev.sw_nk <= 0 || !k_index) return false;
+  bool one = true;
+  for (int j = 1; j < ncols; ++j) one = one && k_index[j] == k_index[0];
+  if (one) return false;
+  const int nk = 1 + (int)h->sub.size();
+  cm::SweepSlots sw;
+  sw.on = 1;
+  cm::ColList cl;
+  cl.n = 0;
+  for (int kk = 0; kk < nk; ++kk) {
+    int cnt = 0;
+    for (int j = 0; j < ncols; ++j)
+      if (k_index[j] == kk) {
+        if (cnt % 4 == 0) {
+          if (sw.n == cm::kMaxSlots) return false;
+          sw.k[sw.n++] = kk;
+        }
+        if (cl.n == 64) return false;
+        cl.c[cl.n++] = j;
+        ++cnt;
+      }
+    while (cnt % 4 != 0) {
+      if (cl.n == 64) return false;
+      cl.c[cl.n++] = -1;
+      ++cnt;
+    }
+  }
+  const int nc = 4 * sw.n;
+  if (!cm::sweep_covers(h->dev, h->plan, nc)) return false;
+  std::vector<cm::Dev*> dk{&h->dev};
+  std::vector<const cm::Plan*> pk{&h->plan};
+  for (cm_handle* t : h->sub) {
+    dk.push_back(&t->dev);
+    pk.push_back(&t->plan);
+  }
+  bool inplace = true;
+  for (int j = 0; j < cl.n; ++j) inplace = inplace && cl.c[j] == j;
+  if (inplace) {
+    cm::dev_apply_sweep(h->dev, h->plan, dk.data(), pk.data(), sw, op, x, y, ld, s);
+  } else {
+    cm::blas_gather_cols(x, ld, cl, nc, h->xs, h->dev.N, false, s);
+    cm::dev_apply_sweep(h->dev, h->plan, dk.data(), pk.data(), sw, op, h->xs, h->ys, nc, s);
+    cm::blas_scatter_cols(h->ys, nc, cl, y, ld, h->dev.N, false, s);
+  }
+  return true;
+}
+
 extern "C" {
 
 static cm_status check_k_index(const cm_handle* h, const int32_t* k_index, int32_t ncols) {
@@ -665,6 +796,9 @@ cm_status cm_apply(cm_handle* h, cm_op op, const void* x, void* y, int64_t ld, i
   if ((st = check_k_index(h, k_index, ncols)) != CM_OK) return st;
   const bool fp64 = dt == CM_C128;
   CM_TRY({
+    if (!fp64 && (op == CM_OP_Z || op == CM_OP_ZH) && sweep_one_pass(h, (int)op, x, y, ld, ncols, k_index,
+                                                                    (hipStream_t)hip_stream))
+      return CM_OK;
     by_wavenumber(h, x, y, ld, ncols, k_index, fp64, (hipStream_t)hip_stream,
                   [&](cm_handle* t, const void* xx, void* yy, int64_t l, int n, hipStream_t ss) {
                     cm::dev_apply(t->dev, t->plan, (int)op, xx, yy, l, n, fp64, ss);
@@ -806,6 +940,9 @@ cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* need
   std::string s = h->plan.stats_json();
   if (h->has_dev && !h->dev.tune_json.empty() && !s.empty() && s.back() == '}')
     s = s.substr(0, s.size() - 1) + ", \"autotune\": " + h->dev.tune_json + "}";
+  if (h->has_dev && h->dev.sw_nk > 0 && !s.empty() && s.back() == '}')
+    s = s.substr(0, s.size() - 1) + ", \"sweep_tables\": " + std::to_string(h->dev.sw_nk) +
+        ", \"sweep_one_pass_calls\": " + std::to_string(h->dev.sw_calls) + "}";
   if (needed) *needed = (int64_t)s.size() + 1;
   if (!buf || buf_len < (int64_t)s.size() + 1) return fail(CM_E_BADARG, "buffer too small");
   std::memcpy(buf, s.c_str(), s.size() + 1);

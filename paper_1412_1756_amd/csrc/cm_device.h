@@ -26,6 +26,18 @@ struct RwgD {
   double len;
 };
 
+// Columns of a one-pass wavenumber-sweep batch: slots of four columns, slot
+// j at the handle's wavenumber k[j]; the kernels index per-wavenumber tables
+// (translators, shift phases) `stride` complex values apart.  on == 0: an
+// ordinary batch (one wavenumber, columns in tiles of eight).
+constexpr int kMaxSlots = 16;
+struct SweepSlots {
+  int on = 0;
+  int n = 0;
+  int32_t k[kMaxSlots] = {};
+  int64_t stride = 0;
+};
+
 // Matrix-core interpolation tables of one level pair (FP32 path), see MfTab.
 struct MfD {
   int ok = 0, NT = 0, S2 = 0, half = 0, nchunk = 0, kmax = 0, ktmax = 0;
@@ -69,6 +81,14 @@ struct LevelD {
   MfD mip_alt, mat_alt;
   void *zg_alt = nullptr, *dzg_alt = nullptr;
   int rg_ip = 0, rg_at = 0;
+  // one-pass wavenumber sweeps (CM_FLAG_SWEEP_SHARED, on the first
+  // wavenumber's handle): Z's translators of all wavenumbers interleaved,
+  // [n_off][K][n_k], and the shift tables of the interpolation into this
+  // level (shiftT layout) and of the anterpolation from it (zg layout of the
+  // table in use), one wavenumber after the other
+  void* sw_T = nullptr;
+  void *sw_shiftT = nullptr, *sw_zg = nullptr;
+  int64_t sw_shift_stride = 0, sw_zg_stride = 0;
 };
 
 template <typename R>
@@ -129,6 +149,8 @@ struct Dev {
   std::vector<double> stage_ms;
   std::vector<int64_t> stage_calls;
   std::string tune_json;                    // autotuner's choices (empty when not tuned)
+  int sw_nk = 0;                            // wavenumbers of the one-pass sweep tables (0: none)
+  int64_t sw_calls = 0;                     // one-pass sweep applies so far
 };
 
 // stage ids for timing: 0 permute, 1 near, 2 aggregate, 3 interp, 4 m2l,
@@ -141,17 +163,22 @@ void collect_stage_times(Dev& d);
 // complex-float patterns with nc % 8 == 0; false when the level is not covered.
 // Lp: the parent level, Lc: the child level.  shiftT: Lp.shiftT or
 // Lp.dshiftT; zg: Lp.zg or Lp.dzg.
+// sw: a sweep batch (nc = 4 sw.n; shiftT / zg then hold the tables of all
+// wavenumbers, sw.stride apart), or nullptr.
 bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc, int ldp,
-               int accum, const void* shiftT, hipStream_t s);
+               int accum, const void* shiftT, hipStream_t s, const SweepSlots* sw = nullptr);
 bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc, int ldp,
-               int add, const void* zg, hipStream_t s);
+               int add, const void* zg, hipStream_t s, const SweepSlots* sw = nullptr);
 // Matrix-core leaf aggregation / disaggregation (complex float, nc % 8 == 0);
 // false when not covered (disaggregation: boxes of more than 64 unknowns).
+// ncv (< 0: nc): only the first ncv columns are read from x / G and written
+// to S / y (the rest of the column tiles count as zero); ldyi (< 0: nc): the
+// row stride of the near-field result yi.
 bool mf_aggregate(const void* V, const float2* xi, int ldx, float2* S, int ldS, const int32_t* box_start, int nbox,
-                  int K, int nc, hipStream_t s);
+                  int K, int nc, hipStream_t s, int ncv = -1);
 bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const float2* yi, const int32_t* box_start,
                int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
-               hipStream_t s);
+               hipStream_t s, int ncv = -1, int ldyi = -1);
 // Near-field product on the FP64 matrix cores (x, y complex R; nc % 8 == 0,
 // nc <= 64, leaf boxes of at most 64 unknowns); mode 0 Z, 1 Re Z self box, 2 Im Z.
 template <typename R>
@@ -171,7 +198,9 @@ std::string mf_autotune(PrecD<float>& pd, int lf, const std::vector<void*>& S, c
 std::string m2l_autotune(Dev& d, const Plan& P, const std::vector<void*>& S, const std::vector<void*>& G, int nc,
                          hipStream_t s);
 // whether mf_anterp takes the anterpolation from level Lp for nc columns
-bool mf_covers(const LevelD<float>& Lp, int nc);
+bool mf_covers(const LevelD<float>& Lp, int nc, bool sweep = false);
+// whether mf_interp takes the interpolation into level Lp (sweep batch: nc = 4 slots)
+bool mf_interp_covers(const LevelD<float>& Lp, const LevelD<float>& Lc, int nc, bool sweep);
 
 void blas_to_c64(const double2* x, float2* y, int64_t N, hipStream_t s);   // complex double -> float
 void dev_build(Dev& d, const Plan& P, hipStream_t s);
@@ -199,6 +228,12 @@ void dev_apply(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld
 // the same on a caller-provided workspace (no allocation, no stage timing)
 void dev_apply_ws(Dev& d, const Plan& P, int op, const void* x, void* y, int64_t ld, int nc, bool fp64,
                   const Work& w, hipStream_t s);
+// one pass over a wavenumber-sweep batch (FP32, op 0 Z or 3 Z^H; dk, Pk
+// indexed by wavenumber), see cm_apply.hip; sweep_covers: whether the
+// handle's sweep tables and the matrix-core kernels cover nc columns
+void dev_apply_sweep(Dev& d0, const Plan& P0, Dev* const* dk, const Plan* const* Pk, const SweepSlots& sw, int op,
+                     const void* x, void* y, int64_t ld, hipStream_t s);
+bool sweep_covers(const Dev& d0, const Plan& P0, int nc);
 // SAI of the near field of tau R + i X: tau = 1 is Z_near (slot 0); any
 // other tau goes to slot 1, tau = 0 meaning the real matrix X_near
 void dev_sai_build(Dev& d, const Plan& P, double e1, double e2, double e3, double tau, hipStream_t s);
@@ -259,8 +294,9 @@ struct ColList {
   int c[64];
 };
 // gather the listed columns of x into the staging block xs (N x ws, ws >=
-// cols.n; columns past the list are zero) / scatter the first cols.n columns
-// of ys (N x ws) back to the listed columns of y
+// cols.n; columns past the list and entries -1 are zero) / scatter the first
+// cols.n columns of ys (N x ws) back to the listed columns of y (entries -1
+// skipped)
 void blas_gather_cols(const void* x, int64_t ld, ColList cols, int ws, void* xs, int64_t N, bool fp64,
                       hipStream_t s);
 void blas_scatter_cols(const void* ys, int ws, ColList cols, void* y, int64_t ld, int64_t N, bool fp64,

@@ -76,13 +76,16 @@ __device__ __forceinline__ void stage_theta_tables(const MfD& T, int t0, int NT,
 // z = groups of NT theta row tiles (more than four tiles are split over
 // blocks, each redoing the phi step).  The phi-step loads of a child are
 // double-buffered in groups of kRG rows and the first group of the next
-// child is loaded during the theta step, which touches only LDS.
+// child is loaded during the theta step, which touches only LDS.  A column
+// tile is eight columns of one component, or in a wavenumber-sweep batch (sw)
+// the four columns of one slot in both components (the Lagrange weights and
+// the shift phase are the same for both), with the slot's shift table.
 template <int NT, int S2, int kMK, int kRG, int kW>
 __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__ Sc, float* __restrict__ Sp,
                                                    const int32_t* __restrict__ child_ptr,
                                                    const int8_t* __restrict__ octant, MfD T,
                                                    const float2* __restrict__ shiftT, int ntc, int npc, int ntp,
-                                                   int npp, int nbox, int nc, int ldp, int accum) {
+                                                   int npp, int nbox, int nc, int ldp, int accum, SweepSlots sw) {
   constexpr int S = 2 * S2, RS = 16 * S + 16, SB = S < 8 ? S : 8, SH = S * 16 * NT;   // SH: shift entries
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -95,14 +98,25 @@ __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__
   __syncthreads();
   const int cpt = nc >> 3;
   const int tile = blockIdx.y * (int)(blockDim.x >> 6) + w;
-  if (tile >= 2 * cpt) return;
+  if (tile >= (sw.on ? sw.n : 2 * cpt)) return;
   float* O = tAl + NT * T.ktmax * 64 + w * (ntc * RS + 2 * SH);
   float2* ShL = reinterpret_cast<float2*>(O + ntc * RS);   // [slot][16 NT] shift of the current child
   const int m = b / T.nchunk, c = b - m * T.nchunk;
-  const int comp = tile / cpt, col = 16 * (tile - comp * cpt);
   const int g = lane >> 4, n = lane & 15;
+  // this lane's component and float offset within a row of that component
+  int comp, lcol;
+  const float2* shk = shiftT;
+  if (sw.on) {
+    comp = n >> 3;
+    lcol = 8 * tile + (n & 7);
+    shk += (int64_t)sw.k[tile] * sw.stride;
+  } else {
+    comp = tile / cpt;
+    lcol = 16 * (tile - comp * cpt) + n;
+  }
   const int ld2 = 2 * ldp;
   const int64_t Kc = (int64_t)ntc * npc, Kp = (int64_t)ntp * npp;
+  const unsigned coff = (unsigned)comp * (unsigned)(Kc * ld2) + (unsigned)lcol;
   const int u0 = T.chunk[2 * c], h = T.chunk[2 * c + 1];
   const int nk = T.nk[c];
   unsigned uoff[kMK];
@@ -112,7 +126,7 @@ __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__
     uoff[kk] = 0;
     pa[kk] = 0.f;
     if (kk < nk) {
-      uoff[kk] = (unsigned)T.kidx[(c * T.kmax + kk) * 4 + g] * (unsigned)ld2 + (unsigned)(col + n);
+      uoff[kk] = (unsigned)T.kidx[(c * T.kmax + kk) * 4 + g] * (unsigned)ld2 + coff;
       pa[kk] = T.kA[(c * T.kmax + kk) * 64 + lane];
     }
   }
@@ -123,7 +137,7 @@ __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__
     for (int s = 0; s < S; ++s) acc[t][s] = f4{0.f, 0.f, 0.f, 0.f};
   const float sg = (n & 1) ? 1.f : -1.f;   // (sx + i sy)(re + i im): re lane -sy*im, im lane +sy*re
   const int64_t rstride = (int64_t)npc * ld2;
-  auto child_src = [&](int ch) { return Sc + ((int64_t)ch * 2 + comp) * Kc * ld2; };
+  auto child_src = [&](int ch) { return Sc + (int64_t)ch * 2 * Kc * ld2; };
   // phi step of kRG rows from v into LDS rows r0 ..
   auto phi_rows = [&](const float (&v)[kRG][kMK], int r0) {
     f4 d[kRG];
@@ -152,7 +166,7 @@ __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__
     const float* src = child_src(ch);
     // this child's shift rows of the chunk's slots (written to LDS after the phi step)
     // table rows hold 16 T.NT values per phi slot; this block's tiles start at 16 t0
-    const float4* shg = reinterpret_cast<const float4*>(shiftT + (size_t)octant[ch] * npp * (16 * T.NT));
+    const float4* shg = reinterpret_cast<const float4*>(shk + (size_t)octant[ch] * npp * (16 * T.NT));
     float4 shv[(SH / 2 + 63) / 64];
 #pragma unroll
     for (int i = 0; i < (SH / 2 + 63) / 64; ++i) {
@@ -219,7 +233,7 @@ __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__
     }
     wave_lds_sync();
   }
-  float* dst = Sp + ((int64_t)m * 2 + comp) * Kp * ld2 + col + n;
+  float* dst = Sp + ((int64_t)m * 2 + comp) * Kp * ld2 + lcol;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -249,12 +263,14 @@ __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__
 // values for the child's octant (zg: [chunk][octant][parent theta row][4
 // kmax], in K-step key order) and the theta tables in LDS; the parent-row
 // loads are double-buffered in groups of kRG rows.
+// A sweep batch (sw) maps column tiles to slots as the interpolation does;
+// each wave then stages its slot's phase values.
 template <int NT, int S2, int kMK, int kRG, int kW>
 __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__ Gp, float* __restrict__ Gc,
                                                    const int32_t* __restrict__ parent,
                                                    const int8_t* __restrict__ octant, MfD T,
                                                    const float2* __restrict__ zg, int ntc, int npc, int ntp,
-                                                   int npp, int nchild, int nc, int ldp, int add) {
+                                                   int npp, int nchild, int nc, int ldp, int add, SweepSlots sw) {
   constexpr int S = 2 * S2, RS = 16 * S + 16;
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -265,23 +281,41 @@ __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__
   const int t0 = blockIdx.z * NT;   // first child theta row tile of this block
   int* tcode = reinterpret_cast<int*>(lds);
   float* tAl = lds + NT * T.ktmax * 4;
-  float2* Z = reinterpret_cast<float2*>(tAl + NT * T.ktmax * 64);
+  float2* Z0 = reinterpret_cast<float2*>(tAl + NT * T.ktmax * 64);
+  const int nz = sw.on ? (int)(blockDim.x >> 6) : 1;   // phase tables in LDS: one per wave in a sweep batch
   stage_theta_tables(T, t0, NT, tcode, tAl);
-  {
+  if (!sw.on) {
     const float4* zs = reinterpret_cast<const float4*>(zg + ((size_t)c * 8 + octant[ch]) * ntp * kz);
-    float4* zd = reinterpret_cast<float4*>(Z);
+    float4* zd = reinterpret_cast<float4*>(Z0);
     for (int e = threadIdx.x; e < ntp * kz / 2; e += blockDim.x) zd[e] = zs[e];
   }
   __syncthreads();
   const int cpt = nc >> 3;
   const int tile = blockIdx.y * (int)(blockDim.x >> 6) + w;
-  if (tile >= 2 * cpt) return;
-  float* O = reinterpret_cast<float*>(Z + ntp * kz) + w * ntp * RS;
+  if (tile >= (sw.on ? sw.n : 2 * cpt)) return;
+  float2* Z = Z0;
+  if (sw.on) {
+    Z = Z0 + (size_t)w * ntp * kz;
+    const float4* zs = reinterpret_cast<const float4*>(zg + (int64_t)sw.k[tile] * sw.stride +
+                                                       ((size_t)c * 8 + octant[ch]) * ntp * kz);
+    float4* zd = reinterpret_cast<float4*>(Z);
+    for (int e = lane; e < ntp * kz / 2; e += 64) zd[e] = zs[e];
+    wave_lds_sync();
+  }
+  float* O = reinterpret_cast<float*>(Z0 + (size_t)nz * ntp * kz) + w * ntp * RS;
   const int m = parent[ch];
-  const int comp = tile / cpt, col = 16 * (tile - comp * cpt);
   const int g = lane >> 4, n = lane & 15;
+  int comp, lcol;   // this lane's component and float offset within a row of that component
+  if (sw.on) {
+    comp = n >> 3;
+    lcol = 8 * tile + (n & 7);
+  } else {
+    comp = tile / cpt;
+    lcol = 16 * (tile - comp * cpt) + n;
+  }
   const int ld2 = 2 * ldp;
   const int64_t Kc = (int64_t)ntc * npc, Kp = (int64_t)ntp * npp;
+  const unsigned coff = (unsigned)comp * (unsigned)(Kp * ld2) + (unsigned)lcol;
   const int u0 = T.chunk[2 * c], h = T.chunk[2 * c + 1];
   const int nk = T.nk[c];
   unsigned poff[kMK];
@@ -291,11 +325,11 @@ __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__
     poff[kk] = 0;
     pa[kk] = 0.f;
     if (kk < nk) {
-      poff[kk] = (unsigned)T.kidx[(c * T.kmax + kk) * 4 + g] * (unsigned)ld2 + (unsigned)(col + n);
+      poff[kk] = (unsigned)T.kidx[(c * T.kmax + kk) * 4 + g] * (unsigned)ld2 + coff;
       pa[kk] = T.kA[(c * T.kmax + kk) * 64 + lane];
     }
   }
-  const float* par = Gp + ((int64_t)m * 2 + comp) * Kp * ld2;
+  const float* par = Gp + (int64_t)m * 2 * Kp * ld2;
   const int64_t rstride = (int64_t)npp * ld2;
   const float sg = (n & 1) ? -1.f : 1.f;   // (sx - i sy)(re + i im): re lane +sy*im, im lane -sy*re
   auto phiT_rows = [&](const float (&v)[kRG][kMK], int r0) {
@@ -356,7 +390,7 @@ __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__
   }
   float* dst = Gc + ((int64_t)ch * 2 + comp) * Kc * ld2;
   const unsigned rstep = (unsigned)npc * (unsigned)ld2;
-  const unsigned loff = 4u * g * rstep + (unsigned)(col + n);
+  const unsigned loff = 4u * g * rstep + (unsigned)lcol;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -385,7 +419,7 @@ template <int MTW, int NTL>
 __global__ void __launch_bounds__(256) k_aggregate_mf(const float2* __restrict__ V, const float* __restrict__ xi,
                                                       int ldx, float* __restrict__ S, int ldS,
                                                       const int32_t* __restrict__ box_start, int nbox, int K2, int nc,
-                                                      int wpb) {
+                                                      int wpb, int cvf) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
   const int wid = blockIdx.x * 4 + w;
@@ -413,7 +447,8 @@ __global__ void __launch_bounds__(256) k_aggregate_mf(const float2* __restrict__
       }
 #pragma unroll
       for (int nt = 0; nt < NTL; ++nt)
-        bq[nt] = (ok && nt0 + nt < ntiles) ? xi[(int64_t)ii * 2 * ldx + 16 * (nt0 + nt) + r] : 0.f;
+        bq[nt] = (ok && nt0 + nt < ntiles && 16 * (nt0 + nt) + r < cvf) ? xi[(int64_t)ii * 2 * ldx + 16 * (nt0 + nt) + r]
+                                                                         : 0.f;
 #pragma unroll
       for (int nt = 0; nt < NTL; ++nt) {
         const float bs = sg * pair_swap(bq[nt]);
@@ -432,7 +467,8 @@ __global__ void __launch_bounds__(256) k_aggregate_mf(const float2* __restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int row = m0 + 16 * mt + 4 * g + j;
-          if (row < K2) S[((int64_t)box * K2 + row) * 2 * ldS + 16 * (nt0 + nt) + r] = acc[mt][nt][j];
+          if (row < K2 && 16 * (nt0 + nt) + r < cvf)
+            S[((int64_t)box * K2 + row) * 2 * ldS + 16 * (nt0 + nt) + r] = acc[mt][nt][j];
         }
       }
   }
@@ -451,7 +487,8 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
                                                    const float* __restrict__ qwc, const float* __restrict__ yi,
                                                    const int32_t* __restrict__ box_start,
                                                    const int32_t* __restrict__ perm, int K, int nc,
-                                                   float* __restrict__ y, int64_t ld, int conj_out) {
+                                                   float* __restrict__ y, int64_t ld, int conj_out, int cvf,
+                                                   int ldyi) {
   constexpr int NR = MTU * 2 * 4;     // floats per lane of one reduction round (two column tiles)
   extern __shared__ float red[];      // [4 waves][NR][64]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -484,7 +521,9 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
       }
 #pragma unroll
       for (int nt = 0; nt < NTL; ++nt)
-        bq[nt] = (rok && nt0 + nt < ntiles) ? gb[(int64_t)row * 2 * ldp + 16 * (nt0 + nt) + r] : 0.f;
+        bq[nt] = (rok && nt0 + nt < ntiles && 16 * (nt0 + nt) + r < cvf)
+                     ? gb[(int64_t)row * 2 * ldp + 16 * (nt0 + nt) + r]
+                     : 0.f;
 #pragma unroll
       for (int nt = 0; nt < NTL; ++nt) {
         const float bs = sg * pair_swap(bq[nt]);
@@ -512,9 +551,9 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
         const int nt = np + h;
         const int i = i0 + 16 * mt + 4 * (l >> 4) + j;
         const int colf = 16 * (nt0 + nt) + (l & 15);
-        if (i >= i1 || nt >= NTL || nt0 + nt >= ntiles) continue;
+        if (i >= i1 || nt >= NTL || nt0 + nt >= ntiles || colf >= cvf) continue;
         float sum = red[e] + red[NR * 64 + e] + red[2 * NR * 64 + e] + red[3 * NR * 64 + e];
-        sum += yi[(int64_t)i * 2 * nc + colf];
+        sum += yi[(int64_t)i * 2 * ldyi + colf];
         if (conj_out && (colf & 1)) sum = -sum;
         y[(int64_t)(perm ? perm[i] : i) * 2 * ld + colf] = sum;
       }
@@ -523,37 +562,53 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
 }
 
 bool mf_aggregate(const void* V, const float2* xi, int ldx, float2* S, int ldS, const int32_t* box_start, int nbox,
-                  int K, int nc, hipStream_t s) {
+                  int K, int nc, hipStream_t s, int ncv) {
   if (nc % 8 != 0) return false;
-  constexpr int MTW = 3, NTL = 4;
+  if (ncv < 0) ncv = nc;
+  constexpr int MTW = 3;
   const int K2 = 2 * K;
   const int wpb = (K2 + 16 * MTW - 1) / (16 * MTW);
   const int64_t waves = (int64_t)nbox * wpb;
-  hipLaunchKernelGGL((k_aggregate_mf<MTW, NTL>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                     (const float2*)V, (const float*)xi, ldx, (float*)S, ldS, box_start, nbox, K2, nc, wpb);
+  // four column tiles per pass over the leaf patterns, one for a single tile
+  // (no matrix-core steps on empty tiles)
+  if (nc <= 8)
+    hipLaunchKernelGGL((k_aggregate_mf<MTW, 1>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                       (const float2*)V, (const float*)xi, ldx, (float*)S, ldS, box_start, nbox, K2, nc, wpb, 2 * ncv);
+  else
+    hipLaunchKernelGGL((k_aggregate_mf<MTW, 4>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                       (const float2*)V, (const float*)xi, ldx, (float*)S, ldS, box_start, nbox, K2, nc, wpb, 2 * ncv);
   return true;
 }
 
 bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const float2* yi, const int32_t* box_start,
                int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
-               hipStream_t s) {
+               hipStream_t s, int ncv, int ldyi) {
   if (nc % 8 != 0 || max_box > 64) return false;
+  if (ncv < 0) ncv = nc;
+  if (ldyi < 0) ldyi = nc;
   // four column tiles per pass over the leaf patterns (each read once for
   // 32 columns), reduced two tiles at a time: the LDS buffer (4 waves x MTU
   // x 2 x 4 floats per lane) leaves room for four blocks per CU
-  constexpr int NTL = 4;
-#define CM_DIS(MTU)                                                                                            \
+  // (one column tile per pass for a single tile)
+#define CM_DIS(MTU, NTL)                                                                                       \
   hipLaunchKernelGGL((k_disagg_mf<MTU, NTL>), dim3(nbox), dim3(256), (size_t)4 * MTU * 2 * 4 * 64 * 4, s,     \
                      (const float2*)V, (const float*)G, ldp, qwc, (const float*)yi, box_start, perm, K, nc,   \
-                     (float*)y, ld, conj)
-  if (max_box <= 16)
-    CM_DIS(1);
-  else if (max_box <= 32)
-    CM_DIS(2);
-  else if (max_box <= 48)
-    CM_DIS(3);
-  else
-    CM_DIS(4);
+                     (float*)y, ld, conj, 2 * ncv, ldyi)
+#define CM_DIS_N(MTU)  \
+  if (nc <= 8)         \
+    CM_DIS(MTU, 1);    \
+  else                 \
+    CM_DIS(MTU, 4);
+  if (max_box <= 16) {
+    CM_DIS_N(1)
+  } else if (max_box <= 32) {
+    CM_DIS_N(2)
+  } else if (max_box <= 48) {
+    CM_DIS_N(3)
+  } else {
+    CM_DIS_N(4)
+  }
+#undef CM_DIS_N
 #undef CM_DIS
   return true;
 }
@@ -809,19 +864,30 @@ bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bc
   (void)max_box;
   // one row tile and two column tiles per wave: four waves per leaf box
   // (0.53 ms for the 32-column product at N = 122,880 against 0.73 ms with
-  // one wave per box)
-  constexpr int MT = 1, NW = 2, BPB = 4 / ((2 / MT) * (4 / NW));   // boxes per block of four waves
-  const dim3 grid((unsigned)((nleaf + BPB - 1) / BPB), (unsigned)((nc + 31) / 32));
-#define CM_NEAR(M)                                                                                          \
-  hipLaunchKernelGGL((k_near_mf<R, M, MT, NW>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol, \
-                     self_off, Zn, (const R*)xi, (R*)yi, nleaf, nc, xcap)
-  if (mode == 0)
-    CM_NEAR(0);
-  else if (mode == 1)
-    CM_NEAR(1);
-  else
-    CM_NEAR(2);
+  // one wave per box); a batch of one column tile takes two waves per box
+  // with all four column slots each, so that every value is loaded once
+  constexpr int MT = 1;
+#define CM_NEAR_W(M, NW)                                                                                       \
+  {                                                                                                            \
+    constexpr int BPB = 4 / ((2 / MT) * (4 / NW));                                                             \
+    const dim3 grid((unsigned)((nleaf + BPB - 1) / BPB), (unsigned)((nc + 31) / 32));                          \
+    hipLaunchKernelGGL((k_near_mf<R, M, MT, NW>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol,  \
+                       self_off, Zn, (const R*)xi, (R*)yi, nleaf, nc, xcap);                                   \
+  }
+#define CM_NEAR(M)        \
+  if (nc <= 8)            \
+    CM_NEAR_W(M, 4)       \
+  else                    \
+    CM_NEAR_W(M, 2)
+  if (mode == 0) {
+    CM_NEAR(0)
+  } else if (mode == 1) {
+    CM_NEAR(1)
+  } else {
+    CM_NEAR(2)
+  }
 #undef CM_NEAR
+#undef CM_NEAR_W
   return true;
 }
 template bool mf_near<float>(const int64_t*, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
@@ -851,9 +917,10 @@ static size_t interp_lds(const MfD& T, int ntc, int wpb) {
   const int nb = nt_block(T), S = 2 * T.S2, RS = 16 * S + 16, SH = S * 16 * nb;
   return (size_t)nb * T.ktmax * 68 * 4 + (size_t)wpb * (ntc * RS + 2 * SH) * 4;
 }
-static size_t anterp_lds(const MfD& T, int ntp, int wpb) {
+static size_t anterp_lds(const MfD& T, int ntp, int wpb, bool sweep) {
   const int S = 2 * T.S2, RS = 16 * S + 16;
-  return (size_t)nt_block(T) * T.ktmax * 68 * 4 + (size_t)ntp * 4 * T.kmax * 8 + (size_t)wpb * ntp * RS * 4;
+  return (size_t)nt_block(T) * T.ktmax * 68 * 4 + (size_t)(sweep ? wpb : 1) * ntp * 4 * T.kmax * 8 +
+         (size_t)wpb * ntp * RS * 4;
 }
 // waves per block: four (one column tile each), fewer where the rows of four
 // waves do not fit in LDS (large angular grids at coarse levels); 0: none fits
@@ -862,9 +929,9 @@ static int interp_wpb(const MfD& T, int ntc) {
     if (lds_fits(interp_lds(T, ntc, w))) return w;
   return 0;
 }
-static int anterp_wpb(const MfD& T, int ntp) {
+static int anterp_wpb(const MfD& T, int ntp, bool sweep) {
   for (int w = 4; w >= 1; w /= 2)
-    if (lds_fits(anterp_lds(T, ntp, w))) return w;
+    if (lds_fits(anterp_lds(T, ntp, w, sweep))) return w;
   return 0;
 }
 
@@ -883,10 +950,10 @@ static bool rg_valid(int mk, int rg) {
 
 template <int NT, int S2, int MK, int RG, int W>
 static void launch_interp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
-                             int ldp, int accum, const void* shiftT, hipStream_t s) {
+                             int ldp, int accum, const void* shiftT, const SweepSlots& sw, hipStream_t s) {
   const MfD& T = Lp.mip;
   const int nb = (Lp.nbox * T.nchunk + 7) / 8 * 8;
-  const int ntiles = nc / 4;   // 2 components x nc/8
+  const int ntiles = nc / 4;   // 2 components x nc/8, or the slots of a sweep batch
   const int wpb = interp_wpb(T, Lc.nt);
   const size_t sh = interp_lds(T, Lc.nt, wpb);
   lds_limit((const void*)k_interp_mf<NT, S2, MK, RG, W>, sh);
@@ -894,45 +961,45 @@ static void launch_interp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, c
                      sh, s,
                      (const float*)Sc,
                      (float*)Sp, Lp.child_ptr, Lc.octant, T, (const float2*)shiftT, Lc.nt, Lc.np, Lp.nt, Lp.np,
-                     Lp.nbox, nc, ldp, accum);
+                     Lp.nbox, nc, ldp, accum, sw);
 }
 
 template <int NT, int S2, int MK>
 static void launch_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc,
-                          int ldp, int accum, const void* shiftT, int rg, hipStream_t s) {
+                          int ldp, int accum, const void* shiftT, int rg, const SweepSlots& sw, hipStream_t s) {
   if constexpr (MK <= 8)
-    if (rg == 4) return launch_interp_rg<NT, S2, MK, 4, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
-  if (rg == (1 | kRgW3)) return launch_interp_rg<NT, S2, MK, 1, 3>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
-  if (rg == (2 | kRgW3)) return launch_interp_rg<NT, S2, MK, 2, 3>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
-  if (rg == 1) return launch_interp_rg<NT, S2, MK, 1, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
-  launch_interp_rg<NT, S2, MK, 2, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, s);
+    if (rg == 4) return launch_interp_rg<NT, S2, MK, 4, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, sw, s);
+  if (rg == (1 | kRgW3)) return launch_interp_rg<NT, S2, MK, 1, 3>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, sw, s);
+  if (rg == (2 | kRgW3)) return launch_interp_rg<NT, S2, MK, 2, 3>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, sw, s);
+  if (rg == 1) return launch_interp_rg<NT, S2, MK, 1, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, sw, s);
+  launch_interp_rg<NT, S2, MK, 2, 1>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, sw, s);
 }
 
 template <int NT, int S2, int MK, int RG, int W>
 static void launch_anterp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
-                             int ldp, int add, const void* zg, hipStream_t s) {
+                             int ldp, int add, const void* zg, const SweepSlots& sw, hipStream_t s) {
   const MfD& T = Lp.mat;
   const int nb = (Lc.nbox * T.nchunk + 7) / 8 * 8;
   const int ntiles = nc / 4;
-  const int wpb = anterp_wpb(T, Lp.nt);
-  const size_t sh = anterp_lds(T, Lp.nt, wpb);
+  const int wpb = anterp_wpb(T, Lp.nt, sw.on);
+  const size_t sh = anterp_lds(T, Lp.nt, wpb, sw.on);
   lds_limit((const void*)k_anterp_mf<NT, S2, MK, RG, W>, sh);
   hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG, W>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
                      sh, s,
                      (const float*)Gp,
                      (float*)Gc, Lc.parent, Lc.octant, T, (const float2*)zg, Lc.nt, Lc.np, Lp.nt, Lp.np, Lc.nbox, nc,
-                     ldp, add);
+                     ldp, add, sw);
 }
 
 template <int NT, int S2, int MK>
 static void launch_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc,
-                          int ldp, int add, const void* zg, int rg, hipStream_t s) {
+                          int ldp, int add, const void* zg, int rg, const SweepSlots& sw, hipStream_t s) {
   if constexpr (MK <= 8)
-    if (rg == 4) return launch_anterp_rg<NT, S2, MK, 4, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
-  if (rg == (1 | kRgW3)) return launch_anterp_rg<NT, S2, MK, 1, 3>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
-  if (rg == (2 | kRgW3)) return launch_anterp_rg<NT, S2, MK, 2, 3>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
-  if (rg == 1) return launch_anterp_rg<NT, S2, MK, 1, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
-  launch_anterp_rg<NT, S2, MK, 2, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, s);
+    if (rg == 4) return launch_anterp_rg<NT, S2, MK, 4, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, sw, s);
+  if (rg == (1 | kRgW3)) return launch_anterp_rg<NT, S2, MK, 1, 3>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, sw, s);
+  if (rg == (2 | kRgW3)) return launch_anterp_rg<NT, S2, MK, 2, 3>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, sw, s);
+  if (rg == 1) return launch_anterp_rg<NT, S2, MK, 1, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, sw, s);
+  launch_anterp_rg<NT, S2, MK, 2, 1>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, sw, s);
 }
 
 #define CM_MF_CASES(X)                                                    \
@@ -951,39 +1018,55 @@ static bool has_case(const MfD& T) {
   return false;
 }
 
-bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc, int ldp,
-               int accum, const void* shiftT, hipStream_t s) {
+// columns per batch: tiles of eight, or slots of four in a sweep batch (at most kMaxSlots)
+static bool cols_ok(int nc, bool sweep) {
+  return sweep ? (nc % 4 == 0 && nc / 4 <= kMaxSlots) : nc % 8 == 0;
+}
+
+bool mf_interp_covers(const LevelD<float>& Lp, const LevelD<float>& Lc, int nc, bool sweep) {
   const MfD& T = Lp.mip;
-  if (!T.ok || nc % 8 != 0 || !shiftT || !interp_wpb(T, Lc.nt) || !has_case(T)) return false;
+  return T.ok && cols_ok(nc, sweep) && interp_wpb(T, Lc.nt) && has_case(T);
+}
+
+bool mf_interp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Sc, float2* Sp, int nc, int ldp,
+               int accum, const void* shiftT, hipStream_t s, const SweepSlots* sw) {
+  const MfD& T = Lp.mip;
+  if (!shiftT || !mf_interp_covers(Lp, Lc, nc, sw != nullptr)) return false;
+  if (sw && (!sw->on || sw->n * 4 != nc)) return false;
+  const SweepSlots none;
+  const SweepSlots& sv = sw ? *sw : none;
   const int mk = mk_of(T);
   const int rg = rg_valid(mk, Lp.rg_ip) ? Lp.rg_ip : rg_default(mk);
   const int nb = nt_block(T);
-#define X(a, b, c)                                                           \
-  if (nb == a && T.S2 == b && mk == c) {                                   \
-    launch_interp<a, b, c>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, rg, s);   \
-    return true;                                                             \
+#define X(a, b, c)                                                               \
+  if (nb == a && T.S2 == b && mk == c) {                                       \
+    launch_interp<a, b, c>(Lp, Lc, Sc, Sp, nc, ldp, accum, shiftT, rg, sv, s);   \
+    return true;                                                                 \
   }
   CM_MF_CASES(X)
 #undef X
   return false;
 }
 
-bool mf_covers(const LevelD<float>& Lp, int nc) {
+bool mf_covers(const LevelD<float>& Lp, int nc, bool sweep) {
   const MfD& T = Lp.mat;
-  return T.ok && nc % 8 == 0 && Lp.zg && anterp_wpb(T, Lp.nt) && has_case(T);
+  return T.ok && cols_ok(nc, sweep) && Lp.zg && anterp_wpb(T, Lp.nt, sweep) && has_case(T);
 }
 
 bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* Gp, float2* Gc, int nc, int ldp,
-               int add, const void* zg, hipStream_t s) {
+               int add, const void* zg, hipStream_t s, const SweepSlots* sw) {
   const MfD& T = Lp.mat;
-  if (!mf_covers(Lp, nc) || !zg) return false;
+  if (!mf_covers(Lp, nc, sw != nullptr) || !zg) return false;
+  if (sw && (!sw->on || sw->n * 4 != nc)) return false;
+  const SweepSlots none;
+  const SweepSlots& sv = sw ? *sw : none;
   const int mk = mk_of(T);
   const int rg = rg_valid(mk, Lp.rg_at) ? Lp.rg_at : rg_default(mk);
   const int nb = nt_block(T);
-#define X(a, b, c)                                                       \
-  if (nb == a && T.S2 == b && mk == c) {                               \
-    launch_anterp<a, b, c>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, rg, s);     \
-    return true;                                                         \
+#define X(a, b, c)                                                           \
+  if (nb == a && T.S2 == b && mk == c) {                                   \
+    launch_anterp<a, b, c>(Lp, Lc, Gp, Gc, nc, ldp, add, zg, rg, sv, s);     \
+    return true;                                                             \
   }
   CM_MF_CASES(X)
 #undef X

@@ -598,6 +598,16 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     Level& Lv = lev[l];
     const double kd = (o.k_sampling > 0 ? o.k_sampling : k) * std::sqrt(3.0) * Lv.a;
     Lv.L = (int)std::ceil(kd + 1.8 * std::pow(o.d0, 2.0 / 3.0) * std::cbrt(kd));
+    // translator truncation: eq. (30) at the sampling wavenumber, or for a
+    // sweep sharing its sampling (CM_FLAG_SWEEP_SHARED) at this plan's own
+    // k (the grid of the largest k integrates the smaller degree exactly,
+    // and a translator truncated beyond its own rule loses accuracy through
+    // the growth of the high-order Hankel terms)
+    Lv.Lt = Lv.L;
+    if ((o.flags & 2048u) && o.k_sampling > 0 && k < o.k_sampling) {
+      const double kdo = k * std::sqrt(3.0) * Lv.a;
+      Lv.Lt = std::min(Lv.L, (int)std::ceil(kdo + 1.8 * std::pow(o.d0, 2.0 / 3.0) * std::cbrt(kdo)));
+    }
     Lv.nt = Lv.L + 1;
     Lv.np = 2 * (Lv.L + 1);
     Lv.K = Lv.nt * Lv.np;
@@ -634,7 +644,7 @@ void Plan::build(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t 
     Level& Lv = lev[l];
     for (int32_t f : Lv.farR_off) off_used[l][f] = 1;
     for (int32_t f : Lv.far_off) off_used[l][f] = 1;
-    const int K = Lv.K, Lt = Lv.L;
+    const int K = Lv.K, Lt = Lv.Lt;
     std::vector<int> offs;
     Lv.off_compact.assign(kNoff, -1);
     for (int f = 0; f < kNoff; ++f)
@@ -884,7 +894,7 @@ std::string Plan::stats_json() const {
   for (int l = 0; l <= lf; ++l) {
     const Level& Lv = lev[l];
     if (l) s << ", ";
-    s << "{\"l\": " << l << ", \"a\": " << Lv.a << ", \"nbox\": " << Lv.nbox << ", \"L\": " << Lv.L
+    s << "{\"l\": " << l << ", \"a\": " << Lv.a << ", \"nbox\": " << Lv.nbox << ", \"L\": " << Lv.L << ", \"L_translator\": " << Lv.Lt
       << ", \"nt\": " << Lv.nt << ", \"np\": " << Lv.np << ", \"K\": " << Lv.K
       << ", \"far_pairs\": " << (Lv.far_src.size()) << ", \"farR_pairs\": " << (Lv.farR_src.size())
       << ", \"tile_sources\": " << Lv.tile_src.size() << ", \"tile64_sources\": " << Lv.tile64_src.size()

@@ -32,6 +32,7 @@ struct Level {
   int l = 0;
   double a = 0;
   int L = 0, nt = 0, np = 0, K = 0;          // truncation and sampling (nt x np)
+  int Lt = 0;                                 // translator truncation (L, or less in a shared-sampling sweep)
   std::vector<double> theta, wtheta;          // nt Gauss-Legendre nodes (theta ascending)
   int nbox = 0;
   std::vector<uint64_t> code;

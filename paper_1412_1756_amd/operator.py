@@ -37,13 +37,16 @@ class Operator:
     m2l_single_tiles=True makes single-column translations use the 16-box
     receiver tiles instead of the receiver-major kernel
     (CM_FLAG_M2L_SINGLE_TILES; same bits).  k may be a
-    sequence of wavenumbers (a sweep; apply's k_index picks one per column).
+    sequence of wavenumbers (a sweep; apply's k_index picks one per column);
+    sweep_shared=True gives all of them the sampling of the largest (or of
+    k_sampling) and runs FP32 Z / Z^H batches that span several wavenumbers
+    as one pass (CM_FLAG_SWEEP_SHARED).
     """
 
     def __init__(self, V, F, k, nlv, d0=3.0, interp_p=6, eta=None, max_cols=32, host_only=False,
                  deriv=False, check_coverage=False, matrix_cores=True, near_fp32=False, wide_near=False,
                  autotune=False, r_standard=False, k_sampling=None, verbose=False, m2l_tile16=False,
-                 m2l_single_tiles=False, stream=None):
+                 m2l_single_tiles=False, sweep_shared=False, stream=None):
         L = lib()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -65,7 +68,8 @@ class Operator:
                    | (_lib.CM_FLAG_R_STANDARD if r_standard else 0)
                    | (_lib.CM_FLAG_VERBOSE if verbose else 0)
                    | (_lib.CM_FLAG_M2L_TILE16 if m2l_tile16 else 0)
-                   | (_lib.CM_FLAG_M2L_SINGLE_TILES if m2l_single_tiles else 0))
+                   | (_lib.CM_FLAG_M2L_SINGLE_TILES if m2l_single_tiles else 0)
+                   | (_lib.CM_FLAG_SWEEP_SHARED if sweep_shared else 0))
         kk = np.atleast_1d(np.asarray(k, dtype=np.float64)).copy()
         h = C.c_void_p()
         s = self._stream_ptr(stream) if not host_only else None

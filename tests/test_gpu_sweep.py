@@ -64,6 +64,66 @@ def test_sweep_columns_equal_single_k_handles(torch_cuda, dtype):
         sw.apply(X, k_index=np.full(12, 3, np.int32))
 
 
+def test_sweep_shared_one_pass_matches_per_wavenumber(torch_cuda):
+    """CM_FLAG_SWEEP_SHARED: a Z or Z^H batch spanning several wavenumbers
+    runs as one pass (leaf stages per four-column slot, one tree pass over all
+    columns with per-slot translators and shift phases).  Each column must
+    equal, to FP32 rounding, the same column through a single-wavenumber
+    handle with the same discretisation (k_sampling = the largest k, the
+    translators truncated at their own k): the two
+    routes take the same tables, but the leaf-stage kernels differ (vector
+    ALU per slot against the matrix cores), so the sums round differently.
+    The bound is three times the distance between the single handle's
+    matrix-core and vector-ALU routes (the FP32 rounding scale of this
+    operator; measured 2e-5 .. 1.5e-4 across the band, the largest at 0.9 k
+    where the sampling of 1.1 k makes the translators large).  Uneven column
+    counts per wavenumber go through the gather into slots (padding columns);
+    other ops take the per-wavenumber route and match the single handles bit
+    for bit."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = workloads.icosphere(4, 1.0)
+    ks = [0.9 * K0, K0, 1.1 * K0]
+    sw = Operator(V, F, ks, nlv=4, max_cols=16, sweep_shared=True, **ACC32)
+    st = sw.stats()
+    assert st["sweep_tables"] == 3 and abs(st["k_sampling"] - ks[2]) < 1e-12
+    # single handles with the sweep's discretisation: sampling at the largest
+    # k, translators truncated at their own k (sweep_shared with one k)
+    same = dict(nlv=4, max_cols=16, k_sampling=ks[2], sweep_shared=True, **ACC32)
+    singles = [Operator(V, F, k, **same) for k in ks]
+    vec = [Operator(V, F, k, matrix_cores=False, **same) for k in ks]
+    X = torch.tensor(workloads.cn01_block(sw.N, 12, 41), dtype=torch.complex64, device="cuda")
+    layouts = {"interleaved": np.array([j % 3 for j in range(12)], dtype=np.int32),
+               "grouped": np.repeat(np.arange(3, dtype=np.int32), 4),
+               "uneven": np.array([0, 0, 0, 0, 0, 1, 1, 2, 2, 2], dtype=np.int32)}
+    calls = 0
+    for name, kidx in layouts.items():
+        Xc = X[:, :len(kidx)].contiguous()
+        for opname in ("Z", "ZH", "R"):
+            Y = sw.apply(Xc, op=opname, k_index=kidx).cpu().numpy()
+            if opname != "R":
+                calls += 1
+            for i, op in enumerate(singles):
+                cols = np.nonzero(kidx == i)[0]
+                Xp = torch.zeros((Xc.shape[0], 8), dtype=Xc.dtype, device="cuda")
+                Xp[:, :len(cols)] = Xc[:, cols]
+                ref = op.apply(Xp, op=opname)[:, :len(cols)].cpu().numpy()
+                e = float(np.linalg.norm(Y[:, cols] - ref) / np.linalg.norm(ref))
+                if opname == "R":
+                    assert e == 0.0
+                    continue
+                alt = vec[i].apply(Xp, op=opname)[:, :len(cols)].cpu().numpy()
+                scale = float(np.linalg.norm(alt - ref) / np.linalg.norm(ref))
+                print(f"one-pass sweep {name} op={opname} k={ks[i] / K0:.2f} k0: {e:.1e} "
+                      f"(matrix-core vs vector-ALU single handle: {scale:.1e})", flush=True)
+                assert e < max(3 * scale, 1e-5)
+            assert sw.stats()["sweep_one_pass_calls"] == calls
+    # a batch at one wavenumber runs in place through that wavenumber's handle
+    Y1 = sw.apply(X, k_index=np.full(12, 1, np.int32)).cpu().numpy()
+    assert colerr(Y1, singles[1].apply(X).cpu().numpy()) == 0.0
+    assert sw.stats()["sweep_one_pass_calls"] == calls
+
+
 @pytest.fixture(scope="module")
 def band():
     """The band's wavenumbers and, per wavenumber, eight oracle rows of Z."""
@@ -82,11 +142,11 @@ def band():
     return V, F, ks, rows, Zr
 
 
-def _band_errors(torch, band, acc, ncols, dt, seed):
+def _band_errors(torch, band, acc, ncols, dt, seed, **kw):
     from paper_1412_1756_amd import Operator
     V, F, ks, rows, Zr = band
-    print(f"building the 8-wavenumber handle {acc} (8 plans and near-field fills)", flush=True)
-    sw = Operator(V, F, ks, nlv=6, max_cols=ncols, **acc)
+    print(f"building the 8-wavenumber handle {acc} {kw} (8 plans and near-field fills)", flush=True)
+    sw = Operator(V, F, ks, nlv=6, max_cols=ncols, **acc, **kw)
     N = sw.N
     Xh = workloads.cn01_block(N, ncols, seed)
     kidx = np.arange(ncols, dtype=np.int32) % 8
@@ -105,6 +165,14 @@ def test_sweep_config4_fp32_batch(torch_cuda, band):
     """A block of 32 right-hand sides, column j at wavenumber j mod 8, FP32
     far field."""
     errs = _band_errors(torch_cuda, band, BAND32, 32, torch_cuda.complex64, 100)
+    assert max(errs) < 5e-4
+
+
+def test_sweep_config4_one_pass(torch_cuda, band):
+    """The same block through the one-pass route (CM_FLAG_SWEEP_SHARED: the
+    eight wavenumbers sampled at 1.1 k0, each translator truncated by eq. (30)
+    at its own k, slots of four columns)."""
+    errs = _band_errors(torch_cuda, band, BAND32, 32, torch_cuda.complex64, 100, sweep_shared=True)
     assert max(errs) < 5e-4
 
 

@@ -136,6 +136,26 @@ def test_config2_plan_sizes():
     assert [lv[l]["far_pairs"] for l in range(2, 6)] == [2504, 12216, 54000, 207456]
 
 
+def test_shared_sweep_sampling_and_translator_truncation():
+    """CM_FLAG_SWEEP_SHARED: every wavenumber's plan samples at the largest k
+    of the sweep (eq. (30) at k_max sets L and the grid) while its
+    translators are truncated by eq. (30) at its own k; without the flag a
+    k_sampling freezes both."""
+    V, F = workloads.icosphere(3, 0.5)
+    from oracle.translators import truncation_L
+    ks = [0.9 * 2 * np.pi, 1.1 * 2 * np.pi]
+    for shared in (True, False):
+        from paper_1412_1756_amd import Operator
+        kw = dict(sweep_shared=True) if shared else dict(k_sampling=ks[1])
+        op = Operator(V, F, ks, nlv=3, d0=4.5, host_only=True, **kw)
+        st = op.stats()
+        assert abs(st["k_sampling"] - ks[1]) < 1e-12
+        lv = st["levels"][2]
+        assert lv["L"] == truncation_L(ks[1], lv["a"], 4.5)
+        assert lv["L_translator"] == (truncation_L(ks[0], lv["a"], 4.5) if shared else lv["L"])
+        assert lv["L_translator"] <= lv["L"]
+
+
 def test_truncation_rule_per_level():
     V, F = workloads.icosphere(3, 0.5)
     from oracle.translators import truncation_L
