@@ -1809,13 +1809,21 @@ void dev_apply_sweep(Dev& d0, const Plan& P0, Dev* const* dk, const Plan* const*
                        (const CR*)x + 4 * j, ld, 4, d0.perm, xs(j), N, conj, kSB);
   stage_end(d0, s);
   fork_to(s, sA, 0);
+  // the leaf stages of all slots in one launch each (grid z = slot; the
+  // wavenumbers share tree and near-field structure, only the values differ)
+  Dev& dz = *dk[sw.k[0]];
+  SlotTabs tn;
+  for (int j = 0; j < sw.n; ++j) tn.t0[j] = dk[sw.k[j]]->Zn;
+  tn.in_off = tn.out_off = 2 * N * kSB;   // floats per slot block
   stage_begin(d0, sA, 1);
-  for (int j = 0; j < sw.n; ++j) near_product<float>(*dk[sw.k[j]], *Pk[sw.k[j]], xs(j), ys(j), kSB, 0, false, sA);
+  if (!mf_near<float>(dz.row_ptr, dz.box_start, dz.bcol_ptr, dz.bcol, dz.self_off, dz.Zn, xs(0), ys(0), dz.nleaf,
+                      dz.max_box, dz.max_near_cols, kSB, 0, sA, &tn, sw.n))
+    throw Error(-7, "sweep batch: near-field kernel does not cover the leaf boxes");
   stage_end(d0, sA);
   if (fork) chk(hipEventRecord(d0.fork_ev[1], sA), "hipEventRecord");
   auto m2l = [&](hipStream_t ss, int l) {
     LevelD<float>& Lv = d0.f32.lev[l];
-    constexpr int RT = 8, PD = 2;
+    constexpr int RT = 8, PD = 3;
     const int qb = 256 / sw.n;
     const dim3 grid((Lv.ntile + 7) / 8 * 8, (Lv.K + qb - 1) / qb, kTile / RT);
     stage_begin(d0, ss, 4 + 10 * l);
@@ -1825,11 +1833,12 @@ void dev_apply_sweep(Dev& d0, const Plan& P0, Dev* const* dk, const Plan* const*
     stage_end(d0, ss);
   };
   stage_begin(d0, s, 2);
-  for (int j = 0; j < sw.n; ++j) {
-    Dev& dj = *dk[sw.k[j]];
-    mf_aggregate(dj.f32.V, (const float2*)xs(j), kSB, (float2*)d0.S[lf] + 4 * j, nc, dj.box_start, dj.nleaf,
-                 P0.lev[lf].K, kSB, s, 4);
-  }
+  SlotTabs ta;
+  for (int j = 0; j < sw.n; ++j) ta.t0[j] = dk[sw.k[j]]->f32.V;
+  ta.in_off = 2 * N * kSB;   // xi floats per slot block
+  ta.out_off = 8;            // S floats per slot (four complex columns)
+  mf_aggregate(dz.f32.V, (const float2*)xs(0), kSB, (float2*)d0.S[lf], nc, dz.box_start, dz.nleaf, P0.lev[lf].K, kSB,
+               s, 4, &ta, sw.n);
   stage_end(d0, s);
   fork_to(s, sB, 2);
   m2l(sB, lf);
@@ -1860,13 +1869,18 @@ void dev_apply_sweep(Dev& d0, const Plan& P0, Dev* const* dk, const Plan* const*
   }
   if (fork) chk(hipStreamWaitEvent(s, d0.fork_ev[1], 0), "hipStreamWaitEvent");
   stage_begin(d0, s, 6);
+  SlotTabs td;
   for (int j = 0; j < sw.n; ++j) {
-    Dev& dj = *dk[sw.k[j]];
-    if (!mf_disagg(dj.f32.V, (const float2*)d0.G[lf] + 4 * j, nc, (const float*)dj.f32.qwc,
-                           (const float2*)ys(j), dj.box_start, dj.nleaf, dj.max_box, d0.perm, P0.lev[lf].K, kSB,
-                           (float2*)y + 4 * j, ld, conj, s, 4, kSB))
-      throw Error(-7, "sweep batch: leaf boxes too large for the matrix-core disaggregation");
+    td.t0[j] = dk[sw.k[j]]->f32.V;
+    td.t1[j] = dk[sw.k[j]]->f32.qwc;
   }
+  td.in_off = 8;               // G floats per slot
+  td.aux_off = 2 * N * kSB;    // near-field result floats per slot block
+  td.out_off = 8;              // y floats per slot
+  if (!mf_disagg(dz.f32.V, (const float2*)d0.G[lf], nc, (const float*)dz.f32.qwc, (const float2*)ys(0),
+                 dz.box_start, dz.nleaf, dz.max_box, d0.perm, P0.lev[lf].K, kSB, (float2*)y, ld, conj, s, 4, kSB,
+                 &td, sw.n))
+    throw Error(-7, "sweep batch: leaf boxes too large for the matrix-core disaggregation");
   stage_end(d0, s);
   chk(hipGetLastError(), "sweep apply launch");
   ++d0.sw_calls;
@@ -1874,7 +1888,7 @@ void dev_apply_sweep(Dev& d0, const Plan& P0, Dev* const* dk, const Plan* const*
 
 bool sweep_covers(const Dev& d0, const Plan& P0, int nc) {
   if (d0.sw_nk <= 0 || nc % 4 != 0 || nc / 4 > kMaxSlots || nc > d0.max_cols) return false;
-  if ((P0.opt.flags & CM_FLAG_NO_MATRIX_CORES) || d0.max_box > 64) return false;
+  if ((P0.opt.flags & CM_FLAG_NO_MATRIX_CORES) || d0.max_box > 64 || d0.max_near_cols > 4096) return false;
   for (int l = 2; l < d0.lf; ++l)
     if (!mf_interp_covers(d0.f32.lev[l], d0.f32.lev[l + 1], nc, true) || !mf_covers(d0.f32.lev[l], nc, true) ||
         !d0.f32.lev[l].sw_shiftT || !d0.f32.lev[l].sw_zg)

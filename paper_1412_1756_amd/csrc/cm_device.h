@@ -38,6 +38,19 @@ struct SweepSlots {
   int64_t stride = 0;
 };
 
+// Leaf stages of a one-pass sweep launched for all slots at once: slot z > 0
+// takes the tables t0[z], t1[z] and the kernel's arrays moved by z times the
+// given element offsets (slot 0: the launch arguments).  The near field puts
+// the slot on grid z; aggregation and disaggregation make it the fastest
+// block index (n slots), so that the slots' 32-byte pieces of a box's
+// pattern rows are written (read) back to back while the lines are in L2.
+struct SlotTabs {
+  const void* t0[kMaxSlots] = {};
+  const void* t1[kMaxSlots] = {};
+  int64_t in_off = 0, out_off = 0, aux_off = 0;
+  int n = 1;
+};
+
 // Matrix-core interpolation tables of one level pair (FP32 path), see MfTab.
 struct MfD {
   int ok = 0, NT = 0, S2 = 0, half = 0, nchunk = 0, kmax = 0, ktmax = 0;
@@ -174,17 +187,22 @@ bool mf_anterp(const LevelD<float>& Lp, const LevelD<float>& Lc, const float2* G
 // ncv (< 0: nc): only the first ncv columns are read from x / G and written
 // to S / y (the rest of the column tiles count as zero); ldyi (< 0: nc): the
 // row stride of the near-field result yi.
+// st, nslot: a sweep's slots in one launch (aggregation: t0 = V, offsets
+// in = xi, out = S; disaggregation: t0 = V, t1 = qwc, in = G, aux = yi,
+// out = y; element offsets in floats).
 bool mf_aggregate(const void* V, const float2* xi, int ldx, float2* S, int ldS, const int32_t* box_start, int nbox,
-                  int K, int nc, hipStream_t s, int ncv = -1);
+                  int K, int nc, hipStream_t s, int ncv = -1, const SlotTabs* st = nullptr, int nslot = 1);
 bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const float2* yi, const int32_t* box_start,
                int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
-               hipStream_t s, int ncv = -1, int ldyi = -1);
+               hipStream_t s, int ncv = -1, int ldyi = -1, const SlotTabs* st = nullptr, int nslot = 1);
 // Near-field product on the FP64 matrix cores (x, y complex R; nc % 8 == 0,
 // nc <= 64, leaf boxes of at most 64 unknowns); mode 0 Z, 1 Re Z self box, 2 Im Z.
+// (st, nslot: a sweep's slots in one launch, t0 = near-field values, in /
+// out = xi / yi in elements of R)
 template <typename R>
 bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
              const int32_t* self_off, const double2* Zn, const void* xi, void* yi, int nleaf, int max_box,
-             int max_cols_box, int nc, int mode, hipStream_t s);
+             int max_cols_box, int nc, int mode, hipStream_t s, const SlotTabs* st = nullptr, int nslot = 1);
 // the same on FP32 near-field values and FP32 matrix cores (complex float x, y)
 bool mf_near32(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
                const int32_t* self_off, const float2* Zn, const float2* xi, float2* yi, int nleaf,

@@ -419,10 +419,16 @@ template <int MTW, int NTL>
 __global__ void __launch_bounds__(256) k_aggregate_mf(const float2* __restrict__ V, const float* __restrict__ xi,
                                                       int ldx, float* __restrict__ S, int ldS,
                                                       const int32_t* __restrict__ box_start, int nbox, int K2, int nc,
-                                                      int wpb, int cvf) {
+                                                      int wpb, int cvf, SlotTabs st) {
+  const int z = (int)blockIdx.x % st.n, bx = (int)blockIdx.x / st.n;
+  if (z) {
+    V = (const float2*)st.t0[z];
+    xi += z * st.in_off;
+    S += z * st.out_off;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const int wid = blockIdx.x * 4 + w;
+  const int wid = bx * 4 + w;
   const int box = wid / wpb, m0 = (wid - box * wpb) * MTW * 16;
   if (box >= nbox || m0 >= K2) return;
   const int i0 = box_start[box], i1 = box_start[box + 1];
@@ -488,12 +494,20 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
                                                    const int32_t* __restrict__ box_start,
                                                    const int32_t* __restrict__ perm, int K, int nc,
                                                    float* __restrict__ y, int64_t ld, int conj_out, int cvf,
-                                                   int ldyi) {
+                                                   int ldyi, SlotTabs st) {
+  const int z = (int)blockIdx.x % st.n;
+  if (z) {
+    V = (const float2*)st.t0[z];
+    qwc = (const float*)st.t1[z];
+    G += z * st.in_off;
+    yi += z * st.aux_off;
+    y += z * st.out_off;
+  }
   constexpr int NR = MTU * 2 * 4;     // floats per lane of one reduction round (two column tiles)
   extern __shared__ float red[];      // [4 waves][NR][64]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const int box = blockIdx.x;
+  const int box = (int)blockIdx.x / st.n;
   const int i0 = box_start[box], i1 = box_start[box + 1];
   const int K2 = 2 * K, nks = (K2 + 3) / 4;
   const int ks0 = w * nks / 4, ks1 = (w + 1) * nks / 4;
@@ -562,38 +576,43 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
 }
 
 bool mf_aggregate(const void* V, const float2* xi, int ldx, float2* S, int ldS, const int32_t* box_start, int nbox,
-                  int K, int nc, hipStream_t s, int ncv) {
-  if (nc % 8 != 0) return false;
+                  int K, int nc, hipStream_t s, int ncv, const SlotTabs* st, int nslot) {
+  if (nc % 8 != 0 || nslot < 1 || nslot > kMaxSlots || (nslot > 1 && !st)) return false;
   if (ncv < 0) ncv = nc;
+  SlotTabs sv = st ? *st : SlotTabs();
+  sv.n = nslot;
   constexpr int MTW = 3;
   const int K2 = 2 * K;
   const int wpb = (K2 + 16 * MTW - 1) / (16 * MTW);
   const int64_t waves = (int64_t)nbox * wpb;
   // four column tiles per pass over the leaf patterns, one for a single tile
   // (no matrix-core steps on empty tiles)
+  const dim3 grid((unsigned)((waves + 3) / 4 * nslot));
   if (nc <= 8)
-    hipLaunchKernelGGL((k_aggregate_mf<MTW, 1>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                       (const float2*)V, (const float*)xi, ldx, (float*)S, ldS, box_start, nbox, K2, nc, wpb, 2 * ncv);
+    hipLaunchKernelGGL((k_aggregate_mf<MTW, 1>), grid, dim3(256), 0, s, (const float2*)V, (const float*)xi, ldx,
+                       (float*)S, ldS, box_start, nbox, K2, nc, wpb, 2 * ncv, sv);
   else
-    hipLaunchKernelGGL((k_aggregate_mf<MTW, 4>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                       (const float2*)V, (const float*)xi, ldx, (float*)S, ldS, box_start, nbox, K2, nc, wpb, 2 * ncv);
+    hipLaunchKernelGGL((k_aggregate_mf<MTW, 4>), grid, dim3(256), 0, s, (const float2*)V, (const float*)xi, ldx,
+                       (float*)S, ldS, box_start, nbox, K2, nc, wpb, 2 * ncv, sv);
   return true;
 }
 
 bool mf_disagg(const void* V, const float2* G, int ldp, const float* qwc, const float2* yi, const int32_t* box_start,
                int nbox, int max_box, const int32_t* perm, int K, int nc, float2* y, int64_t ld, int conj,
-               hipStream_t s, int ncv, int ldyi) {
-  if (nc % 8 != 0 || max_box > 64) return false;
+               hipStream_t s, int ncv, int ldyi, const SlotTabs* st, int nslot) {
+  if (nc % 8 != 0 || max_box > 64 || nslot < 1 || nslot > kMaxSlots || (nslot > 1 && !st)) return false;
   if (ncv < 0) ncv = nc;
   if (ldyi < 0) ldyi = nc;
+  SlotTabs sv = st ? *st : SlotTabs();
+  sv.n = nslot;
   // four column tiles per pass over the leaf patterns (each read once for
   // 32 columns), reduced two tiles at a time: the LDS buffer (4 waves x MTU
   // x 2 x 4 floats per lane) leaves room for four blocks per CU
   // (one column tile per pass for a single tile)
 #define CM_DIS(MTU, NTL)                                                                                       \
-  hipLaunchKernelGGL((k_disagg_mf<MTU, NTL>), dim3(nbox), dim3(256), (size_t)4 * MTU * 2 * 4 * 64 * 4, s,     \
-                     (const float2*)V, (const float*)G, ldp, qwc, (const float*)yi, box_start, perm, K, nc,   \
-                     (float*)y, ld, conj, 2 * ncv, ldyi)
+  hipLaunchKernelGGL((k_disagg_mf<MTU, NTL>), dim3(nbox * nslot), dim3(256), (size_t)4 * MTU * 2 * 4 * 64 * 4,   \
+                     s, (const float2*)V, (const float*)G, ldp, qwc, (const float*)yi, box_start, perm, K, nc,    \
+                     (float*)y, ld, conj, 2 * ncv, ldyi, sv)
 #define CM_DIS_N(MTU)  \
   if (nc <= 8)         \
     CM_DIS(MTU, 1);    \
@@ -642,7 +661,12 @@ __global__ void __launch_bounds__(256) k_near_mf(const int64_t* __restrict__ row
                                                  const int32_t* __restrict__ bcol,
                                                  const int32_t* __restrict__ self_off, const double2* __restrict__ Zn,
                                                  const R* __restrict__ xi, R* __restrict__ yi, int nleaf, int nc,
-                                                 int xcap) {
+                                                 int xcap, SlotTabs st) {
+  if (blockIdx.z) {
+    Zn = (const double2*)st.t0[blockIdx.z];
+    xi += blockIdx.z * st.in_off;
+    yi += blockIdx.z * st.out_off;
+  }
   extern __shared__ int32_t xoff_all[];   // per wave: the box's column rows as offsets into x (floats)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
@@ -857,8 +881,11 @@ bool mf_near32(const int64_t* row_ptr, const int32_t* box_start, const int32_t* 
 template <typename R>
 bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bcol_ptr, const int32_t* bcol,
              const int32_t* self_off, const double2* Zn, const void* xi, void* yi, int nleaf, int max_box,
-             int max_cols_box, int nc, int mode, hipStream_t s) {
+             int max_cols_box, int nc, int mode, hipStream_t s, const SlotTabs* st, int nslot) {
   if (nc % 8 != 0 || nc > 64 || max_cols_box > 4096) return false;
+  if (nslot < 1 || nslot > kMaxSlots || (nslot > 1 && !st)) return false;
+  const SlotTabs none;
+  const SlotTabs& sv = st ? *st : none;
   const int xcap = (max_cols_box + 8 + 7) / 8 * 8;
   const size_t sh = (size_t)4 * xcap * sizeof(int32_t);
   (void)max_box;
@@ -870,9 +897,9 @@ bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bc
 #define CM_NEAR_W(M, NW)                                                                                       \
   {                                                                                                            \
     constexpr int BPB = 4 / ((2 / MT) * (4 / NW));                                                             \
-    const dim3 grid((unsigned)((nleaf + BPB - 1) / BPB), (unsigned)((nc + 31) / 32));                          \
+    const dim3 grid((unsigned)((nleaf + BPB - 1) / BPB), (unsigned)((nc + 31) / 32), (unsigned)nslot);        \
     hipLaunchKernelGGL((k_near_mf<R, M, MT, NW>), grid, dim3(256), sh, s, row_ptr, box_start, bcol_ptr, bcol,  \
-                       self_off, Zn, (const R*)xi, (R*)yi, nleaf, nc, xcap);                                   \
+                       self_off, Zn, (const R*)xi, (R*)yi, nleaf, nc, xcap, sv);                               \
   }
 #define CM_NEAR(M)        \
   if (nc <= 8)            \
@@ -891,9 +918,11 @@ bool mf_near(const int64_t* row_ptr, const int32_t* box_start, const int32_t* bc
   return true;
 }
 template bool mf_near<float>(const int64_t*, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
-                             const double2*, const void*, void*, int, int, int, int, int, hipStream_t);
+                             const double2*, const void*, void*, int, int, int, int, int, hipStream_t,
+                             const SlotTabs*, int);
 template bool mf_near<double>(const int64_t*, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
-                              const double2*, const void*, void*, int, int, int, int, int, hipStream_t);
+                              const double2*, const void*, void*, int, int, int, int, int, hipStream_t,
+                              const SlotTabs*, int);
 
 static void lds_limit(const void* f, size_t bytes) {
   if (bytes > 64 * 1024) {
