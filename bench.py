@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no error, no CPU baseline)")
     ap.add_argument("--no-eigs", action="store_true", help="skip the eigenmodes-per-hour measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 8-wavenumber sweep measurement")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the one-pass 8-wavenumber sweep (profiling of its kernels): prints its record")
     ap.add_argument("--no-d0-3", action="store_true", help="skip the 3-digit truncation measurement")
     ap.add_argument("--no-sai", action="store_true", help="skip the SAI build and apply measurement")
     ap.add_argument("--no-cmp", action="store_true",
@@ -384,6 +386,9 @@ def main():
     V, F, spec = workloads.workload(name)
     k = spec["k"]
     dev = torch.device("cuda:0")
+    if a.sweep_only:
+        print(json.dumps({"sweep_8k": sweep_rate(V, F, k, a.ncols, a.steps, a.d0, a.p)}), flush=True)
+        return
     op32 = Operator(V, F, k, nlv=a.nlv, d0=a.d0, interp_p=a.p, max_cols=max(a.ncols, 1), wide_near=a.wide,
                     autotune=not a.no_autotune)
     op64 = Operator(V, F, k, nlv=a.nlv, d0=a.d0_64, interp_p=a.p_64, max_cols=1, wide_near=not a.narrow_64)
