@@ -508,8 +508,10 @@ __global__ void __launch_bounds__(256) k_m2l(const int32_t* __restrict__ tptr, c
 // Translation of a single column, receiver-major: one wave per (receiver
 // box, 64 directions), walking the receiver's far list (sorted by source, so
 // each receiver sums its sources in the order of the tile kernel and gives
-// the same bits) in groups of kGP entries whose source-pattern and translator
-// loads are all issued before the group is applied.  Without the tile's
+// the same bits) in groups of kGP = 8 entries whose source-pattern and
+// translator loads (24 per lane) are all issued before the group is applied
+// (4 entries: 0.305 ms at level 5 of the FP64 vector on the 122,880-unknown
+// sphere, 8: 0.283 ms, 12 or 16: no faster).  Without the tile's
 // register reuse each pair reads its source rows again, but a single
 // column's patterns of a level (tens of MB) stay in L2 and the MALL, and
 // every wave has independent work: the tile kernel has few blocks per level
@@ -521,7 +523,7 @@ __global__ void __launch_bounds__(256) k_m2l_pairs(const int32_t* __restrict__ f
                                                    const int32_t* __restrict__ foff, const C2<R>* __restrict__ T,
                                                    const C2<R>* __restrict__ S, C2<R>* __restrict__ G, int nbox,
                                                    int K, int nqc, int ldp, int accum) {
-  constexpr int kGP = 4;
+  constexpr int kGP = 8;
   const int per_xcd = gridDim.x / 8;
   const int lb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   const int wid = lb * 4 + (int)(threadIdx.x >> 6);
@@ -1016,13 +1018,16 @@ __global__ void __launch_bounds__(256) k_interp_up(const C2<R>* __restrict__ Sc,
   }
 }
 
-// Per-parent anterpolation: the block stages its parent's pattern once, then
-// for each child applies the conjugated shift (LDS -> LDS), the phi-transpose
-// stencil (LDS -> LDS) and the theta-transpose stencil (LDS -> child, RMW).
+// Anterpolation, one block per child box: the block stages its parent's
+// pattern, applies the child's conjugated shift (LDS -> LDS), the
+// phi-transpose stencil (LDS -> LDS) and the theta-transpose stencil (LDS ->
+// child, RMW).  (One block per parent looping over its children gives the
+// same sums but a quarter of the blocks: 112 blocks for the 56 level-2 boxes
+// of the 122,880-unknown sphere.)
 // LDS: P0 [Kp][cs], A [Kp][cs], B [ntp][npc][cs], stencil tables.
 template <typename R>
 __global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ Gp, C2<R>* __restrict__ Gc,
-                                                     const int32_t* __restrict__ child_ptr,
+                                                     const int32_t* __restrict__ parent,
                                                      const int8_t* __restrict__ octant, LevelD<R> P, int Kc, int nc,
                                                      int cs, int ldp) {
   extern __shared__ unsigned char smem_raw[];
@@ -1047,7 +1052,7 @@ __global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ G
     thI[e] = P.tht_idx[e] | (P.tht_ref[e] << 30);
     thW[e] = P.tht_ref[e] ? -P.tht_w[e] : P.tht_w[e];
   }
-  const int m = blockIdx.x, c0 = blockIdx.y * cs, comp = blockIdx.z;
+  const int ch = blockIdx.x, m = parent[ch], c0 = blockIdx.y * cs, comp = blockIdx.z;
   const int cw = min(cs, nc - c0);
   const int hc = npc / 2;
   const C2<R>* g = Gp + ((int64_t)m * 2 + comp) * Kp * ldp + c0;
@@ -1056,7 +1061,7 @@ __global__ void __launch_bounds__(256) k_anterp_down(const C2<R>* __restrict__ G
     const int c = e % cs, q = e / cs;
     P0[e] = (c < cw) ? g[(int64_t)q * ldp + c] : mk<R>(0, 0);
   }
-  for (int ch = child_ptr[m]; ch < child_ptr[m + 1]; ++ch) {
+  {
     const C2<R>* shift = reinterpret_cast<const C2<R>*>(P.shift) + octant[ch] * Kp;
     __syncthreads();
     for (int e = threadIdx.x; e < Kp * cs; e += blockDim.x) {
@@ -1586,8 +1591,8 @@ struct Stages {
       const int cs = std::max(1, std::min(nc, (48 * 1024 - tables) / per_col));   // >= 3 blocks per CU
       const size_t sh = (size_t)per_col * cs + tables;
       set_lds_limit((const void*)k_anterp_down<R>, sh);
-      hipLaunchKernelGGL(k_anterp_down<R>, dim3(Lp.nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s, Gp, Gc,
-                         Lp.child_ptr, pd.lev[l + 1].octant, Lp, Kc, nc, cs, ldp);
+      hipLaunchKernelGGL(k_anterp_down<R>, dim3(pd.lev[l + 1].nbox, (nc + cs - 1) / cs, 2), dim3(256), sh, s, Gp,
+                         Gc, pd.lev[l + 1].parent, pd.lev[l + 1].octant, Lp, Kc, nc, cs, ldp);
     } else {
       // each block takes a chunk of child rows and stages the transposed phi
       // step of only the parent rows they read (a contiguous range); the
