@@ -36,6 +36,7 @@ struct SweepSlots {
   int n = 0;
   int32_t k[kMaxSlots] = {};
   int64_t stride = 0;
+  int zg_global = 0;   // anterpolation: read the slot's phase values from global memory (set by the launcher)
 };
 
 // Leaf stages of a one-pass sweep launched for all slots at once: slot z > 0

@@ -264,7 +264,9 @@ __global__ void __launch_bounds__(256, kW) k_interp_mf(const float* __restrict__
 // kmax], in K-step key order) and the theta tables in LDS; the parent-row
 // loads are double-buffered in groups of kRG rows.
 // A sweep batch (sw) maps column tiles to slots as the interpolation does;
-// each wave then stages its slot's phase values.
+// each wave then needs its own slot's phase values: a per-wave LDS copy, or
+// where a chunk's table is small (sw.zg_global) reads straight from global
+// memory (L1/L2), which saves the copies' LDS and occupancy.
 template <int NT, int S2, int kMK, int kRG, int kW>
 __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__ Gp, float* __restrict__ Gc,
                                                    const int32_t* __restrict__ parent,
@@ -282,7 +284,8 @@ __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__
   int* tcode = reinterpret_cast<int*>(lds);
   float* tAl = lds + NT * T.ktmax * 4;
   float2* Z0 = reinterpret_cast<float2*>(tAl + NT * T.ktmax * 64);
-  const int nz = sw.on ? (int)(blockDim.x >> 6) : 1;   // phase tables in LDS: one per wave in a sweep batch
+  const bool zl = sw.on && !sw.zg_global;                          // per-wave LDS copies
+  const int nz = sw.on ? (zl ? (int)(blockDim.x >> 6) : 0) : 1;   // phase tables in LDS
   stage_theta_tables(T, t0, NT, tcode, tAl);
   if (!sw.on) {
     const float4* zs = reinterpret_cast<const float4*>(zg + ((size_t)c * 8 + octant[ch]) * ntp * kz);
@@ -293,12 +296,11 @@ __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__
   const int cpt = nc >> 3;
   const int tile = blockIdx.y * (int)(blockDim.x >> 6) + w;
   if (tile >= (sw.on ? sw.n : 2 * cpt)) return;
-  float2* Z = Z0;
-  if (sw.on) {
-    Z = Z0 + (size_t)w * ntp * kz;
-    const float4* zs = reinterpret_cast<const float4*>(zg + (int64_t)sw.k[tile] * sw.stride +
-                                                       ((size_t)c * 8 + octant[ch]) * ntp * kz);
-    float4* zd = reinterpret_cast<float4*>(Z);
+  const float2* zslot =
+      sw.on ? zg + (int64_t)sw.k[tile] * sw.stride + ((size_t)c * 8 + octant[ch]) * ntp * kz : zg;
+  if (zl) {
+    const float4* zs = reinterpret_cast<const float4*>(zslot);
+    float4* zd = reinterpret_cast<float4*>(Z0 + (size_t)w * ntp * kz);
     for (int e = lane; e < ntp * kz / 2; e += 64) zd[e] = zs[e];
     wave_lds_sync();
   }
@@ -332,7 +334,7 @@ __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__
   const float* par = Gp + (int64_t)m * 2 * Kp * ld2;
   const int64_t rstride = (int64_t)npp * ld2;
   const float sg = (n & 1) ? -1.f : 1.f;   // (sx - i sy)(re + i im): re lane +sy*im, im lane -sy*re
-  auto phiT_rows = [&](const float (&v)[kRG][kMK], int r0) {
+  auto phiT_rows = [&](const float2* Z, const float (&v)[kRG][kMK], int r0) {
     f4 d[kRG];
 #pragma unroll
     for (int r = 0; r < kRG; ++r) d[r] = f4{0.f, 0.f, 0.f, 0.f};
@@ -356,18 +358,26 @@ __global__ void __launch_bounds__(256, kW) k_anterp_mf(const float* __restrict__
           if (4 * g + j < S) O[(r0 + r) * RS + (4 * g + j) * 16 + n] = d[r][j];
       }
   };
-  // transposed phi step over the parent rows, double-buffered row groups
+  // transposed phi step over the parent rows, double-buffered row groups;
+  // the phase values come from the block's LDS copy, or in a sweep batch
+  // (one wavenumber per wave) straight from the slot's table (L1/L2)
   float va[kRG][kMK], vb[kRG][kMK];
-  load_rows(va, par, 0, ntp, rstride, poff, nk);
-  for (int tp0 = 0; tp0 < ntp; tp0 += 2 * kRG) {
-    const bool more = tp0 + kRG < ntp;
-    if (more) load_rows(vb, par, tp0 + kRG, ntp, rstride, poff, nk);
-    phiT_rows(va, tp0);
-    if (more) {
-      if (tp0 + 2 * kRG < ntp) load_rows(va, par, tp0 + 2 * kRG, ntp, rstride, poff, nk);
-      phiT_rows(vb, tp0 + kRG);
+  auto phi_pass = [&](const float2* Z) {
+    load_rows(va, par, 0, ntp, rstride, poff, nk);
+    for (int tp0 = 0; tp0 < ntp; tp0 += 2 * kRG) {
+      const bool more = tp0 + kRG < ntp;
+      if (more) load_rows(vb, par, tp0 + kRG, ntp, rstride, poff, nk);
+      phiT_rows(Z, va, tp0);
+      if (more) {
+        if (tp0 + 2 * kRG < ntp) load_rows(va, par, tp0 + 2 * kRG, ntp, rstride, poff, nk);
+        phiT_rows(Z, vb, tp0 + kRG);
+      }
     }
-  }
+  };
+  if (sw.on && !zl)
+    phi_pass(zslot);
+  else
+    phi_pass(zl ? Z0 + (size_t)w * ntp * kz : Z0);
   wave_lds_sync();
   // transposed theta step
   f4 acc[NT][S];
@@ -946,10 +956,15 @@ static size_t interp_lds(const MfD& T, int ntc, int wpb) {
   const int nb = nt_block(T), S = 2 * T.S2, RS = 16 * S + 16, SH = S * 16 * nb;
   return (size_t)nb * T.ktmax * 68 * 4 + (size_t)wpb * (ntc * RS + 2 * SH) * 4;
 }
+// a sweep batch reads a chunk's phase values from global memory when the
+// chunk's table is at most this size (measured on the 122,880-unknown sphere:
+// faster than per-wave LDS copies at levels 4 and 5, slower at level 3)
+constexpr size_t kZgGlobalMax = 12 * 1024;
+static bool zg_global(const MfD& T, int ntp) { return (size_t)ntp * 4 * T.kmax * 8 <= kZgGlobalMax; }
 static size_t anterp_lds(const MfD& T, int ntp, int wpb, bool sweep) {
   const int S = 2 * T.S2, RS = 16 * S + 16;
-  return (size_t)nt_block(T) * T.ktmax * 68 * 4 + (size_t)(sweep ? wpb : 1) * ntp * 4 * T.kmax * 8 +
-         (size_t)wpb * ntp * RS * 4;
+  const int nz = sweep ? (zg_global(T, ntp) ? 0 : wpb) : 1;
+  return (size_t)nt_block(T) * T.ktmax * 68 * 4 + (size_t)nz * ntp * 4 * T.kmax * 8 + (size_t)wpb * ntp * RS * 4;
 }
 // waves per block: four (one column tile each), fewer where the rows of four
 // waves do not fit in LDS (large angular grids at coarse levels); 0: none fits
@@ -1012,12 +1027,14 @@ static void launch_anterp_rg(const LevelD<float>& Lp, const LevelD<float>& Lc, c
   const int ntiles = nc / 4;
   const int wpb = anterp_wpb(T, Lp.nt, sw.on);
   const size_t sh = anterp_lds(T, Lp.nt, wpb, sw.on);
+  SweepSlots sv = sw;
+  sv.zg_global = sw.on && zg_global(T, Lp.nt);
   lds_limit((const void*)k_anterp_mf<NT, S2, MK, RG, W>, sh);
   hipLaunchKernelGGL((k_anterp_mf<NT, S2, MK, RG, W>), dim3(nb, (ntiles + wpb - 1) / wpb, nt_groups(T)), dim3(64 * wpb),
                      sh, s,
                      (const float*)Gp,
                      (float*)Gc, Lc.parent, Lc.octant, T, (const float2*)zg, Lc.nt, Lc.np, Lp.nt, Lp.np, Lc.nbox, nc,
-                     ldp, add, sw);
+                     ldp, add, sv);
 }
 
 template <int NT, int S2, int MK>
