@@ -84,7 +84,10 @@ def test_identities(torch_cuda, cfg1):
     zx = op.apply(x, "Z").cpu().numpy()
     xx = op.apply(x, "X").cpu().numpy()
     # X's far field uses the cos translator alone, R's the sin translator with
-    # its own near/far split, so R + iX equals Z to the truncation error only
+    # its own near/far split, so R + iX equals Z to the truncation error only:
+    # R x + i X x and Z x each lie within TOL64 of the exact product (X x shares
+    # Z's translator, R x has its own), so by the triangle inequality they
+    # differ by at most 2 TOL64
     rx = op.apply(x, "R").cpu().numpy()
     assert relerr(rx + 1j * xx, zx) < 2 * TOL64
     zhg = op.apply(g, "ZH").cpu().numpy()
