@@ -123,7 +123,9 @@ void build_sweep_tables(Dev& d, const Plan& P, const std::vector<const Plan*>& P
   for (int l = 2; l <= P.lf; ++l) {
     const Level& Lv = P.lev[l];
     LevelD<float>& D = d.f32.lev[l];
-    const size_t nT = (size_t)Lv.n_off_used * Lv.K;
+    const size_t nT = P.TZ[l].size();   // n_off_used x K (one row of zeros at a level without translations)
+    for (const Plan* q : Pk)
+      if (q->TZ[l].size() != nT) throw Error(CM_E_UNSUPPORTED, "sweep plans differ in their translator tables");
     std::vector<float> T(2 * nT * nk);
     for (int kk = 0; kk < nk; ++kk)
       for (size_t e = 0; e < nT; ++e) {
