@@ -552,10 +552,11 @@ __global__ void __launch_bounds__(256) k_disagg_mf(const float2* __restrict__ V,
       for (int nt = 0; nt < NTL; ++nt) {
         const float bs = sg * pair_swap(bq[nt]);
 #pragma unroll
-        for (int mt = 0; mt < MTU; ++mt) {
-          acc[mt][nt] = mma(a[mt].x, bq[nt], acc[mt][nt]);
-          acc[mt][nt] = mma(a[mt].y, bs, acc[mt][nt]);
-        }
+        for (int mt = 0; mt < MTU; ++mt)
+          if (16 * mt < i1 - i0) {   // unknown tiles past the box's last unknown are zero: skipped
+            acc[mt][nt] = mma(a[mt].x, bq[nt], acc[mt][nt]);
+            acc[mt][nt] = mma(a[mt].y, bs, acc[mt][nt]);
+          }
       }
     }
 #pragma unroll
