@@ -602,8 +602,13 @@ __global__ void __launch_bounds__(256) k_m2l_slots(const int32_t* __restrict__ t
                                                    int nk, SweepSlots sw, const float2* __restrict__ S,
                                                    float2* __restrict__ G, int nbox, int ntile, int K, int ldp,
                                                    int accum) {
+  // grid x = tiles x receiver groups, XCD-aware: the kTile / RT blocks of a
+  // tile are consecutive on one XCD, so the later ones find the tile's
+  // sources in that XCD's L2
+  constexpr int NRG = kTile / RT;
   const int per_xcd = gridDim.x / 8;
-  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int pos = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int tile = pos / NRG;
   if (tile >= ntile) return;
   const int ns = sw.n;
   const int qb = (int)blockDim.x / ns;
@@ -611,7 +616,7 @@ __global__ void __launch_bounds__(256) k_m2l_slots(const int32_t* __restrict__ t
   const int q = (int)blockIdx.y * qb + ql;
   const bool act = ql < qb && q < K;
   const int qq = act ? q : 0;   // inactive lanes read direction 0 (always in range)
-  const int h = (int)blockIdx.z * RT;
+  const int h = (pos % NRG) * RT;
   const float2* Tq = T + (int64_t)qq * nk + sw.k[slot];
   const int64_t fstride = (int64_t)K * nk;
   const int64_t bstride = (int64_t)2 * K * ldp;
@@ -1830,7 +1835,7 @@ void dev_apply_sweep(Dev& d0, const Plan& P0, Dev* const* dk, const Plan* const*
     LevelD<float>& Lv = d0.f32.lev[l];
     constexpr int RT = 8, PD = 3;
     const int qb = 256 / sw.n;
-    const dim3 grid((Lv.ntile + 7) / 8 * 8, (Lv.K + qb - 1) / qb, kTile / RT);
+    const dim3 grid((Lv.ntile * (kTile / RT) + 7) / 8 * 8, (Lv.K + qb - 1) / qb);
     stage_begin(d0, ss, 4 + 10 * l);
     hipLaunchKernelGGL((k_m2l_slots<RT, PD>), grid, dim3(256), 0, ss, Lv.tile_ptr, Lv.tile_src, Lv.tile_off,
                        (const float2*)Lv.sw_T, d0.sw_nk, sw, (const float2*)d0.S[l], (float2*)d0.G[l], Lv.nbox,
