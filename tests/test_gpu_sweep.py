@@ -124,6 +124,29 @@ def test_sweep_shared_one_pass_matches_per_wavenumber(torch_cuda):
     assert sw.stats()["sweep_one_pass_calls"] == calls
 
 
+def test_sweep_shared_beyond_sixteen_slots_takes_the_per_wavenumber_route(torch_cuda):
+    """A one-pass batch holds at most 16 slots of four columns: 17 wavenumbers
+    with one column each take the per-wavenumber route (no one-pass apply),
+    whose columns equal single handles of the same discretisation (sampling
+    at the largest k, translators truncated at their own k) bit for bit."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = workloads.icosphere(3, 0.5)
+    ks = list(np.linspace(0.9, 1.1, 17) * K0)
+    kw = dict(nlv=3, max_cols=32, d0=5.0, interp_p=10)
+    sw = Operator(V, F, ks, sweep_shared=True, **kw)
+    X = torch.tensor(workloads.cn01_block(sw.N, 17, 60), dtype=torch.complex64, device="cuda")
+    kidx = np.arange(17, dtype=np.int32)
+    Y = sw.apply(X, k_index=kidx).cpu().numpy()
+    assert sw.stats()["sweep_one_pass_calls"] == 0
+    for i in (0, 8, 16):
+        one = Operator(V, F, ks[i], k_sampling=ks[-1], sweep_shared=True, **kw)
+        Xp = torch.zeros((X.shape[0], 8), dtype=X.dtype, device="cuda")
+        Xp[:, 0] = X[:, i]
+        ref = one.apply(Xp)[:, 0].cpu().numpy()
+        assert np.array_equal(Y[:, i], ref), i
+
+
 @pytest.fixture(scope="module")
 def band():
     """The band's wavenumbers and, per wavenumber, eight oracle rows of Z."""
