@@ -124,6 +124,36 @@ def test_sweep_shared_one_pass_matches_per_wavenumber(torch_cuda):
     assert sw.stats()["sweep_one_pass_calls"] == calls
 
 
+def test_sweep_shared_sixteen_slots(torch_cuda):
+    """The largest one-pass batch: 16 wavenumbers x 4 columns (16 slots, 64
+    columns, column j at wavenumber j mod 16); every column against a single
+    handle of the same discretisation, to three times the distance between
+    that handle's matrix-core and vector-ALU routes (as in the 3-wavenumber
+    test)."""
+    torch = torch_cuda
+    from paper_1412_1756_amd import Operator
+    V, F = workloads.icosphere(4, 1.0)
+    ks = list(np.linspace(0.9, 1.1, 16) * K0)
+    kw = dict(nlv=4, max_cols=64, **ACC32)
+    sw = Operator(V, F, ks, sweep_shared=True, **kw)
+    X = torch.tensor(workloads.cn01_block(sw.N, 64, 70), dtype=torch.complex64, device="cuda")
+    kidx = np.arange(64, dtype=np.int32) % 16
+    Y = sw.apply(X, k_index=kidx).cpu().numpy()
+    assert sw.stats()["sweep_one_pass_calls"] == 1
+    for i in (0, 7, 15):
+        same = dict(k_sampling=ks[-1], sweep_shared=True, **kw)
+        one, vec = Operator(V, F, ks[i], **same), Operator(V, F, ks[i], matrix_cores=False, **same)
+        cols = np.nonzero(kidx == i)[0]
+        Xp = torch.zeros((X.shape[0], 8), dtype=X.dtype, device="cuda")
+        Xp[:, :len(cols)] = X[:, cols]
+        ref = one.apply(Xp)[:, :len(cols)].cpu().numpy()
+        alt = vec.apply(Xp)[:, :len(cols)].cpu().numpy()
+        e = float(np.linalg.norm(Y[:, cols] - ref) / np.linalg.norm(ref))
+        scale = float(np.linalg.norm(alt - ref) / np.linalg.norm(ref))
+        print(f"16 slots, k = {ks[i] / K0:.4f} k0: {e:.1e} (matrix-core vs vector-ALU: {scale:.1e})", flush=True)
+        assert e < max(3 * scale, 1e-5)
+
+
 def test_sweep_shared_beyond_sixteen_slots_takes_the_per_wavenumber_route(torch_cuda):
     """A one-pass batch holds at most 16 slots of four columns: 17 wavenumbers
     with one column each take the per-wavenumber route (no one-pass apply),
