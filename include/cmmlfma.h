@@ -458,8 +458,11 @@ cm_status cm_jd(cm_handle* h, int32_t nev, double target, int32_t mmin, int32_t 
 cm_status cm_export_near(const cm_handle* h, int32_t which, int64_t* nnz, int64_t* row_ptr,
                          int32_t* col, double* val);
 
-/* JSON description of the plan (levels, boxes, L, K, list sizes, nnz) and the
-   algorithmic bytes / flops per apply stage, NUL-terminated into buf.
+/* JSON description of the plan of k[0] (levels with boxes, L, the translator
+   truncation L_translator, K and list sizes; nnz; k_sampling), the autotuner's
+   choices ("autotune") and, for a sweep with CM_FLAG_SWEEP_SHARED, the number
+   of wavenumbers in its one-pass tables ("sweep_tables") and of one-pass
+   applies so far ("sweep_one_pass_calls"), NUL-terminated into buf.
    Returns CM_E_BADARG if buf_len is too small (needed size in *needed). */
 cm_status cm_stats(const cm_handle* h, char* buf, int64_t buf_len, int64_t* needed);
 
